@@ -1,0 +1,334 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix (CPU only).
+
+Each test names what pins it: a printed table, a closed form, an invariant of the method, a
+library routine that computes the same textbook operation, or brute force on tiny inputs.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mlpf_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TINY = synth.Config(d_model=8, n_heads=2, d_ff=16, n_layers=2)
+
+
+# ---------------------------------------------------------------- GELU (exact erf form)
+
+def test_gelu_matches_normal_cdf_table():
+    """GELU(x) = x * Phi(x); Phi from a printed table (tests/golden/normal_cdf.txt)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "normal_cdf.txt")) if l[0] != "#"]
+    for x, phi in ((float(a), float(b)) for a, b in rows):
+        assert O.gelu(np.array([x]))[0] == pytest.approx(x * phi, abs=1e-15, rel=1e-14)
+
+
+def test_gelu_identities():
+    x = np.linspace(-6, 6, 241)
+    assert O.gelu(np.array([0.0]))[0] == 0.0
+    np.testing.assert_allclose(O.gelu(x) - O.gelu(-x), x, rtol=0, atol=1e-14)
+    # Not the tanh approximation: at x = 1 the two differ by 1.5e-4.
+    tanh_form = 0.5 * (1 + math.tanh(math.sqrt(2 / math.pi) * (1 + 0.044715)))
+    assert abs(O.gelu(np.array([1.0]))[0] - tanh_form) > 1e-4
+
+
+# ---------------------------------------------------------------- LayerNorm
+
+def test_layer_norm_invariants():
+    rng = np.random.default_rng(1)
+    z = rng.standard_normal((16, 64)) * 3 + 2
+    eps = 1e-5
+    y = O.layer_norm(z, np.ones(64), np.zeros(64), eps)
+    var = z.var(axis=1)
+    np.testing.assert_allclose(y.mean(axis=1), 0, atol=1e-14)
+    np.testing.assert_allclose(y.var(axis=1), var / (var + eps), rtol=1e-12)
+    beta = rng.standard_normal(64)
+    const = np.full((3, 64), 7.25)
+    np.testing.assert_array_equal(O.layer_norm(const, rng.standard_normal(64), beta, eps),
+                                  np.broadcast_to(beta, (3, 64)))
+
+
+def test_layer_norm_vs_torch():
+    rng = np.random.default_rng(2)
+    z, g, b = rng.standard_normal((9, 40)), rng.standard_normal(40), rng.standard_normal(40)
+    ref = torch.nn.functional.layer_norm(torch.tensor(z), (40,), torch.tensor(g), torch.tensor(b), 1e-5)
+    np.testing.assert_allclose(O.layer_norm(z, g, b, 1e-5), ref.numpy(), rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- attention (Eq. 4)
+
+def test_attention_rows_positive_sum_to_one():
+    rng = np.random.default_rng(3)
+    q, k = rng.standard_normal((50, 16)) * 4, rng.standard_normal((70, 16)) * 4
+    a = O.attention_matrix(q, k)
+    assert (a > 0).all()
+    np.testing.assert_allclose(a.sum(axis=1), 1.0, rtol=0, atol=1e-14)
+
+
+def test_attention_special_cases():
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal((12, 8))
+    # one key: A = [1] and O = V
+    np.testing.assert_allclose(O.sdpa(rng.standard_normal((5, 8)), rng.standard_normal((1, 8)), v[:1]),
+                               np.broadcast_to(v[:1], (5, 8)), atol=1e-15)
+    # zero queries, or identical keys: uniform weights, O = column mean of V
+    np.testing.assert_allclose(O.sdpa(np.zeros((4, 8)), rng.standard_normal((12, 8)), v),
+                               np.broadcast_to(v.mean(0), (4, 8)), atol=1e-14)
+    kk = np.broadcast_to(rng.standard_normal(8), (12, 8))
+    np.testing.assert_allclose(O.sdpa(rng.standard_normal((4, 8)), kk, v),
+                               np.broadcast_to(v.mean(0), (4, 8)), atol=1e-14)
+    # one dominant logit: O -> that V row
+    k = np.zeros((12, 8)); k[7, 0] = 1.0
+    q = np.zeros((1, 8)); q[0, 0] = 400.0
+    np.testing.assert_allclose(O.sdpa(q, k, v)[0], v[7], atol=1e-12)
+
+
+def _brute_sdpa(q, k, v):
+    """Pure-Python loops with math.fsum: the definition of Eq. 4 element by element."""
+    nq, nk, dk, dv = len(q), len(k), len(q[0]), len(v[0])
+    out = []
+    for i in range(nq):
+        s = [math.fsum(q[i][c] * k[j][c] for c in range(dk)) / math.sqrt(dk) for j in range(nk)]
+        m = max(s)
+        e = [math.exp(x - m) for x in s]
+        tot = math.fsum(e)
+        out.append([math.fsum(e[j] * v[j][c] for j in range(nk)) / tot for c in range(dv)])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_attention_brute_force(n):
+    rng = np.random.default_rng(10 + n)
+    q, k, v = (rng.standard_normal((n, 4)) * 2 for _ in range(3))
+    np.testing.assert_allclose(O.sdpa(q, k, v), _brute_sdpa(q.tolist(), k.tolist(), v.tolist()),
+                               rtol=0, atol=1e-13)
+
+
+def test_attention_vs_torch_sdpa_with_mask():
+    rng = np.random.default_rng(5)
+    q, k, v = (rng.standard_normal((1, 1, 33, 16)) for _ in range(3))
+    mask = torch.zeros(1, 1, 33, 33, dtype=torch.bool)
+    mask[..., :20] = True
+    ref = torch.nn.functional.scaled_dot_product_attention(
+        torch.tensor(q), torch.tensor(k), torch.tensor(v), attn_mask=mask)[0, 0, :, :].numpy()
+    got = O.sdpa(q[0, 0], k[0, 0, :20], v[0, 0, :20])
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- blocks vs library routines
+
+def _torch_block(cfg, p):
+    blk = torch.nn.TransformerEncoderLayer(
+        cfg.d_model, cfg.n_heads, cfg.d_ff, dropout=0.0, activation="gelu",
+        layer_norm_eps=cfg.ln_eps, batch_first=True, norm_first=True, dtype=torch.float64)
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
+    with torch.no_grad():
+        blk.self_attn.in_proj_weight.copy_(t(p["W_qkv"]).T)
+        blk.self_attn.in_proj_bias.copy_(t(p["b_qkv"]))
+        blk.self_attn.out_proj.weight.copy_(t(p["W_o"]).T)
+        blk.self_attn.out_proj.bias.copy_(t(p["b_o"]))
+        blk.linear1.weight.copy_(t(p["W_1"]).T)
+        blk.linear1.bias.copy_(t(p["b_1"]))
+        blk.linear2.weight.copy_(t(p["W_2"]).T)
+        blk.linear2.bias.copy_(t(p["b_2"]))
+        blk.norm1.weight.copy_(t(p["ln1.gamma"])); blk.norm1.bias.copy_(t(p["ln1.beta"]))
+        blk.norm2.weight.copy_(t(p["ln2.gamma"])); blk.norm2.bias.copy_(t(p["ln2.beta"]))
+    return blk.eval()
+
+
+@pytest.mark.parametrize("cfg", [synth.SMALL, synth.Config(d_model=64, n_heads=4, d_ff=128, n_layers=1)])
+def test_encoder_block_vs_torch_transformer_layer(cfg):
+    """torch.nn.TransformerEncoderLayer(norm_first=True, gelu) is the textbook pre-LN block."""
+    w = synth.make_weights(cfg, seed=7, sharpen=8.0)
+    p = {k[len("layers.0."):]: v for k, v in w.items() if k.startswith("layers.0.")}
+    rng = np.random.default_rng(6)
+    n_valid, n_pad = 37, 48
+    h = rng.standard_normal((n_pad, cfg.d_model))
+    blk = _torch_block(cfg, p)
+    mask = torch.zeros(1, n_pad, dtype=torch.bool)
+    mask[0, n_valid:] = True  # True = padding key
+    with torch.no_grad():
+        ref = blk(torch.tensor(h)[None], src_key_padding_mask=mask)[0].numpy()
+    got = O.encoder_block(h[:n_valid], O._as64(p), cfg.n_heads, cfg.ln_eps)
+    np.testing.assert_allclose(got, ref[:n_valid], rtol=0, atol=1e-11)
+
+
+def test_embed_and_heads_vs_torch_mlp():
+    cfg = synth.SMALL
+    w = synth.make_weights(cfg, seed=8)
+    x = synth.make_features(np.random.default_rng(9), 21)
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
+
+    def mlp(W1, b1, W2, b2):
+        m = torch.nn.Sequential(torch.nn.Linear(W1.shape[0], W1.shape[1]), torch.nn.GELU(),
+                                torch.nn.Linear(W2.shape[0], W2.shape[1])).double()
+        with torch.no_grad():
+            m[0].weight.copy_(t(W1).T); m[0].bias.copy_(t(b1))
+            m[2].weight.copy_(t(W2).T); m[2].bias.copy_(t(b2))
+        return m
+
+    e = mlp(w["embed.W1"], w["embed.b1"], w["embed.W2"], w["embed.b2"])
+    with torch.no_grad():
+        np.testing.assert_allclose(O.embed(x.astype(np.float64), w), e(t(x)).numpy(), atol=1e-13)
+        h = np.random.default_rng(1).standard_normal((21, cfg.d_model))
+        for name, _ in synth.HEADS:
+            p = f"heads.{name}."
+            m = mlp(w[p + "W1"], w[p + "b1"], w[p + "W2"], w[p + "b2"])
+            np.testing.assert_allclose(O.head(h, O._as64(w), name), m(t(h)).numpy(), atol=1e-13)
+
+
+# ---------------------------------------------------------------- whole forward
+
+def _brute_forward(x, w, cfg):
+    """The whole forward as scalar pure-Python loops with math.fsum (tiny sizes only)."""
+    erf = math.erf
+    g = lambda z: 0.5 * z * (1 + erf(z / math.sqrt(2)))
+    W = {k: np.asarray(v, np.float64).tolist() for k, v in w.items()}
+
+    def lin(rows, Wm, b, act=False):
+        out = []
+        for r in rows:
+            o = [math.fsum(r[i] * Wm[i][j] for i in range(len(r))) + b[j] for j in range(len(b))]
+            out.append([g(v) for v in o] if act else o)
+        return out
+
+    def ln(rows, gam, bet):
+        out = []
+        for r in rows:
+            mu = math.fsum(r) / len(r)
+            var = math.fsum((v - mu) ** 2 for v in r) / len(r)
+            out.append([(v - mu) / math.sqrt(var + cfg.ln_eps) * gam[j] + bet[j] for j, v in enumerate(r)])
+        return out
+
+    d, nh = cfg.d_model, cfg.n_heads
+    dh = d // nh
+    h = lin(lin(x.tolist(), W["embed.W1"], W["embed.b1"], True), W["embed.W2"], W["embed.b2"])
+    for layer in range(cfg.n_layers):
+        P = lambda s: W[f"layers.{layer}.{s}"]
+        y = ln(h, P("ln1.gamma"), P("ln1.beta"))
+        qkv = lin(y, P("W_qkv"), P("b_qkv"))
+        o = [[0.0] * d for _ in h]
+        for j in range(nh):
+            cols = range(j * dh, (j + 1) * dh)
+            q = [[r[c] for c in cols] for r in qkv]
+            k = [[r[d + c] for c in cols] for r in qkv]
+            v = [[r[2 * d + c] for c in cols] for r in qkv]
+            oj = _brute_sdpa(q, k, v)
+            for i in range(len(h)):
+                for c in range(dh):
+                    o[i][j * dh + c] = oj[i][c]
+        a = lin(o, P("W_o"), P("b_o"))
+        h = [[h[i][c] + a[i][c] for c in range(d)] for i in range(len(h))]
+        f = lin(lin(ln(h, P("ln2.gamma"), P("ln2.beta")), P("W_1"), P("b_1"), True), P("W_2"), P("b_2"))
+        h = [[h[i][c] + f[i][c] for c in range(d)] for i in range(len(h))]
+    outs = [lin(lin(h, W[f"heads.{n}.W1"], W[f"heads.{n}.b1"], True), W[f"heads.{n}.W2"], W[f"heads.{n}.b2"])
+            for n, _ in synth.HEADS]
+    logits = np.array(outs[0])
+    reg = np.concatenate([np.array(o) for o in outs[1:]], axis=1)
+    return logits, reg
+
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_forward_brute_force_tiny(n):
+    w = synth.make_weights(TINY, seed=11, sharpen=8.0)
+    x = synth.make_features(np.random.default_rng(n), n)
+    out = O.forward(x, w, TINY)
+    logits, reg = _brute_forward(x, w, TINY)
+    np.testing.assert_allclose(out["logits"], logits, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(out["reg"], reg, rtol=0, atol=1e-13)
+
+
+def test_forward_closed_form_zero_weights():
+    """All weight matrices zero: every row is the sum of the biases along the residual path and
+    each head returns its output bias (a closed form of the architecture)."""
+    cfg = synth.SMALL
+    w = synth.make_weights(cfg, seed=12)
+    for k in w:
+        if k.split(".")[-1].startswith("W"):
+            w[k] = np.zeros_like(w[k])
+    x = synth.make_features(np.random.default_rng(0), 10)
+    out = O.forward(x, w, cfg)
+    h = w["embed.b2"].astype(np.float64)
+    for layer in range(cfg.n_layers):
+        h = h + w[f"layers.{layer}.b_o"] + w[f"layers.{layer}.b_2"]
+    np.testing.assert_allclose(out["h_cls"], np.broadcast_to(h, (10, cfg.d_model)), atol=1e-15)
+    np.testing.assert_allclose(out["logits"], np.broadcast_to(w["heads.cls.b2"], (10, 6)), atol=0)
+    reg_b = np.concatenate([w[f"heads.{n}.b2"] for n, _ in synth.HEADS[1:]])
+    np.testing.assert_allclose(out["reg"], np.broadcast_to(reg_b, (10, 5)), atol=0)
+
+
+@pytest.mark.parametrize("cfg", [synth.SMALL, synth.Config(d_model=64, n_heads=4, d_ff=256, n_layers=2,
+                                                           topology="parallel2")])
+def test_forward_permutation_equivariance(cfg):
+    """The model sees a set (no position encoding): permuting the elements permutes the outputs."""
+    w = synth.make_weights(cfg, seed=13, sharpen=8.0)
+    x = synth.make_features(np.random.default_rng(1), 40)
+    perm = np.random.default_rng(2).permutation(40)
+    a, b = O.forward(x, w, cfg), O.forward(x[perm], w, cfg)
+    np.testing.assert_allclose(b["logits"], a["logits"][perm], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(b["reg"], a["reg"][perm], rtol=0, atol=1e-12)
+
+
+def test_parallel2_uses_separate_stacks():
+    """parallel2: the classification output depends only on the first half of the blocks and the
+    regression outputs only on the second half."""
+    cfg = synth.Config(d_model=64, n_heads=4, d_ff=256, n_layers=2, topology="parallel2")
+    w = synth.make_weights(cfg, seed=14)
+    x = synth.make_features(np.random.default_rng(3), 12)
+    a = O.forward(x, w, cfg)
+    w2 = dict(w); w2["layers.1.W_1"] = w["layers.1.W_1"] * 3
+    b = O.forward(x, w2, cfg)
+    np.testing.assert_array_equal(a["logits"], b["logits"])
+    assert np.abs(a["reg"] - b["reg"]).max() > 1e-6
+    w3 = dict(w); w3["layers.0.W_1"] = w["layers.0.W_1"] * 3
+    c = O.forward(x, w3, cfg)
+    np.testing.assert_array_equal(a["reg"], c["reg"])
+    assert np.abs(a["logits"] - c["logits"]).max() > 1e-6
+
+
+def test_forward_packed_matches_alone_and_pads_are_ignored():
+    cfg = synth.SMALL
+    w = synth.make_weights(cfg, seed=15)
+    evs = [synth.make_event(s, n) for s, n in ((1, 5), (2, 70), (3, 1))]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4)
+    out = O.forward_packed(pk, w, cfg)
+    for e, ev in enumerate(evs):
+        ref = O.forward(ev.x, w, cfg)
+        np.testing.assert_array_equal(out["logits"][pk.event_rows(e)], ref["logits"])
+
+
+def test_argmax_ties_lowest_index():
+    lg = np.array([[0.0, 1.0, 1.0, 0.5, 1.0, 0.0], [2.0, 2.0, 2.0, 2.0, 2.0, 2.0], [0, 0, 0, 0, 0, 3.0]])
+    np.testing.assert_array_equal(O.argmax_lowest(lg), [1, 0, 5])
+
+
+def test_decode_inverts_eq2():
+    rng = np.random.default_rng(16)
+    prim = np.exp(rng.standard_normal((50, 2)))
+    pt, e = np.exp(rng.standard_normal(50)) * 10, np.exp(rng.standard_normal(50)) * 20
+    enc = O.encode(pt, e, prim)
+    phi = rng.uniform(-np.pi, np.pi, 50)
+    reg = np.stack([enc[:, 0], rng.standard_normal(50), np.sin(phi), np.cos(phi), enc[:, 1]], axis=1)
+    dec = O.decode(reg, prim)
+    np.testing.assert_allclose(dec["pt"], pt, rtol=1e-12)
+    np.testing.assert_allclose(dec["e"], e, rtol=1e-12)
+    np.testing.assert_allclose(dec["phi"], phi, rtol=0, atol=1e-12)
+
+
+def test_parameter_count_matches_paper():
+    """The paper's model has about 5.1 M parameters (Sec. 5.3); the full configuration read here
+    (d 256, FFN 4d, 6 blocks, 5 two-layer heads) has 5,140,747."""
+    assert synth.param_count(synth.FULL) == 5_140_747
+    assert synth.param_count(synth.PAPER) == 5_140_747
+    assert synth.param_count(synth.SMALL) == 176_779
+
+
+def test_flop_formula_matches_shapes():
+    """Algorithmic FLOPs = 2 N (sum of all Linear weight sizes) + L * 4 N^2 d."""
+    for cfg in (synth.SMALL, synth.FULL):
+        wsize = sum(int(np.prod(s)) for name, s in synth.param_shapes(cfg) if len(s) == 2)
+        for n in (1, 256, 3000):
+            assert O.flops_per_event(n, cfg) == 2 * n * wsize + cfg.n_layers * 4 * n * n * cfg.d_model
