@@ -1,0 +1,209 @@
+"""Benchmark of the MLPF forward pass on one MI355X.
+
+A step is one mlpf_reconstruct_events call (embedding, all encoder blocks, heads) over one batch of
+64 synthetic events packed varlen (element counts log-normal, median 3000, 200..8192) in BF16,
+inputs already resident in HBM. Beside it, the plain FP32 path runs one full-size event per launch
+(the same log-normal counts, 500..8192, padded to a multiple of 64), and the FP64 oracle is timed on
+the host's cores on a bounded sample of the same events.
+
+Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "events/sec + p50/p99 ms/event, BF16 varlen vs FP32 plain, 1 MI355X"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+EVENTS_PER_BATCH = 64
+
+
+def attention_flops(n: np.ndarray, cfg) -> float:
+    """Algorithmic FLOPs of one attention launch (one layer): 4 d sum_e n_e^2."""
+    n = n.astype(np.float64)
+    return float(4.0 * cfg.d_model * (n * n).sum())
+
+
+def forward_flops(n: np.ndarray, cfg) -> float:
+    d, f, dff, L = cfg.d_model, cfg.n_features, cfg.d_ff, cfg.n_layers
+    n = n.astype(np.float64)
+    lin = 2 * n * (f * d + d * d + L * (4 * d * d + 2 * d * dff) + 5 * d * d + 11 * d)
+    return float((lin + L * 4 * d * n * n).sum())
+
+
+def make_batches(count: int, root_seed: int = 300):
+    evs = synth.event_set(root_seed, count * EVENTS_PER_BATCH, lo=200)
+    return [synth.pack(evs[i * EVENTS_PER_BATCH:(i + 1) * EVENTS_PER_BATCH]) for i in range(count)]
+
+
+def bench_varlen(args, cfg, w):
+    import torch
+    from paper_2601_17554_amd import binding as B
+
+    model = B.Model(cfg, w, args.precision)
+    batches = make_batches(args.batches)
+    dev = []
+    for pk in batches:
+        dev.append((torch.from_numpy(pk.x).cuda(), B.Batch.from_host(pk.row_start, pk.n_valid)))
+    cap_rows = max(pk.total_rows for pk in batches)
+    ws = model.workspace(cap_rows, EVENTS_PER_BATCH)
+    outs = [model.outputs(pk.total_rows) for pk in batches]
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        x, b = dev[i % len(dev)]
+        model.reconstruct(x, b, ws=ws, out=outs[i % len(dev)])
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    model.profiler_enable(True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        step(i)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = model.profiler_read()
+    model.profiler_enable(False)
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    n_timed = np.concatenate([batches[i % len(batches)].n_valid for i in range(args.steps)])
+    attn_ms, attn_launches = prof["attention"]
+    attn_flops = sum(attention_flops(batches[i % len(batches)].n_valid, cfg) * cfg.n_layers
+                     for i in range(args.steps))
+    return {
+        "wall_s": wall, "batch_ms": lat, "events": len(n_timed),
+        "flops": forward_flops(n_timed, cfg), "prof": prof,
+        "attn_ms": attn_ms, "attn_launches": attn_launches, "attn_flops": attn_flops,
+        "mean_n": float(n_timed.mean()),
+    }
+
+
+def bench_plain_fp32(args, cfg, w):
+    import torch
+    from paper_2601_17554_amd import binding as B
+
+    model = B.Model(cfg, w, "fp32")
+    evs = synth.event_set(200, args.fp32_events, lo=500)
+    pks = [synth.pack([e], pad_to=64) for e in evs]
+    dev = [(torch.from_numpy(p.x).cuda(), B.Batch.from_host(p.row_start, p.n_valid)) for p in pks]
+    ws = model.workspace(max(p.total_rows for p in pks), 1)
+    outs = [model.outputs(p.total_rows) for p in pks]
+    stream = torch.cuda.current_stream()
+    for i in range(min(3, len(dev))):
+        model.reconstruct(dev[i][0], dev[i][1], ws=ws, out=outs[i])
+    torch.cuda.synchronize()
+    model.profiler_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in dev]
+    t0 = time.perf_counter()
+    for i, (x, b) in enumerate(dev):
+        ev[i][0].record(stream)
+        model.reconstruct(x, b, ws=ws, out=outs[i])
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = model.profiler_read()
+    model.profiler_enable(False)
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    n = np.array([e.n for e in evs])
+    attn_flops = sum(attention_flops(np.array([k]), cfg) * cfg.n_layers for k in n)
+    return {"wall_s": wall, "lat_ms": lat, "n": n, "prof": prof, "attn_flops": attn_flops}
+
+
+def cpu_baseline(cfg, w, budget_s: float):
+    """The FP64 oracle on the first events of the varlen workload until the time budget is spent."""
+    from oracle import mlpf_oracle as O
+    evs = synth.event_set(300, 64, lo=200)
+    done, t0 = 0, time.perf_counter()
+    for e in evs:
+        O.forward(e.x, w, cfg)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", "0")) or 0)
+    cores = threads or len(os.sched_getaffinity(0))
+    return {"value": done / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {done} events of the varlen workload (seed 300), FP64 NumPy, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batches", type=int, default=4)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--fp32-events", type=int, default=40)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(events are independent: the multi-GPU form is data parallel over events)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+
+    cfg = synth.FULL
+    w = synth.make_weights(cfg, 1)
+    vr = bench_varlen(args, cfg, w)
+    pl = bench_plain_fp32(args, cfg, w)
+
+    ms_per_step = vr["wall_s"] * 1e3 / args.steps
+    value = vr["events"] / vr["wall_s"]
+    per_event = vr["batch_ms"] / EVENTS_PER_BATCH
+    attn_avg_ms = vr["attn_ms"] / max(vr["attn_launches"], 1)
+    attn_flops_per_launch = vr["attn_flops"] / max(vr["attn_launches"], 1)
+    achieved = attn_flops_per_launch / (attn_avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    pl_attn_ms, pl_attn_n = pl["prof"]["attention"]
+    pl_achieved = (pl["attn_flops"] / max(pl_attn_n, 1)) / (pl_attn_ms / max(pl_attn_n, 1) * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "events/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"varlen_{args.precision}_64_events_per_launch",
+                   "events_per_step": EVENTS_PER_BATCH, "element_count": "lognormal median 3000 sigma 0.5 in [200, 8192]",
+                   "mean_elements": round(vr["mean_n"], 1), "model": "d256 h8 ffn1024 L6 (5.14M params)"},
+        "p50_ms_per_batch": round(float(np.percentile(vr["batch_ms"], 50)), 3),
+        "p99_ms_per_batch": round(float(np.percentile(vr["batch_ms"], 99)), 3),
+        "p50_ms_per_event_amortised": round(float(np.percentile(per_event, 50)), 4),
+        "p99_ms_per_event_amortised": round(float(np.percentile(per_event, 99)), 4),
+        "forward_tflops": round(vr["flops"] / vr["wall_s"] / 1e12, 1),
+        "fp32_plain": {
+            "value": round(len(pl["n"]) / pl["wall_s"], 2), "unit": "events/s",
+            "p50_ms_per_event": round(float(np.percentile(pl["lat_ms"], 50)), 3),
+            "p99_ms_per_event": round(float(np.percentile(pl["lat_ms"], 99)), 3),
+            "events": int(len(pl["n"])), "median_elements": int(np.median(pl["n"])),
+            "attention_tflops": round(pl_achieved, 1),
+            "attention_frac_fp32_peak": round(pl_achieved / PEAK_TFLOPS["fp32"], 4),
+        },
+        "roofline": {"bound": "mfma", "kernel": "attention", "achieved": round(achieved, 1),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": None, "avg_launch_ms": round(attn_avg_ms, 4)},
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in vr["prof"].items()},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, w, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

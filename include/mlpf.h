@@ -1,0 +1,192 @@
+/*
+ * mlpf.h - C ABI of libmlpf, an MI355X (gfx950) implementation of the MLPF forward pass:
+ * the transformer that maps each collision event's set of PF elements (tracks and calorimeter
+ * clusters) to per-element particle outputs (arxiv 2601.17554, Sec. 5.3).
+ *
+ * Model (Sec. 5.3, with the readings stated below):
+ *   h0      = GELU(x W_e1 + b_e1) W_e2 + b_e2                         element embedding FFN
+ *   block   : h += MHA(LN1(h));  h += GELU(LN2(h) W_1 + b_1) W_2 + b_2   pre-LN transformer block
+ *   MHA     : per head, softmax(Q K^T / sqrt(d_head)) V over the event's own elements (Eq. 4)
+ *   heads   : out_k = GELU(h W_k1 + b_k1) W_k2 + b_k2 for k = cls(6), pT'(1), eta(1), phi(2), E'(1)
+ *   class   = argmax of the 6 logits (class 0 = no particle, lowest index wins exact ties)
+ *   decode  : pT = pT_prim exp(pT'), E = E_prim exp(E') (inverse of Eq. 2), phi = atan2(sin, cos)
+ * Readings where the paper is silent: exact-erf GELU after every hidden linear layer (none after
+ * output layers); LayerNorm eps from the config, biased variance; no final LayerNorm; one
+ * embedding network for all element types; Q/K/V/O biases; contiguous head split.
+ *
+ * Conventions for every call:
+ *   - All pointers to tensors are DEVICE pointers unless a parameter says "host". The caller owns
+ *     all memory; the library never allocates device memory, never synchronises, and never frees.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Work is enqueued on it
+ *     in order; errors of kernels that already ran surface at the caller's next synchronisation.
+ *   - Arguments are validated before anything is enqueued. On failure nothing is written and the
+ *     call returns a status; mlpf_last_error() gives a message (thread-local).
+ *   - Row-major layouts. Rows of all events are packed one after another ("varlen"); see
+ *     mlpf_batch_t. Padding rows (rows of an event beyond its valid count) are never attention
+ *     keys; their outputs are unspecified and must be ignored.
+ *   - Calls on distinct streams with distinct workspaces and outputs may run concurrently on one
+ *     model handle; the handle is immutable after creation.
+ */
+#ifndef MLPF_H
+#define MLPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLPF_N_CLASSES 6     /* classification logits per element */
+#define MLPF_N_REG 5         /* pT', eta, sin phi, cos phi, E' per element */
+#define MLPF_MAX_SEQLEN 8192 /* largest supported element count of one event */
+
+typedef enum {
+  MLPF_OK = 0,
+  MLPF_ERR_INVALID_ARG = 1, /* null pointer, inconsistent sizes, workspace too small, ... */
+  MLPF_ERR_UNSUPPORTED = 2, /* valid but not supported (e.g. max_seqlen > 8192, d_head not 16/32) */
+  MLPF_ERR_CAPACITY = 3,    /* a size exceeds a capacity fixed at creation */
+  MLPF_ERR_HIP = 4,         /* a HIP runtime call failed; the message holds the HIP error string */
+  MLPF_ERR_INTERNAL = 5
+} mlpf_status_t;
+
+/* Arithmetic of the matrix products. Softmax statistics, LayerNorm statistics, the residual
+ * stream h and all outputs are FP32 in every mode; nothing uses FP64 on the GPU. */
+typedef enum {
+  MLPF_FP32 = 0,        /* FP32 operands on FP32 MFMA */
+  MLPF_BF16 = 1,        /* BF16 operands, FP32 accumulation */
+  MLPF_BF16_FP8FFN = 2  /* as BF16, but both FFN products take FP8-E4M3 operands with
+                           per-tensor scales (weights: amax/448; activations: from act_scales) */
+} mlpf_precision_t;
+
+typedef enum {
+  MLPF_TOPO_SERIAL = 0,   /* one stack of n_layers blocks; every head reads its output */
+  MLPF_TOPO_PARALLEL2 = 1 /* the paper's form (Sec. 5.3): two stacks fed by the same embedding;
+                             blocks 0..L/2-1 feed the classification head, blocks L/2..L-1 the
+                             regression heads */
+} mlpf_topology_t;
+
+typedef struct {
+  int32_t n_features; /* F: features per element, 1..32 */
+  int32_t d_model;    /* d: multiple of 64, 64..1024 */
+  int32_t n_heads;    /* d / n_heads must be 16 or 32 */
+  int32_t d_ff;       /* FFN width: multiple of 64, 64..4096 */
+  int32_t n_layers;   /* >= 1; even for MLPF_TOPO_PARALLEL2 */
+  int32_t topology;   /* mlpf_topology_t */
+  float ln_eps;       /* LayerNorm epsilon (> 0) */
+} mlpf_config_t;
+
+typedef struct mlpf_model_s* mlpf_model_t;
+
+/* One launch processes n_events events packed row-wise. Event e owns rows
+ * row_start[e] .. row_start[e+1]-1; the first n_valid[e] of them are its elements, the rest are
+ * padding. Device arrays are read by the kernels; host sizes bound the launch. Out-of-range device
+ * values are clamped into [0, total_rows] and to max_seqlen, so bad offsets cannot make a kernel
+ * touch memory outside the caller's buffers (they give wrong, not unsafe, results). */
+typedef struct {
+  const int32_t* row_start; /* device, [n_events + 1], non-decreasing, last <= total_rows */
+  const int32_t* n_valid;   /* device, [n_events], or NULL: every row of an event is valid */
+  int32_t n_events;         /* >= 0 */
+  int32_t total_rows;       /* T: rows of x, h and the outputs (>= row_start[n_events]) */
+  int32_t max_seqlen;       /* upper bound of every event's valid count; 0..8192 */
+} mlpf_batch_t;
+
+/* Bytes of the device weight buffer for (cfg, precision). */
+size_t mlpf_weights_bytes(const mlpf_config_t* cfg, mlpf_precision_t precision);
+
+/* Number of FP32 values of the host master weight blob for cfg. The blob is the concatenation,
+ * in this order, of row-major arrays with Linear weights stored [in][out] (y = x W + b):
+ *   embed: W1[F][d], b1[d], W2[d][d], b2[d]
+ *   for each layer: ln1_gamma[d], ln1_beta[d], W_qkv[d][3d], b_qkv[3d], W_o[d][d], b_o[d],
+ *                   ln2_gamma[d], ln2_beta[d], W_1[d][d_ff], b_1[d_ff], W_2[d_ff][d], b_2[d]
+ *   heads cls, pt, eta, phi, e (widths 6, 1, 1, 2, 1): W1[d][d], b1[d], W2[d][w], b2[w]
+ * W_qkv columns are [Q | K | V], each split into contiguous head slices of d/n_heads. */
+size_t mlpf_weights_count(const mlpf_config_t* cfg);
+
+/* Creates a model handle. Packs `host_weights` (host, n_floats FP32 values, order above) into the
+ * caller's device buffer `dev_weights` (dev_bytes >= mlpf_weights_bytes) with a copy enqueued on
+ * `stream`; host_weights may be freed when the call returns. act_scales (host, or NULL) is needed
+ * only for MLPF_BF16_FP8FFN: 2 floats per layer, the per-tensor scales of the FFN1 input (the LN2
+ * output) and of the FFN2 input (the GELU output), each amax/448. The handle borrows dev_weights
+ * (which must outlive it) and holds a small host struct. */
+mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t precision,
+                                const float* host_weights, size_t n_floats,
+                                const float* act_scales, void* dev_weights, size_t dev_bytes,
+                                void* stream, mlpf_model_t* out);
+mlpf_status_t mlpf_model_destroy(mlpf_model_t model); /* does not touch dev_weights */
+
+/* Bytes of the workspace needed by any call below for a batch of at most total_rows rows and
+ * n_events events. A workspace may be reused by consecutive calls on one stream. */
+size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t n_events);
+
+/* Element embedding FFN (Sec. 5.3): h[T][d] (FP32) = GELU(x W_e1 + b_e1) W_e2 + b_e2 for every row,
+ * x[T][F] FP32. */
+mlpf_status_t mlpf_embed(mlpf_model_t model, const float* x, const mlpf_batch_t* batch, float* h,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* The transformer encoder (Sec. 5.3, Eq. 4), in place on h, FP32 [S][T][d]: S = 1 for
+ * MLPF_TOPO_SERIAL, 2 for MLPF_TOPO_PARALLEL2. On entry h[0] holds the embedding; on return h[s]
+ * holds stack s's output (h[1] is overwritten for PARALLEL2). */
+mlpf_status_t mlpf_encoder_forward(mlpf_model_t model, float* h, const mlpf_batch_t* batch,
+                                   void* ws, size_t ws_bytes, void* stream);
+
+/* Output heads and the inference rule (Sec. 5.3, Eq. 2): from h (FP32 [S][T][d], as left by
+ * mlpf_encoder_forward) writes logits[T][6], reg[T][5] (pT', eta, sin phi, cos phi, E'), and
+ * cls[T] = argmax of the logits (int32). If prim (FP32 [T][2]: primary pT, E) and decoded
+ * (FP32 [T][4]) are both non-NULL, decoded gets (pT, eta, phi, E). */
+mlpf_status_t mlpf_heads(mlpf_model_t model, const float* h, const mlpf_batch_t* batch,
+                         float* logits, float* reg, int32_t* cls, const float* prim,
+                         float* decoded, void* ws, size_t ws_bytes, void* stream);
+
+/* mlpf_embed + mlpf_encoder_forward + mlpf_heads with h inside the workspace: one event set in,
+ * per-element outputs out. Graph-capturable (no allocation, no synchronisation, no memset). */
+mlpf_status_t mlpf_reconstruct_events(mlpf_model_t model, const float* x,
+                                      const mlpf_batch_t* batch, float* logits, float* reg,
+                                      int32_t* cls, const float* prim, float* decoded, void* ws,
+                                      size_t ws_bytes, void* stream);
+
+/* Optional per-kernel timing for benchmarks. While enabled on a model, every launch of a kernel
+ * class (below) made through that model is bracketed by a pair of HIP events recorded on the launch
+ * stream (event objects are created on first use; do not enable it around graph capture).
+ * mlpf_profiler_enable(model, 1) also resets the counters; mlpf_profiler_read returns the summed
+ * event-to-event time and the launch count of one class since then, and needs every stream that
+ * was used to have been synchronised (else MLPF_ERR_HIP "not ready"). Not thread-safe against
+ * concurrent forward calls on the same model while enabled. */
+typedef enum {
+  MLPF_PROF_EMBED = 0,     /* both products of the embedding FFN */
+  MLPF_PROF_QKV = 1,       /* LN1 + Q/K/V projection */
+  MLPF_PROF_ATTENTION = 2, /* fused masked varlen attention */
+  MLPF_PROF_OUTPROJ = 3,   /* attention output projection + residual */
+  MLPF_PROF_FFN1 = 4,      /* LN2 + FFN1 + GELU */
+  MLPF_PROF_FFN2 = 5,      /* FFN2 + residual */
+  MLPF_PROF_HEADS = 6,     /* both head layers, argmax, decode */
+  MLPF_PROF_WORKLIST = 7,  /* batch sanitising and attention work list */
+  MLPF_PROF_CLASSES = 8
+} mlpf_prof_class_t;
+mlpf_status_t mlpf_profiler_enable(mlpf_model_t model, int enable);
+mlpf_status_t mlpf_profiler_read(mlpf_model_t model, int kernel_class, double* total_ms,
+                                 int64_t* launches);
+
+/* Launch-shape choices. Each product of the forward pass (mlpf_op_t) runs with one of a fixed set
+ * of tile shapes; by default a size-based rule picks it per call. mlpf_tune_set pins op to tile
+ * (0 <= tile < mlpf_tune_count(op)) or restores the rule (tile = -1); this is how the autotuner
+ * stores its choice. Tile shapes change speed only: every GEMM tile sums k in the same order, so
+ * GEMM results are bitwise identical across tiles; attention tiles change the order of the online
+ * softmax updates (results differ by rounding only). Not thread-safe against concurrent forward
+ * calls on the same model. */
+typedef enum {
+  MLPF_OP_EMBED1 = 0, MLPF_OP_EMBED2 = 1, MLPF_OP_QKV = 2, MLPF_OP_OUTPROJ = 3,
+  MLPF_OP_FFN1 = 4, MLPF_OP_FFN2 = 5, MLPF_OP_HEADS1 = 6, MLPF_OP_ATTENTION = 7,
+  MLPF_OP_COUNT = 8
+} mlpf_op_t;
+int32_t mlpf_tune_count(int32_t op);
+mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile);
+int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule */
+
+const char* mlpf_status_string(mlpf_status_t status);
+const char* mlpf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLPF_H */

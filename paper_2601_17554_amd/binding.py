@@ -1,0 +1,295 @@
+"""ctypes binding of libmlpf (include/mlpf.h). Argument marshalling only: every step of the forward
+pass runs in the library's HIP kernels; torch provides device memory and the stream.
+
+The raw entry points keep the C names (``mlpf_embed``, ``mlpf_encoder_forward``, ``mlpf_heads``,
+``mlpf_reconstruct_events``) and take torch tensors. ``Model`` owns the device weight buffer and
+a workspace and is what tests and the benchmark use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Mapping, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlpf.so")
+
+MLPF_FP32, MLPF_BF16, MLPF_BF16_FP8FFN = 0, 1, 2
+PRECISIONS = {"fp32": MLPF_FP32, "bf16": MLPF_BF16, "bf16_fp8ffn": MLPF_BF16_FP8FFN}
+TOPOLOGIES = {"serial": 0, "parallel2": 1}
+HEAD_WIDTHS = (("cls", 6), ("pt", 1), ("eta", 1), ("phi", 2), ("e", 1))
+MAX_SEQLEN = 8192
+
+
+class MlpfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n_features", ctypes.c_int32), ("d_model", ctypes.c_int32),
+                ("n_heads", ctypes.c_int32), ("d_ff", ctypes.c_int32),
+                ("n_layers", ctypes.c_int32), ("topology", ctypes.c_int32),
+                ("ln_eps", ctypes.c_float)]
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("row_start", ctypes.c_void_p), ("n_valid", ctypes.c_void_p),
+                ("n_events", ctypes.c_int32), ("total_rows", ctypes.c_int32),
+                ("max_seqlen", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libmlpf.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2601_17554_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, st = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int
+    cfgp, bp = ctypes.POINTER(_Config), ctypes.POINTER(_Batch)
+    sig = {
+        "mlpf_weights_bytes": (sz, [cfgp, st]),
+        "mlpf_weights_count": (sz, [cfgp]),
+        "mlpf_model_create": (st, [cfgp, st, vp, sz, vp, vp, sz, vp, ctypes.POINTER(vp)]),
+        "mlpf_model_destroy": (st, [vp]),
+        "mlpf_workspace_bytes": (sz, [vp, i32, i32]),
+        "mlpf_embed": (st, [vp, vp, bp, vp, vp, sz, vp]),
+        "mlpf_encoder_forward": (st, [vp, vp, bp, vp, sz, vp]),
+        "mlpf_heads": (st, [vp, vp, bp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "mlpf_reconstruct_events": (st, [vp, vp, bp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "mlpf_profiler_enable": (st, [vp, st]),
+        "mlpf_profiler_read": (st, [vp, st, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64)]),
+        "mlpf_tune_count": (i32, [i32]),
+        "mlpf_tune_set": (st, [vp, i32, i32]),
+        "mlpf_tune_get": (i32, [vp, i32]),
+        "mlpf_status_string": (ctypes.c_char_p, [st]),
+        "mlpf_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype, fn.argtypes = res, args
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> Sequence[str]:
+    return ("mlpf_weights_bytes", "mlpf_weights_count", "mlpf_model_create", "mlpf_model_destroy",
+            "mlpf_workspace_bytes", "mlpf_embed", "mlpf_encoder_forward", "mlpf_heads",
+            "mlpf_reconstruct_events", "mlpf_profiler_enable", "mlpf_profiler_read",
+            "mlpf_tune_count", "mlpf_tune_set", "mlpf_tune_get",
+            "mlpf_status_string", "mlpf_last_error")
+
+
+PROF_CLASSES = ("embed", "qkv", "attention", "outproj", "ffn1", "ffn2", "heads", "worklist")
+OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1", "attention")
+
+
+def _status_name(s: int) -> str:
+    try:
+        return load().mlpf_status_string(s).decode()
+    except Exception:  # pragma: no cover - only while formatting another error
+        return f"status {s}"
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise MlpfError(status, load().mlpf_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libmlpf must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def make_config(cfg) -> _Config:
+    """From any object with the config attributes (n_features, d_model, ...)."""
+    return _Config(cfg.n_features, cfg.d_model, cfg.n_heads, cfg.d_ff, cfg.n_layers,
+                   TOPOLOGIES[cfg.topology], cfg.ln_eps)
+
+
+def flatten_weights(weights: Mapping[str, np.ndarray], cfg) -> np.ndarray:
+    """The master FP32 blob in the library's documented order (include/mlpf.h)."""
+    names = ["embed.W1", "embed.b1", "embed.W2", "embed.b2"]
+    for layer in range(cfg.n_layers):
+        names += [f"layers.{layer}.{s}" for s in
+                  ("ln1.gamma", "ln1.beta", "W_qkv", "b_qkv", "W_o", "b_o",
+                   "ln2.gamma", "ln2.beta", "W_1", "b_1", "W_2", "b_2")]
+    for name, _ in HEAD_WIDTHS:
+        names += [f"heads.{name}.{s}" for s in ("W1", "b1", "W2", "b2")]
+    return np.concatenate([np.ascontiguousarray(weights[n], dtype=np.float32).ravel() for n in names])
+
+
+class Batch:
+    """Device-side batch description: rows of event e are row_start[e]..row_start[e+1]-1, the first
+    n_valid[e] of them valid."""
+
+    def __init__(self, row_start: torch.Tensor, n_valid: Optional[torch.Tensor], n_events: int,
+                 total_rows: int, max_seqlen: int):
+        self.row_start, self.n_valid = row_start, n_valid
+        self.n_events, self.total_rows, self.max_seqlen = n_events, total_rows, max_seqlen
+        self._c = _Batch(_ptr(row_start), _ptr(n_valid), n_events, total_rows, max_seqlen)
+
+    @classmethod
+    def from_host(cls, row_start: np.ndarray, n_valid: Optional[np.ndarray], device="cuda",
+                  max_seqlen: Optional[int] = None) -> "Batch":
+        rs = torch.as_tensor(np.asarray(row_start, dtype=np.int32)).to(device)
+        nv = None if n_valid is None else torch.as_tensor(np.asarray(n_valid, dtype=np.int32)).to(device)
+        n_events = len(row_start) - 1
+        total = int(row_start[-1]) if n_events >= 0 and len(row_start) else 0
+        if max_seqlen is None:
+            spans = np.diff(np.asarray(row_start)) if n_valid is None else np.asarray(n_valid)
+            max_seqlen = int(spans.max()) if len(spans) else 0
+        return cls(rs, nv, n_events, total, max_seqlen)
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+# ------------------------------------------------------------------ raw entry points (C names)
+
+def mlpf_embed(model: "Model", x, batch: Batch, h, ws, stream=None) -> None:
+    _check(load().mlpf_embed(model.handle, _ptr(x), batch.c, _ptr(h), _ptr(ws),
+                             ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mlpf_encoder_forward(model: "Model", h, batch: Batch, ws, stream=None) -> None:
+    _check(load().mlpf_encoder_forward(model.handle, _ptr(h), batch.c, _ptr(ws),
+                                       ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mlpf_heads(model: "Model", h, batch: Batch, logits, reg, cls, prim, decoded, ws,
+               stream=None) -> None:
+    _check(load().mlpf_heads(model.handle, _ptr(h), batch.c, _ptr(logits), _ptr(reg), _ptr(cls),
+                             _ptr(prim), _ptr(decoded), _ptr(ws), ws.numel() * ws.element_size(),
+                             _stream(stream)))
+
+
+def mlpf_reconstruct_events(model: "Model", x, batch: Batch, logits, reg, cls, prim, decoded, ws,
+                            stream=None) -> None:
+    _check(load().mlpf_reconstruct_events(model.handle, _ptr(x), batch.c, _ptr(logits), _ptr(reg),
+                                          _ptr(cls), _ptr(prim), _ptr(decoded), _ptr(ws),
+                                          ws.numel() * ws.element_size(), _stream(stream)))
+
+
+class Model:
+    """A libmlpf model handle with its device weight buffer (allocated by torch)."""
+
+    def __init__(self, cfg, weights: Mapping[str, np.ndarray], precision: str = "fp32",
+                 act_scales: Optional[np.ndarray] = None, device: str = "cuda"):
+        lib = load()
+        self.cfg, self.precision, self.device = cfg, precision, device
+        self._ccfg = make_config(cfg)
+        prec = PRECISIONS[precision]
+        blob = flatten_weights(weights, cfg)
+        if blob.size != lib.mlpf_weights_count(ctypes.byref(self._ccfg)):
+            raise ValueError("weight blob size does not match the configuration")
+        nbytes = lib.mlpf_weights_bytes(ctypes.byref(self._ccfg), prec)
+        if nbytes == 0:
+            raise MlpfError(2, f"unsupported configuration/precision {cfg} {precision}")
+        self.wbuf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        scales = None
+        if act_scales is not None:
+            self._scales = np.ascontiguousarray(act_scales, dtype=np.float32)
+            scales = self._scales.ctypes.data
+        handle = ctypes.c_void_p()
+        _check(lib.mlpf_model_create(ctypes.byref(self._ccfg), prec, blob.ctypes.data, blob.size,
+                                     scales, self.wbuf.data_ptr(), nbytes,
+                                     _stream(None), ctypes.byref(handle)))
+        self.handle = handle
+        self.stacks = 2 if cfg.topology == "parallel2" else 1
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.mlpf_model_destroy(h)
+            self.handle = None
+
+    def profiler_enable(self, on: bool = True) -> None:
+        _check(load().mlpf_profiler_enable(self.handle, 1 if on else 0))
+
+    def profiler_read(self) -> Dict[str, tuple]:
+        """{class: (total_ms, launches)}; the streams used must have been synchronised."""
+        out = {}
+        for i, name in enumerate(PROF_CLASSES):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            _check(load().mlpf_profiler_read(self.handle, i, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    def tune_set(self, op: str, tile: int) -> None:
+        _check(load().mlpf_tune_set(self.handle, OPS.index(op), tile))
+
+    def tune_get(self, op: str) -> int:
+        return int(load().mlpf_tune_get(self.handle, OPS.index(op)))
+
+    @staticmethod
+    def tune_count(op: str) -> int:
+        return int(load().mlpf_tune_count(OPS.index(op)))
+
+    def workspace_bytes(self, total_rows: int, n_events: int) -> int:
+        return int(load().mlpf_workspace_bytes(self.handle, total_rows, n_events))
+
+    def workspace(self, total_rows: int, n_events: int) -> torch.Tensor:
+        return torch.empty(max(self.workspace_bytes(total_rows, n_events), 1), dtype=torch.uint8,
+                           device=self.device)
+
+    def outputs(self, total_rows: int, decode: bool = False) -> Dict[str, torch.Tensor]:
+        t = total_rows
+        out = {"logits": torch.empty(t, 6, dtype=torch.float32, device=self.device),
+               "reg": torch.empty(t, 5, dtype=torch.float32, device=self.device),
+               "cls": torch.empty(t, dtype=torch.int32, device=self.device)}
+        if decode:
+            out["decoded"] = torch.empty(t, 4, dtype=torch.float32, device=self.device)
+        return out
+
+    def reconstruct(self, x: torch.Tensor, batch: Batch, prim: Optional[torch.Tensor] = None,
+                    ws: Optional[torch.Tensor] = None, out: Optional[Dict[str, torch.Tensor]] = None,
+                    stream=None) -> Dict[str, torch.Tensor]:
+        if ws is None:
+            ws = self.workspace(batch.total_rows, batch.n_events)
+        if out is None:
+            out = self.outputs(batch.total_rows, decode=prim is not None)
+        mlpf_reconstruct_events(self, x, batch, out["logits"], out["reg"], out["cls"], prim,
+                                out.get("decoded"), ws, stream)
+        return out
+
+    def embed(self, x, batch: Batch, ws=None) -> torch.Tensor:
+        if ws is None:
+            ws = self.workspace(batch.total_rows, batch.n_events)
+        h = torch.empty(self.stacks, batch.total_rows, self.cfg.d_model, dtype=torch.float32,
+                        device=self.device)
+        mlpf_embed(self, x, batch, h, ws)
+        return h
+
+    def encoder(self, h: torch.Tensor, batch: Batch, ws=None) -> torch.Tensor:
+        if ws is None:
+            ws = self.workspace(batch.total_rows, batch.n_events)
+        mlpf_encoder_forward(self, h, batch, ws)
+        return h
+
+    def heads(self, h: torch.Tensor, batch: Batch, prim=None, ws=None) -> Dict[str, torch.Tensor]:
+        if ws is None:
+            ws = self.workspace(batch.total_rows, batch.n_events)
+        out = self.outputs(batch.total_rows, decode=prim is not None)
+        mlpf_heads(self, h, batch, out["logits"], out["reg"], out["cls"], prim, out.get("decoded"), ws)
+        return out

@@ -1,0 +1,756 @@
+// libmlpf C ABI: argument validation, weight packing, workspace layout and the launch sequence
+// of the MLPF forward pass (declared and documented in include/mlpf.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mlpf.h"
+#include "kernels.h"
+
+using namespace mlpf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mlpf_status_t fail(mlpf_status_t st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+mlpf_status_t hip_fail(hipError_t e, const char* what) {
+  return fail(MLPF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                   \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+  const uint32_t rounding = ((u >> 16) & 1u) + 0x7fffu;
+  return (uint16_t)((u + rounding) >> 16);
+}
+
+// Padded reduction length of the embedding's first product (F <= 32 features, k-tiles <= 64).
+constexpr int kEmbedKp = 64;
+
+struct Layer {
+  size_t ln1g, ln1b, wqkv, bqkv, wo, bo, ln2g, ln2b, w1, b1, w2, b2;
+};
+
+// Byte offsets of every packed tensor inside the device weight buffer.
+struct WeightPlan {
+  size_t e_w1, e_b1, e_w2, e_b2;
+  std::vector<Layer> layers;
+  size_t h_w1, h_b1, h_w2, h_b2;
+  size_t total;
+};
+
+int elem_bytes(mlpf_precision_t p) { return p == MLPF_FP32 ? 4 : 2; }
+
+WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
+  const size_t d = c.d_model, ff = c.d_ff, eb = elem_bytes(prec);
+  WeightPlan w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  w.e_w1 = take(d * kEmbedKp * eb);
+  w.e_b1 = take(d * 4);
+  w.e_w2 = take(d * d * eb);
+  w.e_b2 = take(d * 4);
+  w.layers.resize(c.n_layers);
+  for (auto& L : w.layers) {
+    L.ln1g = take(d * 4);
+    L.ln1b = take(d * 4);
+    L.wqkv = take(3 * d * d * eb);
+    L.bqkv = take(3 * d * 4);
+    L.wo = take(d * d * eb);
+    L.bo = take(d * 4);
+    L.ln2g = take(d * 4);
+    L.ln2b = take(d * 4);
+    L.w1 = take(ff * d * eb);
+    L.b1 = take(ff * 4);
+    L.w2 = take(d * ff * eb);
+    L.b2 = take(d * 4);
+  }
+  w.h_w1 = take(5 * d * d * eb);
+  w.h_b1 = take(5 * d * 4);
+  w.h_w2 = take(d * 11 * 4);
+  w.h_b2 = take(11 * 4);
+  w.total = off;
+  return w;
+}
+
+size_t master_count(const mlpf_config_t& c) {
+  const size_t d = c.d_model, f = c.n_features, ff = c.d_ff;
+  size_t n = f * d + d + d * d + d;
+  n += (size_t)c.n_layers * (2 * d + 3 * d * d + 3 * d + d * d + d + 2 * d + d * ff + ff + ff * d + d);
+  n += 5 * (d * d + d) + d * 11 + 11;
+  return n;
+}
+
+mlpf_status_t check_config(const mlpf_config_t* c) {
+  if (!c) return fail(MLPF_ERR_INVALID_ARG, "config is NULL");
+  if (c->n_features < 1 || c->n_features > 32)
+    return fail(MLPF_ERR_UNSUPPORTED, "n_features=%d not in 1..32", c->n_features);
+  if (c->d_model < 64 || c->d_model > 1024 || c->d_model % 64)
+    return fail(MLPF_ERR_UNSUPPORTED, "d_model=%d must be a multiple of 64 in 64..1024", c->d_model);
+  if (c->n_heads < 1 || c->d_model % c->n_heads)
+    return fail(MLPF_ERR_INVALID_ARG, "n_heads=%d does not divide d_model", c->n_heads);
+  const int dh = c->d_model / c->n_heads;
+  if (dh != 16 && dh != 32) return fail(MLPF_ERR_UNSUPPORTED, "d_head=%d must be 16 or 32", dh);
+  if (c->n_heads > 255) return fail(MLPF_ERR_UNSUPPORTED, "n_heads > 255");
+  if (c->d_ff < 64 || c->d_ff > 4096 || c->d_ff % 64)
+    return fail(MLPF_ERR_UNSUPPORTED, "d_ff=%d must be a multiple of 64 in 64..4096", c->d_ff);
+  if (c->n_layers < 1 || c->n_layers > 64)
+    return fail(MLPF_ERR_UNSUPPORTED, "n_layers=%d not in 1..64", c->n_layers);
+  if (c->topology != MLPF_TOPO_SERIAL && c->topology != MLPF_TOPO_PARALLEL2)
+    return fail(MLPF_ERR_INVALID_ARG, "unknown topology %d", c->topology);
+  if (c->topology == MLPF_TOPO_PARALLEL2 && c->n_layers % 2)
+    return fail(MLPF_ERR_INVALID_ARG, "PARALLEL2 needs an even n_layers");
+  if (!(c->ln_eps > 0.f) || !std::isfinite(c->ln_eps))
+    return fail(MLPF_ERR_INVALID_ARG, "ln_eps must be positive");
+  return MLPF_OK;
+}
+
+}  // namespace
+
+struct mlpf_model_s {
+  mlpf_config_t cfg;
+  mlpf_precision_t prec;
+  Prec kprec;
+  int dh;
+  int stacks;
+  WeightPlan plan;
+  const char* base;  // device weight buffer
+  // Launch choices (tile ids, -1 = size-based rule), set by mlpf_tune_set.
+  int tune[MLPF_OP_COUNT];
+  // Optional per-kernel-class timing (mlpf_profiler_*). Event pairs are recorded on the launch
+  // stream around every launch of a class while enabled.
+  std::mutex prof_mu;
+  bool prof_on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[MLPF_PROF_CLASSES];
+  size_t prof_used[MLPF_PROF_CLASSES] = {};
+  const void* at(size_t off) const { return base + off; }
+  const float* atf(size_t off) const { return (const float*)(base + off); }
+};
+
+namespace {
+
+// Workspace layout for a batch of T rows and E events.
+struct WsPlan {
+  size_t ev_start, ev_n, counters, items, q, k, v, o, y, u, h, total;
+  int cap_items;
+};
+
+WsPlan plan_ws(const mlpf_model_s* m, int64_t T, int64_t E) {
+  const mlpf_config_t& c = m->cfg;
+  const size_t eb = elem_bytes(m->prec);
+  WsPlan w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  // Work items: at most n_heads * sum_e ceil(n_e / 32) <= n_heads * (ceil(T / 32) + E).
+  const int64_t cap = (int64_t)c.n_heads * ((T + 31) / 32 + E);
+  w.cap_items = (int)std::min<int64_t>(cap, 0x7fffffff);
+  w.ev_start = take(E * 4);
+  w.ev_n = take(E * 4);
+  w.counters = take(16);
+  w.items = take((size_t)w.cap_items * 8);
+  const size_t td = (size_t)T * c.d_model;
+  w.q = take(td * eb);
+  w.k = take(td * eb);
+  w.v = take(td * eb);
+  w.o = take(td * eb);
+  w.y = take(td * eb);
+  const size_t uw = std::max<size_t>((size_t)c.d_ff, 5 * (size_t)c.d_model);
+  w.u = take((size_t)T * uw * eb);
+  w.h = take((size_t)m->stacks * td * 4);
+  w.total = off;
+  return w;
+}
+
+int pick_gemm_tile(int M, int N) {
+  const double wg256 = 256.0;
+  if ((double)((M + 127) / 128) * ((N + 127) / 128) >= 2 * wg256) return 2;
+  if ((double)((M + 127) / 128) * ((N + 63) / 64) >= wg256) return 1;
+  return 0;
+}
+
+mlpf_status_t check_batch(const mlpf_model_s* m, const mlpf_batch_t* b) {
+  if (!b) return fail(MLPF_ERR_INVALID_ARG, "batch is NULL");
+  if (b->n_events < 0 || b->total_rows < 0)
+    return fail(MLPF_ERR_INVALID_ARG, "negative n_events or total_rows");
+  if (b->max_seqlen < 0) return fail(MLPF_ERR_INVALID_ARG, "negative max_seqlen");
+  if (b->max_seqlen > MLPF_MAX_SEQLEN)
+    return fail(MLPF_ERR_UNSUPPORTED, "max_seqlen=%d exceeds %d", b->max_seqlen, MLPF_MAX_SEQLEN);
+  if (b->n_events > 0 && !b->row_start) return fail(MLPF_ERR_INVALID_ARG, "row_start is NULL");
+  (void)m;
+  return MLPF_OK;
+}
+
+// Records a HIP event pair around the launches of one kernel class while profiling is enabled.
+struct ProfScope {
+  mlpf_model_s* m;
+  hipStream_t s;
+  hipEvent_t stop = nullptr;
+  ProfScope(mlpf_model_s* model, int cls, hipStream_t stream) : m(model), s(stream) {
+    if (!m->prof_on) return;
+    std::lock_guard<std::mutex> g(m->prof_mu);
+    auto& v = m->prof_events[cls];
+    size_t& used = m->prof_used[cls];
+    if (used == v.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+      v.push_back({a, b});
+    }
+    (void)hipEventRecord(v[used].first, s);
+    stop = v[used].second;
+    ++used;
+  }
+  ~ProfScope() {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
+struct Ctx {
+  mlpf_model_s* m;
+  const mlpf_batch_t* b;
+  WsPlan w;
+  char* ws;
+  hipStream_t s;
+  const int32_t* n_rows;  // device count of live rows, or NULL
+  void* p(size_t off) const { return ws + off; }
+};
+
+int attn_tile_of(const mlpf_model_s* m) {
+  return m->tune[MLPF_OP_ATTENTION] >= 0 ? m->tune[MLPF_OP_ATTENTION] : 0;
+}
+
+mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a) {
+  a.m_dev = cx.n_rows;
+  const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N);
+  HIP_TRY(launch_gemm(cx.m->kprec, al, ep, tile, a, cx.s), "gemm launch");
+  return MLPF_OK;
+}
+
+// y = LayerNorm(h) in the operand type (the A operand of the next product).
+mlpf_status_t run_layernorm(const Ctx& cx, const float* h, size_t g_off, size_t b_off) {
+  LayerNormArgs a;
+  a.x = h;
+  a.y = cx.p(cx.w.y);
+  a.rows = cx.b->total_rows;
+  a.d = cx.m->cfg.d_model;
+  a.m_dev = cx.n_rows;
+  a.gamma = cx.m->atf(g_off);
+  a.beta = cx.m->atf(b_off);
+  a.eps = cx.m->cfg.ln_eps;
+  HIP_TRY(launch_layernorm(cx.m->kprec, a, cx.s), "layernorm launch");
+  return MLPF_OK;
+}
+
+mlpf_status_t do_embed(const Ctx& cx, const float* x, float* h) {
+  const mlpf_model_s* m = cx.m;
+  ProfScope prof(cx.m, MLPF_PROF_EMBED, cx.s);
+  const int T = cx.b->total_rows, d = m->cfg.d_model;
+  if (T == 0) return MLPF_OK;
+  GemmArgs a;
+  a.a = x;
+  a.lda = m->cfg.n_features;
+  a.M = T;
+  a.N = d;
+  a.K = m->cfg.n_features;
+  a.Kp = kEmbedKp;
+  a.wt = m->at(m->plan.e_w1);
+  a.bias = m->atf(m->plan.e_b1);
+  a.out = cx.p(cx.w.u);
+  a.ldo = d;
+  mlpf_status_t st = run_gemm(cx, MLPF_OP_EMBED1, A_SCALAR, E_GELU, a);
+  if (st) return st;
+  GemmArgs b;
+  b.a = cx.p(cx.w.u);
+  b.lda = d;
+  b.M = T;
+  b.N = d;
+  b.K = d;
+  b.Kp = d;
+  b.wt = m->at(m->plan.e_w2);
+  b.bias = m->atf(m->plan.e_b2);
+  b.out = h;
+  b.ldo = d;
+  return run_gemm(cx, MLPF_OP_EMBED2, A_PLAIN, E_BIAS, b);
+}
+
+mlpf_status_t do_worklist(Ctx& cx) {
+  const mlpf_model_s* m = cx.m;
+  WorklistArgs a;
+  a.row_start = cx.b->row_start;
+  a.n_valid = cx.b->n_valid;
+  a.n_events = cx.b->n_events;
+  a.total_rows = cx.b->total_rows;
+  a.max_seqlen = cx.b->max_seqlen;
+  a.q_tile = 32 * attn_tile(attn_tile_of(m)).waves;
+  a.n_heads = m->cfg.n_heads;
+  a.cap_items = cx.w.cap_items;
+  a.ev_start = (int32_t*)cx.p(cx.w.ev_start);
+  a.ev_n = (int32_t*)cx.p(cx.w.ev_n);
+  a.items = (int32_t*)cx.p(cx.w.items);
+  int32_t* ctr = (int32_t*)cx.p(cx.w.counters);
+  a.n_items = ctr;
+  a.n_rows = ctr + 1;
+  {
+    ProfScope prof(cx.m, MLPF_PROF_WORKLIST, cx.s);
+    HIP_TRY(launch_worklist(a, cx.s), "worklist launch");
+  }
+  cx.n_rows = ctr + 1;
+  return MLPF_OK;
+}
+
+mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
+  const mlpf_model_s* m = cx.m;
+  const mlpf_config_t& c = m->cfg;
+  const Layer& L = m->plan.layers[layer];
+  const int T = cx.b->total_rows, d = c.d_model, dh = m->dh;
+  mlpf_status_t st;
+  // LN1 + QKV projection, head-major Q (scaled by log2(e)/sqrt(d_head)), K, V.
+  GemmArgs q;
+  q.a = cx.p(cx.w.y);
+  q.lda = d;
+  q.M = T;
+  q.N = 3 * d;
+  q.K = d;
+  q.Kp = d;
+  q.wt = m->at(L.wqkv);
+  q.bias = m->atf(L.bqkv);
+  q.q = cx.p(cx.w.q);
+  q.k = cx.p(cx.w.k);
+  q.v = cx.p(cx.w.v);
+  q.hstride = (int64_t)T * dh;
+  q.d = d;
+  q.dh = dh;
+  q.q_scale = (float)(1.4426950408889634 / std::sqrt((double)dh));
+  {
+    ProfScope prof(cx.m, MLPF_PROF_QKV, cx.s);
+    if ((st = run_layernorm(cx, h, L.ln1g, L.ln1b))) return st;
+    if ((st = run_gemm(cx, MLPF_OP_QKV, A_PLAIN, E_QKV, q))) return st;
+  }
+  // Attention.
+  AttnArgs at;
+  at.q = cx.p(cx.w.q);
+  at.k = cx.p(cx.w.k);
+  at.v = cx.p(cx.w.v);
+  at.o = cx.p(cx.w.o);
+  at.hstride = (int64_t)T * dh;
+  at.d = d;
+  at.dh = dh;
+  const int32_t* ctr = (const int32_t*)cx.p(cx.w.counters);
+  at.items = (const int32_t*)cx.p(cx.w.items);
+  at.n_items = ctr;
+  at.ev_start = (const int32_t*)cx.p(cx.w.ev_start);
+  at.ev_n = (const int32_t*)cx.p(cx.w.ev_n);
+  at.cap_items = cx.w.cap_items;
+  {
+    ProfScope prof(cx.m, MLPF_PROF_ATTENTION, cx.s);
+    HIP_TRY(launch_attention(m->kprec, attn_tile_of(m), at, cx.s), "attention launch");
+  }
+  // Output projection + residual.
+  GemmArgs o;
+  o.a = cx.p(cx.w.o);
+  o.lda = d;
+  o.M = T;
+  o.N = d;
+  o.K = d;
+  o.Kp = d;
+  o.wt = m->at(L.wo);
+  o.bias = m->atf(L.bo);
+  o.out = h;
+  o.ldo = d;
+  {
+    ProfScope prof(cx.m, MLPF_PROF_OUTPROJ, cx.s);
+    if ((st = run_gemm(cx, MLPF_OP_OUTPROJ, A_PLAIN, E_RESID, o))) return st;
+  }
+  // LN2 + FFN1 + GELU.
+  GemmArgs f1;
+  f1.a = cx.p(cx.w.y);
+  f1.lda = d;
+  f1.M = T;
+  f1.N = c.d_ff;
+  f1.K = d;
+  f1.Kp = d;
+  f1.wt = m->at(L.w1);
+  f1.bias = m->atf(L.b1);
+  f1.out = cx.p(cx.w.u);
+  f1.ldo = c.d_ff;
+  {
+    ProfScope prof(cx.m, MLPF_PROF_FFN1, cx.s);
+    if ((st = run_layernorm(cx, h, L.ln2g, L.ln2b))) return st;
+    if ((st = run_gemm(cx, MLPF_OP_FFN1, A_PLAIN, E_GELU, f1))) return st;
+  }
+  // FFN2 + residual.
+  GemmArgs f2;
+  f2.a = cx.p(cx.w.u);
+  f2.lda = c.d_ff;
+  f2.M = T;
+  f2.N = d;
+  f2.K = c.d_ff;
+  f2.Kp = c.d_ff;
+  f2.wt = m->at(L.w2);
+  f2.bias = m->atf(L.b2);
+  f2.out = h;
+  f2.ldo = d;
+  ProfScope prof(cx.m, MLPF_PROF_FFN2, cx.s);
+  return run_gemm(cx, MLPF_OP_FFN2, A_PLAIN, E_RESID, f2);
+}
+
+mlpf_status_t do_encoder(Ctx& cx, float* h) {
+  const mlpf_model_s* m = cx.m;
+  const int64_t td = (int64_t)cx.b->total_rows * m->cfg.d_model;
+  if (cx.b->total_rows == 0) return MLPF_OK;
+  mlpf_status_t st;
+  if ((st = do_worklist(cx))) return st;
+  if (m->stacks == 1) {
+    for (int l = 0; l < m->cfg.n_layers; ++l)
+      if ((st = do_layer(cx, l, h))) return st;
+  } else {
+    HIP_TRY(launch_copy_f32(h + td, h, td, cx.s), "copy launch");
+    const int half = m->cfg.n_layers / 2;
+    for (int l = 0; l < half; ++l)
+      if ((st = do_layer(cx, l, h))) return st;
+    for (int l = half; l < m->cfg.n_layers; ++l)
+      if ((st = do_layer(cx, l, h + td))) return st;
+  }
+  return MLPF_OK;
+}
+
+mlpf_status_t do_heads(const Ctx& cx, const float* h, float* logits, float* reg, int32_t* cls,
+                       const float* prim, float* decoded) {
+  const mlpf_model_s* m = cx.m;
+  const int T = cx.b->total_rows, d = m->cfg.d_model;
+  if (T == 0) return MLPF_OK;
+  const int64_t td = (int64_t)T * d;
+  const size_t eb = elem_bytes(m->prec);
+  mlpf_status_t st;
+  ProfScope prof(cx.m, MLPF_PROF_HEADS, cx.s);
+  // First layer of the five heads: [T][d] -> GELU -> [T][5d]. For PARALLEL2 the classification
+  // head reads stack 0 and the regression heads stack 1.
+  const int groups = m->stacks == 1 ? 1 : 2;
+  for (int g = 0; g < groups; ++g) {
+    const int c0 = (groups == 1) ? 0 : (g == 0 ? 0 : d);
+    const int nc = (groups == 1) ? 5 * d : (g == 0 ? d : 4 * d);
+    GemmArgs a;
+    a.a = h + (g == 0 ? 0 : td);
+    a.lda = d;
+    a.M = T;
+    a.N = nc;
+    a.K = d;
+    a.Kp = d;
+    a.wt = (const char*)m->at(m->plan.h_w1) + (size_t)c0 * d * eb;
+    a.bias = m->atf(m->plan.h_b1) + c0;
+    a.out = (char*)cx.p(cx.w.u) + (size_t)c0 * eb;
+    a.ldo = 5 * d;
+    if ((st = run_gemm(cx, MLPF_OP_HEADS1, A_F32, E_GELU, a))) return st;
+  }
+  Heads2Args p;
+  p.uh = cx.p(cx.w.u);
+  p.d = d;
+  p.rows = T;
+  p.m_dev = cx.n_rows;
+  p.w2 = m->atf(m->plan.h_w2);
+  p.b2 = m->atf(m->plan.h_b2);
+  p.logits = logits;
+  p.reg = reg;
+  p.cls = cls;
+  p.prim = prim;
+  p.decoded = decoded;
+  HIP_TRY(launch_heads2(m->kprec, p, cx.s), "heads launch");
+  return MLPF_OK;
+}
+
+mlpf_status_t make_ctx(mlpf_model_t m, const mlpf_batch_t* b, void* ws, size_t ws_bytes,
+                       void* stream, bool need_h, Ctx* cx) {
+  if (!m) return fail(MLPF_ERR_INVALID_ARG, "model is NULL");
+  mlpf_status_t st = check_batch(m, b);
+  if (st) return st;
+  cx->m = m;
+  cx->b = b;
+  cx->w = plan_ws(m, b->total_rows, b->n_events);
+  const size_t need = need_h ? cx->w.total : cx->w.h;
+  if (need > 0 && !ws) return fail(MLPF_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < need)
+    return fail(MLPF_ERR_INVALID_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  cx->ws = (char*)ws;
+  cx->s = (hipStream_t)stream;
+  cx->n_rows = nullptr;
+  return MLPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mlpf_weights_bytes(const mlpf_config_t* cfg, mlpf_precision_t precision) {
+  if (check_config(cfg) != MLPF_OK) return 0;
+  if (precision != MLPF_FP32 && precision != MLPF_BF16) return 0;
+  return plan_weights(*cfg, precision).total;
+}
+
+size_t mlpf_weights_count(const mlpf_config_t* cfg) {
+  if (check_config(cfg) != MLPF_OK) return 0;
+  return master_count(*cfg);
+}
+
+mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t precision,
+                                const float* host_weights, size_t n_floats,
+                                const float* act_scales, void* dev_weights, size_t dev_bytes,
+                                void* stream, mlpf_model_t* out) {
+  (void)act_scales;
+  if (!out) return fail(MLPF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  mlpf_status_t st = check_config(cfg);
+  if (st) return st;
+  if (precision == MLPF_BF16_FP8FFN)
+    return fail(MLPF_ERR_UNSUPPORTED, "precision MLPF_BF16_FP8FFN is not available in this build");
+  if (precision != MLPF_FP32 && precision != MLPF_BF16)
+    return fail(MLPF_ERR_INVALID_ARG, "unknown precision %d", (int)precision);
+  if (!host_weights) return fail(MLPF_ERR_INVALID_ARG, "host_weights is NULL");
+  if (n_floats != master_count(*cfg))
+    return fail(MLPF_ERR_INVALID_ARG, "n_floats=%zu, expected %zu", n_floats, master_count(*cfg));
+  const WeightPlan plan = plan_weights(*cfg, precision);
+  if (!dev_weights) return fail(MLPF_ERR_INVALID_ARG, "dev_weights is NULL");
+  if (dev_bytes < plan.total)
+    return fail(MLPF_ERR_INVALID_ARG, "dev_bytes=%zu < %zu", dev_bytes, plan.total);
+
+  // Pack on the host: Linear weights transposed to [out][in] in the operand type.
+  const mlpf_config_t& c = *cfg;
+  const int d = c.d_model, f = c.n_features, ff = c.d_ff;
+  std::vector<unsigned char> img(plan.total, 0);
+  const float* src = host_weights;
+  auto put_f32 = [&](size_t off, int n) {
+    memcpy(img.data() + off, src, (size_t)n * 4);
+    src += n;
+  };
+  // W is [in][out] in the blob; writes W^T [out][kp] (kp >= in, zero padded).
+  auto put_wt = [&](size_t off, int in, int outn, int kp) {
+    for (int i = 0; i < in; ++i)
+      for (int o = 0; o < outn; ++o) {
+        const float v = src[(size_t)i * outn + o];
+        const size_t idx = (size_t)o * kp + i;
+        if (precision == MLPF_FP32)
+          memcpy(img.data() + off + idx * 4, &v, 4);
+        else {
+          const uint16_t b = f32_to_bf16_rne(v);
+          memcpy(img.data() + off + idx * 2, &b, 2);
+        }
+      }
+    src += (size_t)in * outn;
+  };
+  put_wt(plan.e_w1, f, d, kEmbedKp);
+  put_f32(plan.e_b1, d);
+  put_wt(plan.e_w2, d, d, d);
+  put_f32(plan.e_b2, d);
+  for (int l = 0; l < c.n_layers; ++l) {
+    const Layer& L = plan.layers[l];
+    put_f32(L.ln1g, d);
+    put_f32(L.ln1b, d);
+    put_wt(L.wqkv, d, 3 * d, d);
+    put_f32(L.bqkv, 3 * d);
+    put_wt(L.wo, d, d, d);
+    put_f32(L.bo, d);
+    put_f32(L.ln2g, d);
+    put_f32(L.ln2b, d);
+    put_wt(L.w1, d, ff, d);
+    put_f32(L.b1, ff);
+    put_wt(L.w2, ff, d, ff);
+    put_f32(L.b2, d);
+  }
+  // Heads: W1 of the five heads stacked as rows of W^T [5d][d]; W2 as [d][11].
+  static const int widths[5] = {6, 1, 1, 2, 1};
+  const size_t eb = elem_bytes(precision);
+  std::vector<float> w2(d * 11, 0.f), b2(11, 0.f);
+  int col = 0;
+  for (int k = 0; k < 5; ++k) {
+    put_wt(plan.h_w1 + (size_t)k * d * d * eb, d, d, d);
+    put_f32(plan.h_b1 + (size_t)k * d * 4, d);
+    for (int j = 0; j < d; ++j)
+      for (int o = 0; o < widths[k]; ++o) w2[(size_t)j * 11 + col + o] = src[(size_t)j * widths[k] + o];
+    src += (size_t)d * widths[k];
+    for (int o = 0; o < widths[k]; ++o) b2[col + o] = src[o];
+    src += widths[k];
+    col += widths[k];
+  }
+  memcpy(img.data() + plan.h_w2, w2.data(), w2.size() * 4);
+  memcpy(img.data() + plan.h_b2, b2.data(), b2.size() * 4);
+  if ((size_t)(src - host_weights) != n_floats)
+    return fail(MLPF_ERR_INTERNAL, "weight packing consumed %zu of %zu floats",
+                (size_t)(src - host_weights), n_floats);
+
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(dev_weights, img.data(), plan.total, hipMemcpyHostToDevice, s),
+          "weight upload");
+  HIP_TRY(hipStreamSynchronize(s), "weight upload sync");
+
+  mlpf_model_s* m = new (std::nothrow) mlpf_model_s();
+  if (!m) return fail(MLPF_ERR_INTERNAL, "out of host memory");
+  m->cfg = c;
+  m->prec = precision;
+  m->kprec = precision == MLPF_FP32 ? P_F32 : P_BF16;
+  m->dh = d / c.n_heads;
+  m->stacks = c.topology == MLPF_TOPO_PARALLEL2 ? 2 : 1;
+  m->plan = plan;
+  m->base = (const char*)dev_weights;
+  for (int& t : m->tune) t = -1;
+  *out = m;
+  return MLPF_OK;
+}
+
+mlpf_status_t mlpf_model_destroy(mlpf_model_t model) {
+  if (model)
+    for (auto& v : model->prof_events)
+      for (auto& pr : v) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+  delete model;
+  return MLPF_OK;
+}
+
+size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t n_events) {
+  if (!model || total_rows < 0 || n_events < 0) return 0;
+  return plan_ws(model, total_rows, n_events).total;
+}
+
+mlpf_status_t mlpf_embed(mlpf_model_t model, const float* x, const mlpf_batch_t* batch, float* h,
+                         void* ws, size_t ws_bytes, void* stream) {
+  Ctx cx;
+  mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, false, &cx);
+  if (st) return st;
+  if (batch->total_rows > 0 && (!x || !h)) return fail(MLPF_ERR_INVALID_ARG, "x or h is NULL");
+  return do_embed(cx, x, h);
+}
+
+mlpf_status_t mlpf_encoder_forward(mlpf_model_t model, float* h, const mlpf_batch_t* batch,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  Ctx cx;
+  mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, false, &cx);
+  if (st) return st;
+  if (batch->total_rows > 0 && !h) return fail(MLPF_ERR_INVALID_ARG, "h is NULL");
+  return do_encoder(cx, h);
+}
+
+mlpf_status_t mlpf_heads(mlpf_model_t model, const float* h, const mlpf_batch_t* batch,
+                         float* logits, float* reg, int32_t* cls, const float* prim,
+                         float* decoded, void* ws, size_t ws_bytes, void* stream) {
+  Ctx cx;
+  mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, false, &cx);
+  if (st) return st;
+  if (batch->total_rows > 0 && (!h || !logits || !reg || !cls))
+    return fail(MLPF_ERR_INVALID_ARG, "h, logits, reg or cls is NULL");
+  return do_heads(cx, h, logits, reg, cls, prim, decoded);
+}
+
+mlpf_status_t mlpf_reconstruct_events(mlpf_model_t model, const float* x,
+                                      const mlpf_batch_t* batch, float* logits, float* reg,
+                                      int32_t* cls, const float* prim, float* decoded, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  Ctx cx;
+  mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, true, &cx);
+  if (st) return st;
+  if (batch->total_rows == 0) return MLPF_OK;
+  if (!x || !logits || !reg || !cls) return fail(MLPF_ERR_INVALID_ARG, "x or an output is NULL");
+  float* h = (float*)cx.p(cx.w.h);
+  if ((st = do_embed(cx, x, h))) return st;
+  if ((st = do_encoder(cx, h))) return st;
+  return do_heads(cx, h, logits, reg, cls, prim, decoded);
+}
+
+int32_t mlpf_tune_count(int32_t op) {
+  if (op < 0 || op >= MLPF_OP_COUNT) return 0;
+  return op == MLPF_OP_ATTENTION ? attn_num_tiles() : gemm_num_tiles();
+}
+
+mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile) {
+  if (!model) return fail(MLPF_ERR_INVALID_ARG, "model is NULL");
+  if (op < 0 || op >= MLPF_OP_COUNT) return fail(MLPF_ERR_INVALID_ARG, "op=%d out of range", op);
+  if (tile < -1 || tile >= mlpf_tune_count(op))
+    return fail(MLPF_ERR_INVALID_ARG, "tile=%d out of range for op %d", tile, op);
+  model->tune[op] = tile;
+  return MLPF_OK;
+}
+
+int32_t mlpf_tune_get(mlpf_model_t model, int32_t op) {
+  if (!model || op < 0 || op >= MLPF_OP_COUNT) return -1;
+  return model->tune[op];
+}
+
+mlpf_status_t mlpf_profiler_enable(mlpf_model_t model, int enable) {
+  if (!model) return fail(MLPF_ERR_INVALID_ARG, "model is NULL");
+  std::lock_guard<std::mutex> g(model->prof_mu);
+  model->prof_on = enable != 0;
+  for (auto& u : model->prof_used) u = 0;
+  return MLPF_OK;
+}
+
+mlpf_status_t mlpf_profiler_read(mlpf_model_t model, int kernel_class, double* total_ms,
+                                 int64_t* launches) {
+  if (!model || !total_ms || !launches) return fail(MLPF_ERR_INVALID_ARG, "NULL argument");
+  if (kernel_class < 0 || kernel_class >= MLPF_PROF_CLASSES)
+    return fail(MLPF_ERR_INVALID_ARG, "kernel_class=%d out of range", kernel_class);
+  std::lock_guard<std::mutex> g(model->prof_mu);
+  double tot = 0.0;
+  const size_t used = model->prof_used[kernel_class];
+  for (size_t i = 0; i < used; ++i) {
+    float ms = 0.f;
+    const auto& pr = model->prof_events[kernel_class][i];
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "profiler event");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)used;
+  return MLPF_OK;
+}
+
+const char* mlpf_status_string(mlpf_status_t s) {
+  switch (s) {
+    case MLPF_OK: return "MLPF_OK";
+    case MLPF_ERR_INVALID_ARG: return "MLPF_ERR_INVALID_ARG";
+    case MLPF_ERR_UNSUPPORTED: return "MLPF_ERR_UNSUPPORTED";
+    case MLPF_ERR_CAPACITY: return "MLPF_ERR_CAPACITY";
+    case MLPF_ERR_HIP: return "MLPF_ERR_HIP";
+    case MLPF_ERR_INTERNAL: return "MLPF_ERR_INTERNAL";
+  }
+  return "unknown status";
+}
+
+const char* mlpf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Masked variable-length multi-head self-attention with online softmax (paper Eq. 4, computed
+// exactly as the FlashAttention kernel the paper uses does: tiled, never materialising A).
+//
+// One workgroup = one work item (event, head, block of 32*NW queries); each wave owns 32 queries.
+// Keys are the event's own valid elements only, so events never see each other and padding rows
+// are never keys. K and V tiles of KT keys are staged through LDS (double buffered) and shared by
+// the workgroup's waves; V is transposed while it is written to LDS.
+//
+// The scores are computed transposed, S^T = K Q^T, with 32x32 MFMAs: lane l then holds, for its
+// query l%32, the scores of 16 keys of each 32-key block (keys 8*(r/4) + 4*(l/32) + r%4 in register
+// r). The row maximum is one in-lane reduction plus one exchange with lane l^32, and the
+// probabilities P^T are already in the layout of the B operand of the second product,
+// O^T = V^T P^T, so P never leaves registers. Softmax statistics are FP32; scores are in log2
+// units because Q was pre-scaled by log2(e)/sqrt(d_head), so exp2 is used.
+#include "common.h"
+#include "kernels.h"
+
+namespace mlpf {
+
+template <class T, int DH, int NW, int KT>
+__global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
+  using S = typename T::storage;
+  constexpr int NT = NW * 64;
+  constexpr int SZ = T::kBytes;
+  constexpr int E = 16 / SZ;              // elements per 16-byte chunk
+  constexpr int KRS = DH * SZ + 16;       // LDS row stride of the K tile [KT][DH]
+  constexpr int VRS = KT * SZ + 16;       // LDS row stride of the V^T tile [DH][KT]
+  constexpr int K_BYTES = KT * KRS, V_BYTES = DH * VRS;
+  constexpr int CH_ROW = DH / E;          // chunks per K or V row
+  constexpr int NCH = KT * CH_ROW;        // chunks per tile
+  constexpr int PT = (NCH + NT - 1) / NT;
+  constexpr int NB = KT / 32;             // 32-key blocks per tile
+  constexpr int QKG = DH / (2 * E);       // k-groups of the QK^T product
+  static_assert(KT % 32 == 0 && DH % (2 * E) == 0 && DH <= 32, "bad attention shape");
+
+  __shared__ __attribute__((aligned(16))) char smem[2 * (K_BYTES + V_BYTES)];
+
+  if ((int)blockIdx.x >= min(*p.n_items, p.cap_items)) return;
+  const int ev = p.items[2 * blockIdx.x], code = p.items[2 * blockIdx.x + 1];
+  const int head = code & 255, qtile = code >> 8;
+  const int start = p.ev_start[ev], n = p.ev_n[ev];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, h = lane >> 5;
+  const int qi = qtile * (32 * NW) + wave * 32 + i;
+  const bool q_ok = qi < n;
+
+  const S* qb = (const S*)p.q + (int64_t)head * p.hstride + (int64_t)start * DH;
+  const S* kb = (const S*)p.k + (int64_t)head * p.hstride + (int64_t)start * DH;
+  const S* vb = (const S*)p.v + (int64_t)head * p.hstride + (int64_t)start * DH;
+
+  u32x4 qr[QKG];
+#pragma unroll
+  for (int c = 0; c < QKG; ++c)
+    qr[c] = q_ok ? *(const u32x4*)(qb + (int64_t)qi * DH + (2 * c + h) * E) : u32x4{0, 0, 0, 0};
+
+  u32x4 rk[PT], rv[PT];
+  auto load = [&](int kt0) {
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int c = t * NT + tid;
+      const int r = c / CH_ROW, ch = c % CH_ROW;
+      const bool ok = (NCH % NT == 0 || c < NCH) && kt0 + r < n;
+      const int64_t off = (int64_t)(kt0 + r) * DH + ch * E;
+      rk[t] = ok ? *(const u32x4*)(kb + off) : u32x4{0, 0, 0, 0};
+      rv[t] = ok ? *(const u32x4*)(vb + off) : u32x4{0, 0, 0, 0};
+    }
+  };
+  auto store = [&](int buf) {
+    char* Ks = smem + buf * (K_BYTES + V_BYTES);
+    char* Vs = Ks + K_BYTES;
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int c = t * NT + tid;
+      if (NCH % NT != 0 && c >= NCH) break;
+      const int r = c / CH_ROW, ch = c % CH_ROW;
+      *(u32x4*)(Ks + r * KRS + ch * 16) = rk[t];
+      if constexpr (SZ == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) *(uint32_t*)(Vs + (ch * 4 + e) * VRS + r * 4) = rv[t][e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          *(uint16_t*)(Vs + (ch * 8 + e) * VRS + r * 2) = (uint16_t)(rv[t][e >> 1] >> (16 * (e & 1)));
+      }
+    }
+  };
+
+  float m_run = -INFINITY, l_run = 0.f;
+  f32x16 oacc = f32x16{};
+  const int nkt = (n + KT - 1) / KT;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < nkt; ++t) {
+    const int kt0 = t * KT;
+    if (t + 1 < nkt) load(kt0 + KT);
+    const char* Ks = smem + (t & 1) * (K_BYTES + V_BYTES);
+    const char* Vs = Ks + K_BYTES;
+
+    // S^T = K Q^T for each 32-key block.
+    f32x16 s[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      s[b] = f32x16{};
+#pragma unroll
+      for (int c = 0; c < QKG; ++c) {
+        const u32x4 ka = *(const u32x4*)(Ks + (32 * b + i) * KRS + (2 * c + h) * 16);
+        mma_kg<T>(ka, qr[c], s[b]);
+      }
+    }
+    if (kt0 + KT > n) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (kt0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3) >= n) s[b][r] = -INFINITY;
+    }
+
+    // Online softmax (log2 domain). Both lane halves hold the same query.
+    float mx = -INFINITY;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[b][r]);
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    const float m_new = fmaxf(m_run, mx);  // finite: every tile holds a valid key
+    const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
+    m_run = m_new;
+    float ls = 0.f;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float e = __builtin_amdgcn_exp2f(s[b][r] - m_new);
+        s[b][r] = e;
+        ls += e;
+      }
+    l_run = l_run * alpha + ls;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) oacc[r] *= alpha;
+
+    // O^T += V^T P^T. Row dh = l%32 of V^T (zero for dh >= DH). In FP32 the tile's product goes
+    // to a fresh partial first (shorter sequential addition chains over long events).
+    f32x16 pv = f32x16{};
+    f32x16& dst = (SZ == 4) ? pv : oacc;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if constexpr (SZ == 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const u32x4 va = (i < DH) ? *(const u32x4*)(Vs + i * VRS + (32 * b + 8 * c + 4 * h) * 4)
+                                    : u32x4{0, 0, 0, 0};
+          const u32x4 pb = {__float_as_uint(s[b][4 * c + 0]), __float_as_uint(s[b][4 * c + 1]),
+                            __float_as_uint(s[b][4 * c + 2]), __float_as_uint(s[b][4 * c + 3])};
+          mma_kg<T>(va, pb, dst);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          u32x4 va = u32x4{0, 0, 0, 0};
+          if (i < DH) {
+            const u32x2 lo = *(const u32x2*)(Vs + i * VRS + (32 * b + 16 * c + 4 * h) * 2);
+            const u32x2 hi = *(const u32x2*)(Vs + i * VRS + (32 * b + 16 * c + 8 + 4 * h) * 2);
+            va = u32x4{lo[0], lo[1], hi[0], hi[1]};
+          }
+          const u32x2 p0 = pack_bf16x4(s[b][8 * c + 0], s[b][8 * c + 1], s[b][8 * c + 2], s[b][8 * c + 3]);
+          const u32x2 p1 = pack_bf16x4(s[b][8 * c + 4], s[b][8 * c + 5], s[b][8 * c + 6], s[b][8 * c + 7]);
+          mma_kg<T>(va, u32x4{p0[0], p0[1], p1[0], p1[1]}, dst);
+        }
+      }
+    }
+    if constexpr (SZ == 4) oacc += pv;
+    if (t + 1 < nkt) store((t + 1) & 1);
+    __syncthreads();
+  }
+
+  // O = O^T / l. Lane l holds dh = 8c + 4*(l/32) + (0..3) of query l%32 in registers 4c..4c+3.
+  const float l_tot = l_run + __shfl_xor(l_run, 32, 64);
+  if (q_ok) {
+    const float inv = 1.0f / l_tot;
+    S* orow = (S*)p.o + (int64_t)(start + qi) * p.d + head * DH;
+#pragma unroll
+    for (int c = 0; c < DH / 8; ++c) {
+      const float a0 = oacc[4 * c] * inv, a1 = oacc[4 * c + 1] * inv;
+      const float a2 = oacc[4 * c + 2] * inv, a3 = oacc[4 * c + 3] * inv;
+      if constexpr (SZ == 4) {
+        *(f32x4*)(orow + 8 * c + 4 * h) = f32x4{a0, a1, a2, a3};
+      } else {
+        *(u32x2*)(orow + 8 * c + 4 * h) = pack_bf16x4(a0, a1, a2, a3);
+      }
+    }
+  }
+}
+
+namespace {
+
+constexpr AttnTile kTiles[] = {
+    {4, 64},
+    {2, 64},
+    {4, 32},
+    {1, 64},
+};
+
+template <class T, int DH, int NW, int KT>
+hipError_t launch_t(const AttnArgs& p, hipStream_t s) {
+  if (p.cap_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL((attn_kernel<T, DH, NW, KT>), dim3(p.cap_items), dim3(NW * 64), 0, s, p);
+  return hipGetLastError();
+}
+
+template <class T, int DH>
+hipError_t launch_dh(int tile, const AttnArgs& p, hipStream_t s) {
+  switch (tile) {
+    case 0: return launch_t<T, DH, 4, 64>(p, s);
+    case 1: return launch_t<T, DH, 2, 64>(p, s);
+    case 2: return launch_t<T, DH, 4, 32>(p, s);
+    case 3: return launch_t<T, DH, 1, 64>(p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class T>
+hipError_t launch_prec(int tile, const AttnArgs& p, hipStream_t s) {
+  if (p.dh == 32) return launch_dh<T, 32>(tile, p, s);
+  if (p.dh == 16) return launch_dh<T, 16>(tile, p, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int attn_num_tiles() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
+AttnTile attn_tile(int id) { return kTiles[id]; }
+
+hipError_t launch_attention(Prec prec, int tile, const AttnArgs& p, hipStream_t s) {
+  if (prec == P_F32) return launch_prec<F32>(tile, p, s);
+  if (prec == P_BF16) return launch_prec<BF16>(tile, p, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mlpf

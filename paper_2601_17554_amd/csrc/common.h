@@ -1,0 +1,91 @@
+// Internal helpers shared by the libmlpf kernels (gfx950 / CDNA4 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlpf {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// Matrix-product operand types. Storage of a bf16 value is its 16 raw bits.
+struct F32 {
+  using storage = float;
+  static constexpr int kBytes = 4;
+};
+struct BF16 {
+  using storage = __bf16;
+  static constexpr int kBytes = 2;
+};
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float gelu_erf(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+
+// Rounds 4 floats to bf16 (round to nearest even) and packs them into 2 dwords.
+__device__ __forceinline__ u32x2 pack_bf16x4(float a, float b, float c, float d) {
+  bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+  return __builtin_bit_cast(u32x2, v);
+}
+
+// One 32x32 MFMA "k-group": each lane holds 16 bytes of A (row l%32) and 16 bytes of B
+// (column l%32); lane half h = l/32 holds the h-th half of the group's k-values. The k order
+// inside a group is the same for A and B, so any fixed permutation gives the same sum.
+//   F32 : 4 x v_mfma_f32_32x32x2_f32  (group = 8 k-values: half h holds k = 4h .. 4h+3)
+//   BF16: 1 x v_mfma_f32_32x32x16_bf16 (group = 16 k-values: half h holds k = 8h .. 8h+7)
+template <class T>
+__device__ __forceinline__ void mma_kg(const u32x4& a, const u32x4& b, f32x16& c);
+
+template <>
+__device__ __forceinline__ void mma_kg<F32>(const u32x4& a, const u32x4& b, f32x16& c) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[t]), __uint_as_float(b[t]), c, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ void mma_kg<BF16>(const u32x4& a, const u32x4& b, f32x16& c) {
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                              __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// Converts E = 16 / sizeof(T) floats to one 16-byte chunk of T.
+template <class T>
+__device__ __forceinline__ u32x4 to_chunk(const float* v);
+
+template <>
+__device__ __forceinline__ u32x4 to_chunk<F32>(const float* v) {
+  return u32x4{__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+               __float_as_uint(v[3])};
+}
+
+template <>
+__device__ __forceinline__ u32x4 to_chunk<BF16>(const float* v) {
+  u32x2 lo = pack_bf16x4(v[0], v[1], v[2], v[3]);
+  u32x2 hi = pack_bf16x4(v[4], v[5], v[6], v[7]);
+  return u32x4{lo[0], lo[1], hi[0], hi[1]};
+}
+
+// Workgroups of a launch are dealt round-robin to the 8 XCDs (each with its own L2). This maps
+// the hardware order to a logical order in which consecutive logical ids share an XCD, so tiles
+// that reuse the same operand rows sit behind the same L2. It is a bijection for any grid size.
+__device__ __forceinline__ int xcd_remap(int b, int g) {
+  const int q = g / 8, r = g % 8;
+  const int xcd = b % 8, local = b / 8;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+}  // namespace mlpf

@@ -1,0 +1,260 @@
+// Tiled MFMA GEMM with a fused conversion prologue and fused epilogues (bias, GELU,
+// residual update, head-major Q/K/V scatter). All dense products of the MLPF forward pass run
+// here: embedding FFN, Q/K/V projection, attention output projection, both FFN layers and the
+// first layer of the output heads (paper Sec. 5.3).
+//
+// C[M][N] = op_A(A)[M][K] * W[K][N], with W stored transposed (W^T [N][Kp], the operand type) so
+// that both operands are k-contiguous rows. A workgroup owns a BM x BN output tile; its waves
+// (WM x WN) each own a (BM/WM) x (BN/WN) sub-tile made of 32x32 MFMA blocks. k-tiles of BK
+// elements of A and W^T are staged through LDS (double buffered, one barrier per k-tile): the
+// next tile's global loads are issued before the current tile's MFMAs and written to LDS after
+// them. LDS rows are padded by 16 bytes so that the 32 rows read by one MFMA operand load fall
+// in different banks.
+#include "common.h"
+#include "kernels.h"
+
+namespace mlpf {
+
+template <class T, int ALD, int EPI, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
+  using S = typename T::storage;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int E = 16 / T::kBytes;        // operand elements per 16-byte chunk
+  constexpr int C = BK / E;                // chunks per row of a k-tile
+  constexpr int RS = BK * T::kBytes + 16;  // padded LDS row stride in bytes
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int FM = WTM / 32, FN = WTN / 32;
+  constexpr int A_CH = BM * C, B_CH = BN * C;
+  constexpr int A_PT = (A_CH + NT - 1) / NT, B_PT = (B_CH + NT - 1) / NT;
+  constexpr bool A_FROM_F32 = (ALD != A_PLAIN);
+  constexpr int A_BYTES = BM * RS, B_BYTES = BN * RS;
+  constexpr bool kSplit = (T::kBytes == 4);
+  static_assert(C % 2 == 0 && FM >= 1 && FN >= 1, "bad tile");
+
+  __shared__ __attribute__((aligned(16))) char smem[2 * (A_BYTES + B_BYTES)];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int ntn = (p.N + BN - 1) / BN;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tm = bid / ntn, tn = bid % ntn;
+  int M = p.M;
+  if (p.m_dev) M = min(M, max(*p.m_dev, 0));
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (m0 >= M) return;  // uniform over the workgroup
+
+  u32x4 ra[A_FROM_F32 ? 1 : A_PT];
+  float raf[A_FROM_F32 ? A_PT * E : 1];
+  u32x4 rb[B_PT];
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < A_PT; ++t) {
+      const int c = t * NT + tid;
+      const int row = c / C, ch = c % C;
+      const int grow = m0 + row, kb = k0 + ch * E;
+      const bool ok = (A_CH % NT == 0 || c < A_CH) && grow < M;
+      if constexpr (ALD == A_PLAIN) {
+        ra[t] = ok ? *(const u32x4*)((const S*)p.a + (int64_t)grow * p.lda + kb) : u32x4{0, 0, 0, 0};
+      } else if constexpr (ALD == A_SCALAR) {
+        const float* ar = (const float*)p.a + (int64_t)(ok ? grow : 0) * p.lda;
+#pragma unroll
+        for (int e = 0; e < E; ++e) raf[t * E + e] = (ok && kb + e < p.K) ? ar[kb + e] : 0.f;
+      } else {
+        const f32x4* ar = (const f32x4*)((const float*)p.a + (int64_t)(ok ? grow : 0) * p.lda + kb);
+#pragma unroll
+        for (int e = 0; e < E / 4; ++e) {
+          const f32x4 v = ok ? ar[e] : f32x4{0.f, 0.f, 0.f, 0.f};
+          raf[t * E + 4 * e + 0] = v[0];
+          raf[t * E + 4 * e + 1] = v[1];
+          raf[t * E + 4 * e + 2] = v[2];
+          raf[t * E + 4 * e + 3] = v[3];
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < B_PT; ++t) {
+      const int c = t * NT + tid;
+      const int n = c / C, ch = c % C;
+      const int col = n0 + n;
+      const bool ok = (B_CH % NT == 0 || c < B_CH) && col < p.N;
+      rb[t] = ok ? *(const u32x4*)((const S*)p.wt + (int64_t)col * p.Kp + k0 + ch * E)
+                 : u32x4{0, 0, 0, 0};
+    }
+  };
+
+  auto store = [&](int buf) {
+    char* As = smem + buf * (A_BYTES + B_BYTES);
+    char* Bs = As + A_BYTES;
+#pragma unroll
+    for (int t = 0; t < A_PT; ++t) {
+      const int c = t * NT + tid;
+      if (A_CH % NT != 0 && c >= A_CH) break;
+      const int row = c / C, ch = c % C;
+      u32x4 val;
+      if constexpr (ALD == A_PLAIN) {
+        val = ra[t];
+      } else {
+        val = to_chunk<T>(&raf[t * E]);
+      }
+      *(u32x4*)(As + row * RS + ch * 16) = val;
+    }
+#pragma unroll
+    for (int t = 0; t < B_PT; ++t) {
+      const int c = t * NT + tid;
+      if (B_CH % NT != 0 && c >= B_CH) break;
+      const int n = c / C, ch = c % C;
+      *(u32x4*)(Bs + n * RS + ch * 16) = rb[t];
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = f32x16{};
+
+  const int nk = p.Kp / BK;
+  const int i = lane & 31, h = lane >> 5;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+    const char* As = smem + buf * (A_BYTES + B_BYTES);
+    const char* Bs = As + A_BYTES;
+    // FP32 operands: each k-tile sums into a fresh partial that is then added to the total, so
+    // the longest chain of sequential FP32 additions is BK/2 + K/BK instead of K/2.
+    f32x16 part[kSplit ? FM : 1][kSplit ? FN : 1];
+    if constexpr (kSplit) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) part[a][b] = f32x16{};
+    }
+#pragma unroll
+    for (int g = 0; g < C / 2; ++g) {
+      u32x4 af[FM], bf[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+        af[a] = *(const u32x4*)(As + (wm * WTM + a * 32 + i) * RS + (2 * g + h) * 16);
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+        bf[b] = *(const u32x4*)(Bs + (wn * WTN + b * 32 + i) * RS + (2 * g + h) * 16);
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          if constexpr (kSplit)
+            mma_kg<T>(af[a], bf[b], part[a][b]);
+          else
+            mma_kg<T>(af[a], bf[b], acc[a][b]);
+        }
+    }
+    if constexpr (kSplit) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] += part[a][b];
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue. In a 32x32 accumulator block, lane l holds column l%32 of rows
+  // 8*(r/4) + 4*(l/32) + r%4 for r = 0..15.
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      const int col = n0 + wn * WTN + b * 32 + i;
+      if (col >= p.N) continue;
+      const float bias = p.bias ? p.bias[col] : 0.f;
+      [[maybe_unused]] S* qkv_base = nullptr;
+      [[maybe_unused]] float qkv_scale = 1.f;
+      if constexpr (EPI == E_QKV) {
+        const int which = col / p.d, rem = col % p.d;
+        const int hh = rem / p.dh, cc = rem % p.dh;
+        S* base = (S*)(which == 0 ? p.q : which == 1 ? p.k : p.v);
+        qkv_base = base + (int64_t)hh * p.hstride + cc;
+        qkv_scale = which == 0 ? p.q_scale : 1.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * WTM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (row >= M) continue;
+        const float v = acc[a][b][r] + bias;
+        if constexpr (EPI == E_BIAS) {
+          ((float*)p.out)[(int64_t)row * p.ldo + col] = v;
+        } else if constexpr (EPI == E_RESID) {
+          float* o = (float*)p.out + (int64_t)row * p.ldo + col;
+          *o = *o + v;
+        } else if constexpr (EPI == E_GELU) {
+          ((S*)p.out)[(int64_t)row * p.ldo + col] = (S)gelu_erf(v);
+        } else {
+          qkv_base[(int64_t)row * p.dh] = (S)(v * qkv_scale);
+        }
+      }
+    }
+  }
+}
+
+namespace {
+
+constexpr GemmTile kTiles[] = {
+    {64, 64, 2, 2},
+    {128, 64, 2, 2},
+    {128, 128, 2, 2},
+    {64, 128, 2, 2},
+};
+
+template <class T, int ALD, int EPI, int BM, int BN, int WM, int WN>
+hipError_t launch_t(const GemmArgs& p, hipStream_t s) {
+  constexpr int BK = (T::kBytes == 4) ? 32 : 64;
+  if (p.Kp % BK != 0) return hipErrorInvalidValue;
+  const int gm = (p.M + BM - 1) / BM, gn = (p.N + BN - 1) / BN;
+  const int64_t grid = (int64_t)gm * gn;
+  if (grid == 0) return hipSuccess;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_kernel<T, ALD, EPI, BM, BN, BK, WM, WN>), dim3((unsigned)grid),
+                     dim3(64 * WM * WN), 0, s, p);
+  return hipGetLastError();
+}
+
+template <class T, int ALD, int EPI>
+hipError_t launch_tile(int tile, const GemmArgs& p, hipStream_t s) {
+  switch (tile) {
+    case 0: return launch_t<T, ALD, EPI, 64, 64, 2, 2>(p, s);
+    case 1: return launch_t<T, ALD, EPI, 128, 64, 2, 2>(p, s);
+    case 2: return launch_t<T, ALD, EPI, 128, 128, 2, 2>(p, s);
+    case 3: return launch_t<T, ALD, EPI, 64, 128, 2, 2>(p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class T>
+hipError_t launch_prec(ALoad aload, Epi epi, int tile, const GemmArgs& p, hipStream_t s) {
+  // Only the combinations the forward pass uses are instantiated.
+  if (aload == A_SCALAR && epi == E_GELU) return launch_tile<T, A_SCALAR, E_GELU>(tile, p, s);
+  if (aload == A_PLAIN && epi == E_BIAS) return launch_tile<T, A_PLAIN, E_BIAS>(tile, p, s);
+  if (aload == A_PLAIN && epi == E_QKV) return launch_tile<T, A_PLAIN, E_QKV>(tile, p, s);
+  if (aload == A_PLAIN && epi == E_RESID) return launch_tile<T, A_PLAIN, E_RESID>(tile, p, s);
+  if (aload == A_PLAIN && epi == E_GELU) return launch_tile<T, A_PLAIN, E_GELU>(tile, p, s);
+  if (aload == A_F32 && epi == E_GELU) return launch_tile<T, A_F32, E_GELU>(tile, p, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int gemm_num_tiles() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
+GemmTile gemm_tile(int id) { return kTiles[id]; }
+
+hipError_t launch_gemm(Prec prec, ALoad aload, Epi epi, int tile, const GemmArgs& p,
+                       hipStream_t s) {
+  if (prec == P_F32) return launch_prec<F32>(aload, epi, tile, p, s);
+  if (prec == P_BF16) return launch_prec<BF16>(aload, epi, tile, p, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mlpf

@@ -1,0 +1,121 @@
+// Host-side launch interfaces of the libmlpf kernels (internal; the public ABI is mlpf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlpf {
+
+enum Prec { P_F32 = 0, P_BF16 = 1 };
+
+// How the GEMM's A operand is produced while it is staged into LDS.
+enum ALoad {
+  A_PLAIN = 0,   // A already holds the operand type (row stride lda, K % 16 bytes == 0)
+  A_F32 = 1,     // A is FP32, converted to the operand type
+  A_SCALAR = 2,  // A is FP32 with any K and row stride (element loads, zero beyond K)
+};
+
+// What the GEMM does with acc = A W (+ bias) for each output element.
+enum Epi {
+  E_BIAS = 0,   // out_f32[row][col] = acc + bias
+  E_RESID = 1,  // out_f32[row][col] += acc + bias           (residual update, in place)
+  E_GELU = 2,   // out_T[row][col] = GELU(acc + bias)
+  E_QKV = 3,    // Q (scaled), K, V written head-major [head][row][d_head] in the operand type
+};
+
+struct GemmArgs {
+  const void* a = nullptr;  // A [M][lda]
+  int lda = 0;
+  int M = 0, N = 0, K = 0;  // logical sizes; K is the reduction length
+  int Kp = 0;               // row length of wt (K rounded up to the k-tile)
+  const void* wt = nullptr; // W^T [N][Kp] in the operand type
+  const float* bias = nullptr;
+  const int32_t* m_dev = nullptr;  // optional device count of live rows (rows beyond it are skipped)
+  void* out = nullptr;
+  int ldo = 0;
+  // E_QKV
+  void* q = nullptr;
+  void* k = nullptr;
+  void* v = nullptr;
+  int64_t hstride = 0;  // elements between heads in q/k/v (= rows capacity * d_head)
+  int d = 0, dh = 0;
+  float q_scale = 1.f;
+};
+
+// Tile shapes available to the GEMM (index = tile id). Each entry: BM, BN, BK(bytes-agnostic
+// elements), waves along M, waves along N.
+struct GemmTile {
+  int bm, bn, wm, wn;
+};
+int gemm_num_tiles();
+GemmTile gemm_tile(int id);
+hipError_t launch_gemm(Prec prec, ALoad aload, Epi epi, int tile, const GemmArgs& args,
+                       hipStream_t stream);
+
+// Attention over a device work list (see worklist).
+struct AttnArgs {
+  const void* q = nullptr;  // [H][rows_cap][dh], pre-scaled by log2(e)/sqrt(dh)
+  const void* k = nullptr;
+  const void* v = nullptr;
+  void* o = nullptr;        // [rows][d]
+  int64_t hstride = 0;
+  int d = 0, dh = 0;
+  const int32_t* items = nullptr;    // [cap][2]: event, (q_tile << 8) | head
+  const int32_t* n_items = nullptr;  // device count
+  const int32_t* ev_start = nullptr;
+  const int32_t* ev_n = nullptr;
+  int cap_items = 0;
+};
+struct AttnTile {
+  int waves;  // queries per work item = 32 * waves
+  int kt;     // keys per LDS tile
+};
+int attn_num_tiles();
+AttnTile attn_tile(int id);
+hipError_t launch_attention(Prec prec, int tile, const AttnArgs& args, hipStream_t stream);
+
+// Sanitises the batch description and builds the attention work list (one workgroup).
+struct WorklistArgs {
+  const int32_t* row_start = nullptr;
+  const int32_t* n_valid = nullptr;
+  int n_events = 0, total_rows = 0, max_seqlen = 0;
+  int q_tile = 32, n_heads = 1, cap_items = 0;
+  int32_t* ev_start = nullptr;
+  int32_t* ev_n = nullptr;
+  int32_t* items = nullptr;
+  int32_t* n_items = nullptr;
+  int32_t* n_rows = nullptr;
+};
+hipError_t launch_worklist(const WorklistArgs& args, hipStream_t stream);
+
+// Second layer of the five output heads, argmax and optional decode.
+struct Heads2Args {
+  const void* uh = nullptr;   // [rows][5d] hidden activations (operand type)
+  int d = 0, rows = 0;
+  const int32_t* m_dev = nullptr;
+  const float* w2 = nullptr;  // [d][11]: columns cls0..5, pt, eta, sin, cos, e
+  const float* b2 = nullptr;  // [11]
+  float* logits = nullptr;
+  float* reg = nullptr;
+  int32_t* cls = nullptr;
+  const float* prim = nullptr;
+  float* decoded = nullptr;
+};
+hipError_t launch_heads2(Prec prec, const Heads2Args& args, hipStream_t stream);
+
+// LayerNorm of FP32 rows [rows][d] into y [rows][d] of the operand type.
+struct LayerNormArgs {
+  const float* x = nullptr;
+  void* y = nullptr;
+  int rows = 0, d = 0;
+  const int32_t* m_dev = nullptr;
+  const float* gamma = nullptr;
+  const float* beta = nullptr;
+  float eps = 1e-5f;
+};
+hipError_t launch_layernorm(Prec prec, const LayerNormArgs& args, hipStream_t stream);
+
+// Copies n floats (used to duplicate the embedding into the second stack of PARALLEL2).
+hipError_t launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t stream);
+
+}  // namespace mlpf

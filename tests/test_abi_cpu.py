@@ -1,0 +1,55 @@
+"""The C ABI library on the CPU: it loads, exports every entry point its header declares, and
+rejects bad configurations before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2601_17554_amd import binding as B
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libmlpf.so is not built (run __graft_entry__.build())")
+    return B, B.load()
+
+
+def test_exports_every_declared_symbol():
+    B, lib = _lib()
+    header = open(os.path.join(ROOT, "include", "mlpf.h")).read()
+    declared = set(re.findall(r"\b(mlpf_[a-z0-9_]+)\s*\(", header))
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(lib, name), f"{name} not exported"
+    assert declared == set(B.exported_symbols())
+
+
+def test_sizes_and_validation_without_gpu():
+    B, lib = _lib()
+    cfg = B.make_config(synth.FULL)
+    assert lib.mlpf_weights_count(ctypes.byref(cfg)) == synth.param_count(synth.FULL)
+    fp32 = lib.mlpf_weights_bytes(ctypes.byref(cfg), 0)
+    bf16 = lib.mlpf_weights_bytes(ctypes.byref(cfg), 1)
+    assert fp32 >= 4 * synth.param_count(synth.FULL) and bf16 < fp32
+    bad = B.make_config(synth.Config(d_model=96, n_heads=3))
+    assert lib.mlpf_weights_bytes(ctypes.byref(bad), 0) == 0
+    h = ctypes.c_void_p()
+    st = lib.mlpf_model_create(ctypes.byref(bad), 0, None, 0, None, None, 0, None, ctypes.byref(h))
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_UNSUPPORTED"
+    assert b"d_model" in lib.mlpf_last_error()
+    st = lib.mlpf_model_create(ctypes.byref(cfg), 0, None, 0, None, None, 0, None, None)
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG"
+    st = lib.mlpf_model_create(ctypes.byref(cfg), 0, None, 0, None, None, 0, None, ctypes.byref(h))
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG"  # host_weights NULL
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch):
+    from paper_2601_17554_amd import binding as B
+    monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libmlpf.so")
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        B.load()

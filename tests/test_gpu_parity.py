@@ -1,0 +1,205 @@
+"""GPU parity of libmlpf (called through its C ABI) against the FP64 oracle, element by element on
+the same seeded inputs, plus the method's invariants on the GPU (permutation equivariance,
+padding and batch independence, determinism)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlpf_oracle as O
+from parity_util import TOL, check_event, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+_ORACLE_CACHE = {}
+
+
+def oracle(x, w, cfg, key=None):
+    if key is not None and key in _ORACLE_CACHE:
+        return _ORACLE_CACHE[key]
+    out = O.forward(x, w, cfg)
+    if key is not None:
+        _ORACLE_CACHE[key] = out
+    return out
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2601_17554_amd import binding
+    binding.load()
+    return binding
+
+
+def _model(B, cfg, seed, prec, sharpen=1.0):
+    w = synth.make_weights(cfg, seed, sharpen=sharpen)
+    return w, B.Model(cfg, w, prec)
+
+
+def _check_all(got, pk, w, cfg, tol, tag, keys=None):
+    for e in range(pk.n_events):
+        rows = pk.event_rows(e)
+        if rows.stop == rows.start:
+            continue
+        key = None if keys is None else keys[e]
+        ref = oracle(pk.x[rows], w, cfg, key)
+        print(f"[{tag}] event {e} n={rows.stop - rows.start}", flush=True)
+        check_event(got, ref, rows, tol, f"{tag} event {e}")
+
+
+def test_fp32_small_single_event(B):
+    """256 elements, small model (d 64, 4 heads, 3 blocks), FP32."""
+    w, m = _model(B, synth.SMALL, 0, "fp32")
+    pk = synth.pack([synth.make_event(100, 256)])
+    _check_all(run_gpu(m, pk), pk, w, synth.SMALL, TOL["fp32"], "C1")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_small_tile_edges_padded_garbage(B, prec):
+    """Events whose sizes straddle the 32/64-row tiles, an empty event, padding rows holding
+    +-1e4 garbage; sharpened Q/K so the softmax is far from uniform."""
+    w, m = _model(B, synth.SMALL, 3, prec, sharpen=8.0)
+    sizes = [1, 2, 31, 32, 33, 0, 63, 64, 65, 127, 128, 129, 300]
+    evs = [synth.make_event(1000 + i, n) for i, n in enumerate(sizes)]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=5)
+    _check_all(run_gpu(m, pk), pk, w, synth.SMALL, TOL[prec], f"edges-{prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_full_varlen_ragged(B, prec):
+    """Full model, events packed without padding at unaligned row offsets."""
+    w, m = _model(B, synth.FULL, 2, prec, sharpen=4.0)
+    evs = [synth.make_event(2000 + i, n) for i, n in enumerate([70, 1, 517, 200, 33])]
+    pk = synth.pack(evs)
+    _check_all(run_gpu(m, pk), pk, w, synth.FULL, TOL[prec], f"varlen-{prec}",
+               keys=[("varlen", i) for i in range(len(evs))])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_full_event_from_workload(B, prec):
+    """Full-size model on the first events of the seeded single-event workload (log-normal N),
+    one event per launch padded to a multiple of 64."""
+    w = synth.make_weights(synth.FULL, 1)
+    m = B.Model(synth.FULL, w, prec)
+    evs = synth.event_set(200, 2, lo=500)
+    for i, ev in enumerate(evs):
+        pk = synth.pack([ev], pad_to=64)
+        got = run_gpu(m, pk)
+        ref = oracle(ev.x, w, synth.FULL, ("workload", i))
+        print(f"[full-{prec}] event {i} n={ev.n}", flush=True)
+        check_event(got, ref, pk.event_rows(0), TOL[prec], f"full-{prec} event {i}")
+
+
+def test_fp32_max_seqlen_8192(B):
+    """The largest event (8192 elements) through a one-block full-width model."""
+    cfg = synth.Config(d_model=256, n_heads=8, d_ff=1024, n_layers=1)
+    w, m = _model(B, cfg, 4, "fp32", sharpen=4.0)
+    ev = synth.make_event(77, 8192)
+    pk = synth.pack([ev])
+    got = run_gpu(m, pk)
+    check_event(got, O.forward(ev.x, w, cfg), pk.event_rows(0), TOL["fp32"], "8192")
+
+
+@pytest.mark.parametrize("cfg", [
+    synth.Config(d_model=64, n_heads=4, d_ff=256, n_layers=2, topology="parallel2"),
+    synth.Config(d_model=128, n_heads=8, d_ff=256, n_layers=2, topology="parallel2"),
+])
+def test_fp32_parallel2_topology(B, cfg):
+    """The paper's two-encoder layout; the second config has d_head 16."""
+    w, m = _model(B, cfg, 6, "fp32", sharpen=8.0)
+    evs = [synth.make_event(3000 + i, n) for i, n in enumerate([40, 129, 7])]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4)
+    _check_all(run_gpu(m, pk), pk, w, cfg, TOL["fp32"], "parallel2")
+
+
+def test_stages_separately_fp32(B):
+    """mlpf_embed, mlpf_encoder_forward and mlpf_heads each against the oracle's stage."""
+    import torch
+    cfg = synth.SMALL
+    w, m = _model(B, cfg, 8, "fp32", sharpen=8.0)
+    ev = synth.make_event(8, 150)
+    pk = synth.pack([ev], pad_to=64)
+    batch = B.Batch.from_host(pk.row_start, pk.n_valid)
+    x = torch.from_numpy(pk.x).cuda()
+    ws = m.workspace(pk.total_rows, 1)
+    h = m.embed(x, batch, ws)
+    ref_h0 = O.embed(ev.x.astype(np.float64), O._as64(w))
+    got_h0 = h[0, :150].cpu().numpy()
+    assert np.abs(got_h0 - ref_h0).max() <= 1e-5 * np.abs(ref_h0).max()
+    # encoder from the oracle's own embedding
+    h[0, :150] = torch.from_numpy(ref_h0.astype(np.float32)).cuda()
+    m.encoder(h, batch, ws)
+    ref = O.forward(ev.x, w, cfg)
+    got_h = h[0, :150].cpu().numpy()
+    assert np.abs(got_h - ref["h_cls"]).max() <= 1e-5 * np.abs(ref["h_cls"]).max()
+    # heads from the oracle's encoder output
+    h[0, :150] = torch.from_numpy(ref["h_cls"].astype(np.float32)).cuda()
+    prim = torch.from_numpy(pk.prim).cuda()
+    out = {k: v.cpu().numpy() for k, v in m.heads(h, batch, prim=prim, ws=ws).items()}
+    check_event(out, ref, slice(0, 150), TOL["fp32"], "heads")
+    dec = O.decode(ref["reg"], ev.prim)
+    np.testing.assert_allclose(out["decoded"][:150, 0], dec["pt"], rtol=1e-5)
+    np.testing.assert_allclose(out["decoded"][:150, 1], dec["eta"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(out["decoded"][:150, 2], dec["phi"], rtol=0, atol=1e-5)
+    np.testing.assert_allclose(out["decoded"][:150, 3], dec["e"], rtol=1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_permutation_equivariance(B, prec):
+    w, m = _model(B, synth.FULL, 9, prec, sharpen=4.0)
+    ev = synth.make_event(9, 333)
+    perm = np.random.default_rng(0).permutation(333)
+    a = run_gpu(m, synth.pack([ev]))
+    b = run_gpu(m, synth.pack([synth.Event(ev.x[perm], ev.prim[perm])]))
+    ref = {"logits": a["logits"][perm].astype(np.float64), "reg": a["reg"][perm].astype(np.float64)}
+    check_event(b, ref, slice(0, 333), TOL[prec], f"perm-{prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_padding_and_batch_invariance_bitwise(B, prec):
+    """An event's outputs do not depend on its padding rows' contents nor on the other events of
+    the launch (events share nothing); with this library they are bitwise identical."""
+    w, m = _model(B, synth.FULL, 10, prec)
+    evs = [synth.make_event(4000 + i, n) for i, n in enumerate([300, 65, 1000, 5])]
+    zero = run_gpu(m, synth.pack(evs, pad_to=64, pad_fill=0.0))
+    pk_g = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=3)
+    garbage = run_gpu(m, pk_g)
+    for e in range(len(evs)):
+        r = pk_g.event_rows(e)
+        np.testing.assert_array_equal(garbage["logits"][r], zero["logits"][r])
+        np.testing.assert_array_equal(garbage["reg"][r], zero["reg"][r])
+        alone = run_gpu(m, synth.pack([evs[e]]))
+        np.testing.assert_array_equal(alone["logits"][: evs[e].n], garbage["logits"][r])
+        np.testing.assert_array_equal(alone["reg"][: evs[e].n], garbage["reg"][r])
+
+
+def test_determinism_bitwise(B):
+    w, m = _model(B, synth.FULL, 11, "bf16")
+    pk = synth.pack(synth.event_set(300, 6, lo=200))
+    a, b = run_gpu(m, pk), run_gpu(m, pk)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_empty_inputs(B):
+    import torch
+    w, m = _model(B, synth.SMALL, 12, "fp32")
+    for rs in ([0], [0, 0, 0]):
+        batch = B.Batch.from_host(np.array(rs), None)
+        out = m.reconstruct(torch.zeros(0, 17, device="cuda"), batch)
+        torch.cuda.synchronize()
+        assert out["logits"].shape == (0, 6)
+
+
+def test_invalid_arguments_rejected(B):
+    import torch
+    w, m = _model(B, synth.SMALL, 13, "fp32")
+    pk = synth.pack([synth.make_event(1, 100)])
+    batch = B.Batch.from_host(pk.row_start, pk.n_valid)
+    x = torch.from_numpy(pk.x).cuda()
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.MlpfError, match="INVALID_ARG"):
+        m.reconstruct(x, batch, ws=small)
+    big = B.Batch(batch.row_start, batch.n_valid, 1, pk.total_rows, 9000)
+    with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
+        m.reconstruct(x, big)
