@@ -183,6 +183,16 @@ int32_t mlpf_tune_count(int32_t op);
 mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile);
 int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule */
 
+/* Masked variable-length multi-head self-attention alone (Eq. 4): for every event e and head j,
+ *   o[rows of e][j*d_head .. (j+1)*d_head-1] = softmax(q_j k_j^T / sqrt(d_head)) v_j
+ * where the keys are the event's valid rows only. q, k, v: [n_heads][total_rows][d_head]
+ * (head-major), o: [total_rows][d_model], all in the operand type of the model's precision (FP32
+ * for MLPF_FP32, BF16 otherwise); q is not pre-scaled. Rows beyond an event's valid count are not
+ * written. Uses the same kernel as mlpf_encoder_forward (which computes q, k, v itself). */
+mlpf_status_t mlpf_attention_forward(mlpf_model_t model, const void* q, const void* k,
+                                     const void* v, void* o, const mlpf_batch_t* batch, void* ws,
+                                     size_t ws_bytes, void* stream);
+
 const char* mlpf_status_string(mlpf_status_t status);
 const char* mlpf_last_error(void);
 

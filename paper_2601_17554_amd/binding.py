@@ -70,6 +70,7 @@ def load() -> ctypes.CDLL:
         "mlpf_profiler_enable": (st, [vp, st]),
         "mlpf_profiler_read": (st, [vp, st, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64)]),
+        "mlpf_attention_forward": (st, [vp, vp, vp, vp, vp, bp, vp, sz, vp]),
         "mlpf_tune_count": (i32, [i32]),
         "mlpf_tune_set": (st, [vp, i32, i32]),
         "mlpf_tune_get": (i32, [vp, i32]),
@@ -87,7 +88,7 @@ def exported_symbols() -> Sequence[str]:
     return ("mlpf_weights_bytes", "mlpf_weights_count", "mlpf_model_create", "mlpf_model_destroy",
             "mlpf_workspace_bytes", "mlpf_embed", "mlpf_encoder_forward", "mlpf_heads",
             "mlpf_reconstruct_events", "mlpf_profiler_enable", "mlpf_profiler_read",
-            "mlpf_tune_count", "mlpf_tune_set", "mlpf_tune_get",
+            "mlpf_attention_forward", "mlpf_tune_count", "mlpf_tune_set", "mlpf_tune_get",
             "mlpf_status_string", "mlpf_last_error")
 
 
@@ -191,6 +192,11 @@ def mlpf_reconstruct_events(model: "Model", x, batch: Batch, logits, reg, cls, p
                                           ws.numel() * ws.element_size(), _stream(stream)))
 
 
+def mlpf_attention_forward(model: "Model", q, k, v, o, batch: Batch, ws, stream=None) -> None:
+    _check(load().mlpf_attention_forward(model.handle, _ptr(q), _ptr(k), _ptr(v), _ptr(o), batch.c,
+                                         _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
 class Model:
     """A libmlpf model handle with its device weight buffer (allocated by torch)."""
 
@@ -272,6 +278,15 @@ class Model:
         mlpf_reconstruct_events(self, x, batch, out["logits"], out["reg"], out["cls"], prim,
                                 out.get("decoded"), ws, stream)
         return out
+
+    def attention(self, q, k, v, batch: Batch, ws=None) -> torch.Tensor:
+        """q, k, v: [n_heads][total_rows][d_head] tensors of the operand dtype (float32 or
+        bfloat16); returns o [total_rows][d_model] (rows beyond an event's count untouched: 0)."""
+        if ws is None:
+            ws = self.workspace(batch.total_rows, batch.n_events)
+        o = torch.zeros(batch.total_rows, self.cfg.d_model, dtype=q.dtype, device=self.device)
+        mlpf_attention_forward(self, q, k, v, o, batch, ws)
+        return o
 
     def embed(self, x, batch: Batch, ws=None) -> torch.Tensor:
         if ws is None:

@@ -336,6 +336,28 @@ mlpf_status_t do_worklist(Ctx& cx) {
   return MLPF_OK;
 }
 
+// Attention over the work list built by do_worklist; q is pre-scaled by log2(e)/sqrt(d_head).
+mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const void* v, void* o) {
+  const mlpf_model_s* m = cx.m;
+  AttnArgs at;
+  at.q = q;
+  at.k = k;
+  at.v = v;
+  at.o = o;
+  at.hstride = (int64_t)cx.b->total_rows * m->dh;
+  at.d = m->cfg.d_model;
+  at.dh = m->dh;
+  const int32_t* ctr = (const int32_t*)cx.p(cx.w.counters);
+  at.items = (const int32_t*)cx.p(cx.w.items);
+  at.n_items = ctr;
+  at.ev_start = (const int32_t*)cx.p(cx.w.ev_start);
+  at.ev_n = (const int32_t*)cx.p(cx.w.ev_n);
+  at.cap_items = cx.w.cap_items;
+  ProfScope prof(cx.m, MLPF_PROF_ATTENTION, cx.s);
+  HIP_TRY(launch_attention(m->kprec, attn_tile_of(m), at, cx.s), "attention launch");
+  return MLPF_OK;
+}
+
 mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
   const mlpf_model_s* m = cx.m;
   const mlpf_config_t& c = m->cfg;
@@ -365,24 +387,7 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
     if ((st = run_gemm(cx, MLPF_OP_QKV, A_PLAIN, E_QKV, q))) return st;
   }
   // Attention.
-  AttnArgs at;
-  at.q = cx.p(cx.w.q);
-  at.k = cx.p(cx.w.k);
-  at.v = cx.p(cx.w.v);
-  at.o = cx.p(cx.w.o);
-  at.hstride = (int64_t)T * dh;
-  at.d = d;
-  at.dh = dh;
-  const int32_t* ctr = (const int32_t*)cx.p(cx.w.counters);
-  at.items = (const int32_t*)cx.p(cx.w.items);
-  at.n_items = ctr;
-  at.ev_start = (const int32_t*)cx.p(cx.w.ev_start);
-  at.ev_n = (const int32_t*)cx.p(cx.w.ev_n);
-  at.cap_items = cx.w.cap_items;
-  {
-    ProfScope prof(cx.m, MLPF_PROF_ATTENTION, cx.s);
-    HIP_TRY(launch_attention(m->kprec, attn_tile_of(m), at, cx.s), "attention launch");
-  }
+  if ((st = run_attention(cx, cx.p(cx.w.q), cx.p(cx.w.k), cx.p(cx.w.v), cx.p(cx.w.o)))) return st;
   // Output projection + residual.
   GemmArgs o;
   o.a = cx.p(cx.w.o);
@@ -737,6 +742,21 @@ mlpf_status_t mlpf_profiler_read(mlpf_model_t model, int kernel_class, double* t
   *total_ms = tot;
   *launches = (int64_t)used;
   return MLPF_OK;
+}
+
+mlpf_status_t mlpf_attention_forward(mlpf_model_t model, const void* q, const void* k,
+                                     const void* v, void* o, const mlpf_batch_t* batch, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  Ctx cx;
+  mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, false, &cx);
+  if (st) return st;
+  if (batch->total_rows == 0) return MLPF_OK;
+  if (!q || !k || !v || !o) return fail(MLPF_ERR_INVALID_ARG, "q, k, v or o is NULL");
+  if ((st = do_worklist(cx))) return st;
+  const int64_t n = (int64_t)batch->total_rows * model->cfg.d_model;
+  const float scale = (float)(1.4426950408889634 / std::sqrt((double)model->dh));
+  HIP_TRY(launch_scale(model->kprec, cx.p(cx.w.q), q, n, scale, cx.s), "scale launch");
+  return run_attention(cx, cx.p(cx.w.q), k, v, o);
 }
 
 const char* mlpf_status_string(mlpf_status_t s) {

@@ -12,16 +12,40 @@
 // probabilities P^T are already in the layout of the B operand of the second product,
 // O^T = V^T P^T, so P never leaves registers. Softmax statistics are FP32; scores are in log2
 // units because Q was pre-scaled by log2(e)/sqrt(d_head), so exp2 is used.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace mlpf {
+
+// Exchange with lane l^32 (the other half holding the same query): v_permlane32_swap.
+__device__ __forceinline__ float other_half(float x) {
+  const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  // sw[0] holds x of lane l%32 in every lane, sw[1] x of lane l%32 + 32.
+  const float lo = __uint_as_float(sw[0]), hi = __uint_as_float(sw[1]);
+  return (threadIdx.x & 32) ? lo : hi;
+}
+
+// -x as three bf16 values packed for one lane half of a 32x32x16 MFMA operand: hi + mid + lo
+// represents any normal FP32 value exactly (3 x 8 significant bits), and the MFMA adds the three
+// products (each exact) in FP32.
+__device__ __forceinline__ u32x4 neg_split3(float x) {
+  const __bf16 hi = (__bf16)(-x);
+  const float r1 = -x - (float)hi;
+  const __bf16 mid = (__bf16)r1;
+  const __bf16 lo = (__bf16)(r1 - (float)mid);
+  const uint32_t a = __builtin_bit_cast(uint16_t, hi), b = __builtin_bit_cast(uint16_t, mid);
+  const uint32_t c = __builtin_bit_cast(uint16_t, lo);
+  return u32x4{a | (b << 16), c, 0, 0};
+}
 
 template <class T, int DH, int NW, int KT>
 __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
   using S = typename T::storage;
   constexpr int NT = NW * 64;
   constexpr int SZ = T::kBytes;
+  constexpr bool kBF16 = (SZ == 2);
   constexpr int E = 16 / SZ;              // elements per 16-byte chunk
   constexpr int KRS = DH * SZ + 16;       // LDS row stride of the K tile [KT][DH]
   constexpr int VRS = KT * SZ + 16;       // LDS row stride of the V^T tile [DH][KT]
@@ -86,99 +110,151 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
     }
   };
 
+  // Per-lane softmax state: m = running maximum of the scores (log2 units), l = partial row sum
+  // over this lane's keys (the two lane halves are added at the end), oacc = O^T.
   float m_run = -INFINITY, l_run = 0.f;
   f32x16 oacc = f32x16{};
-  const int nkt = (n + KT - 1) / KT;
-  if (nkt > 0) {
-    load(0);
-    store(0);
-  }
-  __syncthreads();
-  for (int t = 0; t < nkt; ++t) {
+  // BF16: the constant A operand (1, 1, 1, 0, ...) in the lanes of k-slots 0..7 (half 0).
+  [[maybe_unused]] const u32x4 kaug = h == 0 ? u32x4{0x3F803F80u, 0x3F80u, 0, 0} : u32x4{0, 0, 0, 0};
+
+  auto tile = [&](const int t, const auto masked_tag) {
+    constexpr bool kMasked = decltype(masked_tag)::value;
     const int kt0 = t * KT;
-    if (t + 1 < nkt) load(kt0 + KT);
     const char* Ks = smem + (t & 1) * (K_BYTES + V_BYTES);
     const char* Vs = Ks + K_BYTES;
 
     // S^T = K Q^T for each 32-key block.
+    u32x4 ka[NB][QKG];
     f32x16 s[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       s[b] = f32x16{};
 #pragma unroll
       for (int c = 0; c < QKG; ++c) {
-        const u32x4 ka = *(const u32x4*)(Ks + (32 * b + i) * KRS + (2 * c + h) * 16);
-        mma_kg<T>(ka, qr[c], s[b]);
+        ka[b][c] = *(const u32x4*)(Ks + (32 * b + i) * KRS + (2 * c + h) * 16);
+        mma_kg<T>(ka[b][c], qr[c], s[b]);
       }
     }
-    if (kt0 + KT > n) {
+    if constexpr (kMasked) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
           if (kt0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3) >= n) s[b][r] = -INFINITY;
     }
-
-    // Online softmax (log2 domain). Both lane halves hold the same query.
     float mx = -INFINITY;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[b][r]);
-    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-    const float m_new = fmaxf(m_run, mx);  // finite: every tile holds a valid key
-    const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
+    mx = fmaxf(mx, other_half(mx));  // finite: every tile holds a valid key
+    const float m_new = fmaxf(m_run, mx);
+    const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);  // 0 on the first tile
     m_run = m_new;
-    float ls = 0.f;
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float e = __builtin_amdgcn_exp2f(s[b][r] - m_new);
-        s[b][r] = e;
-        ls += e;
-      }
-    l_run = l_run * alpha + ls;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) oacc[r] *= alpha;
 
-    // O^T += V^T P^T. Row dh = l%32 of V^T (zero for dh >= DH). In FP32 the tile's product goes
-    // to a fresh partial first (shorter sequential addition chains over long events).
-    f32x16 pv = f32x16{};
-    f32x16& dst = (SZ == 4) ? pv : oacc;
+    if constexpr (kBF16) {
+      // S' = S - m: the products are recomputed with the offset folded in as an extra k-group
+      // (constant rows (1, 1, 1) times the exact 3-term split of -m): MFMA work instead of one
+      // VALU subtraction per score. Masked keys are re-masked.
+      const u32x4 qaug = h == 0 ? neg_split3(m_new) : u32x4{0, 0, 0, 0};
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if constexpr (SZ == 4) {
+      for (int b = 0; b < NB; ++b) {
+        s[b] = f32x16{};
+        mma_kg<T>(kaug, qaug, s[b]);
+#pragma unroll
+        for (int c = 0; c < QKG; ++c) mma_kg<T>(ka[b][c], qr[c], s[b]);
+      }
+      if constexpr (kMasked) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            if (kt0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3) >= n) s[b][r] = -INFINITY;
+      }
+      l_run *= alpha;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) oacc[r] *= alpha;
+      // P = exp2(S'), packed to bf16 for the PV product; the row sum adds the packed values
+      // (v_dot2_f32_bf16 against (1, 1)), i.e. exactly the weights the product uses. The dot is
+      // written as inline assembly: with this compiler the __builtin_amdgcn_fdot2_f32_bf16 form
+      // (selected as v_dot2c_f32_bf16 with a literal) read the first dword of the packed operand
+      // for all four dwords, which a GPU test caught as l four times too large.
+      uint32_t ones = 0x3F803F80u;
+      asm("" : "+v"(ones));
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          u32x4 pb;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const u32x2 pk = pack_bf16x4(__builtin_amdgcn_exp2f(s[b][8 * c + 4 * q + 0]),
+                                         __builtin_amdgcn_exp2f(s[b][8 * c + 4 * q + 1]),
+                                         __builtin_amdgcn_exp2f(s[b][8 * c + 4 * q + 2]),
+                                         __builtin_amdgcn_exp2f(s[b][8 * c + 4 * q + 3]));
+            pb[2 * q] = pk[0];
+            pb[2 * q + 1] = pk[1];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            asm("v_dot2_f32_bf16 %0, %1, %2, %0" : "+v"(l_run) : "v"(pb[q]), "v"(ones));
+          // O^T += V^T P^T: row dh = l%32 of V^T, keys matching the P^T register order.
+          u32x4 va = u32x4{0, 0, 0, 0};
+          if (i < DH) {
+            const u32x2 v0 = *(const u32x2*)(Vs + i * VRS + (32 * b + 16 * c + 4 * h) * 2);
+            const u32x2 v1 = *(const u32x2*)(Vs + i * VRS + (32 * b + 16 * c + 8 + 4 * h) * 2);
+            va = u32x4{v0[0], v0[1], v1[0], v1[1]};
+          }
+          mma_kg<T>(va, pb, oacc);
+        }
+      }
+    } else {
+      // FP32: P = exp2(S - m); the tile's PV product goes to a fresh partial first (shorter
+      // sequential addition chains over long events).
+      float ls = 0.f;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float e = __builtin_amdgcn_exp2f(s[b][r] - m_new);
+          s[b][r] = e;
+          ls += e;
+        }
+      l_run = l_run * alpha + ls;
+      f32x16 pv = f32x16{};
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const u32x4 va = (i < DH) ? *(const u32x4*)(Vs + i * VRS + (32 * b + 8 * c + 4 * h) * 4)
                                     : u32x4{0, 0, 0, 0};
           const u32x4 pb = {__float_as_uint(s[b][4 * c + 0]), __float_as_uint(s[b][4 * c + 1]),
                             __float_as_uint(s[b][4 * c + 2]), __float_as_uint(s[b][4 * c + 3])};
-          mma_kg<T>(va, pb, dst);
+          mma_kg<T>(va, pb, pv);
         }
-      } else {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          u32x4 va = u32x4{0, 0, 0, 0};
-          if (i < DH) {
-            const u32x2 lo = *(const u32x2*)(Vs + i * VRS + (32 * b + 16 * c + 4 * h) * 2);
-            const u32x2 hi = *(const u32x2*)(Vs + i * VRS + (32 * b + 16 * c + 8 + 4 * h) * 2);
-            va = u32x4{lo[0], lo[1], hi[0], hi[1]};
-          }
-          const u32x2 p0 = pack_bf16x4(s[b][8 * c + 0], s[b][8 * c + 1], s[b][8 * c + 2], s[b][8 * c + 3]);
-          const u32x2 p1 = pack_bf16x4(s[b][8 * c + 4], s[b][8 * c + 5], s[b][8 * c + 6], s[b][8 * c + 7]);
-          mma_kg<T>(va, u32x4{p0[0], p0[1], p1[0], p1[1]}, dst);
-        }
-      }
+      for (int r = 0; r < 16; ++r) oacc[r] = oacc[r] * alpha + pv[r];
     }
-    if constexpr (SZ == 4) oacc += pv;
+  };
+
+  const int nkt = (n + KT - 1) / KT;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  // Full tiles, then the last partial tile (the only one that needs the key mask).
+  const int nfull = n / KT;
+  for (int t = 0; t < nfull; ++t) {
+    if (t + 1 < nkt) load((t + 1) * KT);
+    tile(t, std::false_type{});
     if (t + 1 < nkt) store((t + 1) & 1);
     __syncthreads();
   }
+  if (nfull < nkt) tile(nfull, std::true_type{});
 
   // O = O^T / l. Lane l holds dh = 8c + 4*(l/32) + (0..3) of query l%32 in registers 4c..4c+3.
-  const float l_tot = l_run + __shfl_xor(l_run, 32, 64);
+  const float l_tot = l_run + other_half(l_run);
   if (q_ok) {
     const float inv = 1.0f / l_tot;
     S* orow = (S*)p.o + (int64_t)(start + qi) * p.d + head * DH;

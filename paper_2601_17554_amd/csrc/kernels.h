@@ -115,6 +115,10 @@ struct LayerNormArgs {
 };
 hipError_t launch_layernorm(Prec prec, const LayerNormArgs& args, hipStream_t stream);
 
+// dst[i] = src[i] * scale for n elements of the operand type.
+hipError_t launch_scale(Prec prec, void* dst, const void* src, int64_t n, float scale,
+                        hipStream_t stream);
+
 // Copies n floats (used to duplicate the embedding into the second stack of PARALLEL2).
 hipError_t launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t stream);
 

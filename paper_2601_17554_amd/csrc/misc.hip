@@ -217,6 +217,27 @@ hipError_t launch_layernorm(Prec prec, const LayerNormArgs& p, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void scale_kernel(S* dst, const S* src, int64_t n, float scale) {
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = (S)((float)src[i] * scale);
+}
+
+hipError_t launch_scale(Prec prec, void* dst, const void* src, int64_t n, float scale,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (prec == P_F32)
+    hipLaunchKernelGGL(scale_kernel<float>, dim3((unsigned)grid), dim3(256), 0, s, (float*)dst,
+                       (const float*)src, n, scale);
+  else
+    hipLaunchKernelGGL(scale_kernel<__bf16>, dim3((unsigned)grid), dim3(256), 0, s, (__bf16*)dst,
+                       (const __bf16*)src, n, scale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void copy_f32_kernel(float* dst, const float* src, int64_t n) {
   const int64_t n4 = n / 4;
   for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256)
