@@ -46,82 +46,124 @@ def make_batches(count: int, root_seed: int = 300):
     return [synth.pack(evs[i * EVENTS_PER_BATCH:(i + 1) * EVENTS_PER_BATCH]) for i in range(count)]
 
 
-def bench_varlen(args, cfg, w):
+def _timed_steps(stream, steps, fn):
+    """Runs fn(i) for i < steps between per-step events; returns (wall seconds, per-step ms)."""
     import torch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        fn(i)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+
+
+def bench_varlen(args, cfg, w):
+    """Graph-replayed varlen batches (timed region), then the same steps eagerly with the
+    per-kernel HIP-event profiler (kernel durations for the roofline)."""
+    import torch
+    from paper_2601_17554_amd import autotune
     from paper_2601_17554_amd import binding as B
 
     model = B.Model(cfg, w, args.precision)
     batches = make_batches(args.batches)
-    dev = []
-    for pk in batches:
-        dev.append((torch.from_numpy(pk.x).cuda(), B.Batch.from_host(pk.row_start, pk.n_valid)))
-    cap_rows = max(pk.total_rows for pk in batches)
-    ws = model.workspace(cap_rows, EVENTS_PER_BATCH)
-    outs = [model.outputs(pk.total_rows) for pk in batches]
-    stream = torch.cuda.current_stream()
-
-    def step(i):
-        x, b = dev[i % len(dev)]
-        model.reconstruct(x, b, ws=ws, out=outs[i % len(dev)])
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    model.profiler_enable(True)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record(stream)
-        step(i)
-        ends[i].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = model.profiler_read()
-    model.profiler_enable(False)
-    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    stream = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(stream):
+        dev = [(torch.from_numpy(pk.x).cuda(), B.Batch.from_host(pk.row_start, pk.n_valid)) for pk in batches]
+        wss = [model.workspace(pk.total_rows, EVENTS_PER_BATCH) for pk in batches]
+        outs = [model.outputs(pk.total_rows) for pk in batches]
+        stream.synchronize()
+        res["tiles"] = autotune.tune(model, dev[0][0], dev[0][1], ws=wss[0], use_cache=False)
+        graphs = [B.Graph(model, x, b, o, ws, stream) for (x, b), o, ws in zip(dev, outs, wss)]
+        for i in range(args.warmup):
+            graphs[i % len(graphs)].launch()
+        res["wall_s"], res["batch_ms"] = _timed_steps(stream, args.steps,
+                                                     lambda i: graphs[i % len(graphs)].launch())
+        # Eager pass of the same steps with the profiler on (kernel durations on this stream).
+        model.profiler_enable(True)
+        eager_wall, _ = _timed_steps(stream, args.steps, lambda i: model.reconstruct(
+            dev[i % len(dev)][0], dev[i % len(dev)][1], ws=wss[i % len(dev)], out=outs[i % len(dev)],
+            stream=stream))
+        res["prof"] = model.profiler_read()
+        model.profiler_enable(False)
+    res["eager_ms_per_step"] = eager_wall * 1e3 / args.steps
     n_timed = np.concatenate([batches[i % len(batches)].n_valid for i in range(args.steps)])
-    attn_ms, attn_launches = prof["attention"]
-    attn_flops = sum(attention_flops(batches[i % len(batches)].n_valid, cfg) * cfg.n_layers
-                     for i in range(args.steps))
-    return {
-        "wall_s": wall, "batch_ms": lat, "events": len(n_timed),
-        "flops": forward_flops(n_timed, cfg), "prof": prof,
-        "attn_ms": attn_ms, "attn_launches": attn_launches, "attn_flops": attn_flops,
-        "mean_n": float(n_timed.mean()),
-    }
+    res["events"] = len(n_timed)
+    res["flops"] = forward_flops(n_timed, cfg)
+    res["attn_ms"], res["attn_launches"] = res["prof"]["attention"]
+    res["attn_flops"] = sum(attention_flops(batches[i % len(batches)].n_valid, cfg) * cfg.n_layers
+                            for i in range(args.steps))
+    res["mean_n"] = float(n_timed.mean())
+    del graphs
+    return res
 
 
 def bench_plain_fp32(args, cfg, w):
+    """One full-size event per launch in FP32: eager (profiled) and graph-replayed latency."""
     import torch
+    from paper_2601_17554_amd import autotune
     from paper_2601_17554_amd import binding as B
 
     model = B.Model(cfg, w, "fp32")
     evs = synth.event_set(200, args.fp32_events, lo=500)
     pks = [synth.pack([e], pad_to=64) for e in evs]
-    dev = [(torch.from_numpy(p.x).cuda(), B.Batch.from_host(p.row_start, p.n_valid)) for p in pks]
-    ws = model.workspace(max(p.total_rows for p in pks), 1)
-    outs = [model.outputs(p.total_rows) for p in pks]
-    stream = torch.cuda.current_stream()
-    for i in range(min(3, len(dev))):
-        model.reconstruct(dev[i][0], dev[i][1], ws=ws, out=outs[i])
-    torch.cuda.synchronize()
-    model.profiler_enable(True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in dev]
-    t0 = time.perf_counter()
-    for i, (x, b) in enumerate(dev):
-        ev[i][0].record(stream)
-        model.reconstruct(x, b, ws=ws, out=outs[i])
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = model.profiler_read()
-    model.profiler_enable(False)
-    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        dev = [(torch.from_numpy(p.x).cuda(), B.Batch.from_host(p.row_start, p.n_valid)) for p in pks]
+        ws = model.workspace(max(p.total_rows for p in pks), 1)
+        outs = [model.outputs(p.total_rows) for p in pks]
+        med = int(np.argsort([e.n for e in evs])[len(evs) // 2])
+        stream.synchronize()
+        tiles = autotune.tune(model, dev[med][0], dev[med][1], ws=ws, use_cache=False)
+        for i in range(min(3, len(dev))):
+            model.reconstruct(dev[i][0], dev[i][1], ws=ws, out=outs[i], stream=stream)
+        model.profiler_enable(True)
+        wall, lat = _timed_steps(stream, len(dev), lambda i: model.reconstruct(
+            dev[i][0], dev[i][1], ws=ws, out=outs[i], stream=stream))
+        prof = model.profiler_read()
+        model.profiler_enable(False)
+        graphs = [B.Graph(model, x, b, o, ws, stream) for (x, b), o in zip(dev, outs)]
+        graphs[0].launch()
+        gwall, glat = _timed_steps(stream, len(dev), lambda i: graphs[i].launch())
+        del graphs
     n = np.array([e.n for e in evs])
     attn_flops = sum(attention_flops(np.array([k]), cfg) * cfg.n_layers for k in n)
-    return {"wall_s": wall, "lat_ms": lat, "n": n, "prof": prof, "attn_flops": attn_flops}
+    return {"wall_s": wall, "lat_ms": lat, "graph_wall_s": gwall, "graph_lat_ms": glat, "n": n,
+            "prof": prof, "attn_flops": attn_flops, "tiles": tiles}
+
+
+def bench_serving(args, cfg, w):
+    """Poisson arrivals at several rates through the continuous-batching server (BF16, up to 64
+    events per batch, slots bounded by a 64 GB activation budget); latency = arrival to result on
+    the host, including host packing and both PCIe copies."""
+    from paper_2601_17554_amd import binding as B
+    from paper_2601_17554_amd import serve
+
+    model = B.Model(cfg, w, args.precision)
+    ex = serve.GpuExecutor(model, max_rows=262144, max_events=EVENTS_PER_BATCH, slots=3,
+                           hbm_budget=64 << 30, buckets=4)
+    out = {}
+    for rate in args.serve_rates:
+        count = max(50, int(rate * args.serve_seconds))
+        evs = synth.event_set(400 + int(rate), count, lo=200)
+        arrivals = synth.poisson_arrivals(float(rate), count, seed=1400 + int(rate))
+        srv = serve.Server(ex)
+        wall = serve.run_poisson(srv, [e.x for e in evs], arrivals - arrivals[0])
+        srv.close()
+        lat = srv.latencies_ms()
+        out[str(rate)] = {"offered_events_per_s": rate, "events": count,
+                          "events_per_s": round(count / wall, 1),
+                          "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                          "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                          "batches": srv.stats["batches"],
+                          "max_slots_in_flight": srv.stats["max_inflight_slots"]}
+        print(f"serving {rate}/s: {out[str(rate)]}", file=sys.stderr, flush=True)
+    return {"slots": ex.slots(), "slot_bytes": ex.slot_bytes, "rates": out}
 
 
 def cpu_baseline(cfg, w, budget_s: float):
@@ -151,6 +193,8 @@ def main():
     ap.add_argument("--fp32-events", type=int, default=40)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rates", type=int, nargs="*", default=[200, 500, 1000, 2000])
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -179,27 +223,36 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": f"varlen_{args.precision}_64_events_per_launch",
-                   "events_per_step": EVENTS_PER_BATCH, "element_count": "lognormal median 3000 sigma 0.5 in [200, 8192]",
-                   "mean_elements": round(vr["mean_n"], 1), "model": "d256 h8 ffn1024 L6 (5.14M params)"},
+        "config": {"workload": f"varlen_{args.precision}_64_events_per_launch_hipgraph",
+                   "events_per_step": EVENTS_PER_BATCH,
+                   "element_count": "lognormal median 3000 sigma 0.5 in [200, 8192]",
+                   "mean_elements": round(vr["mean_n"], 1),
+                   "model": "d256 h8 ffn1024 L6 (5.14M params)", "tiles": vr["tiles"]},
         "p50_ms_per_batch": round(float(np.percentile(vr["batch_ms"], 50)), 3),
         "p99_ms_per_batch": round(float(np.percentile(vr["batch_ms"], 99)), 3),
         "p50_ms_per_event_amortised": round(float(np.percentile(per_event, 50)), 4),
         "p99_ms_per_event_amortised": round(float(np.percentile(per_event, 99)), 4),
+        "eager_ms_per_step": round(vr["eager_ms_per_step"], 3),
         "forward_tflops": round(vr["flops"] / vr["wall_s"] / 1e12, 1),
         "fp32_plain": {
-            "value": round(len(pl["n"]) / pl["wall_s"], 2), "unit": "events/s",
-            "p50_ms_per_event": round(float(np.percentile(pl["lat_ms"], 50)), 3),
-            "p99_ms_per_event": round(float(np.percentile(pl["lat_ms"], 99)), 3),
+            "value": round(len(pl["n"]) / pl["graph_wall_s"], 2), "unit": "events/s",
+            "p50_ms_per_event": round(float(np.percentile(pl["graph_lat_ms"], 50)), 3),
+            "p99_ms_per_event": round(float(np.percentile(pl["graph_lat_ms"], 99)), 3),
+            "eager_value": round(len(pl["n"]) / pl["wall_s"], 2),
+            "eager_p50_ms_per_event": round(float(np.percentile(pl["lat_ms"], 50)), 3),
+            "eager_p99_ms_per_event": round(float(np.percentile(pl["lat_ms"], 99)), 3),
             "events": int(len(pl["n"])), "median_elements": int(np.median(pl["n"])),
             "attention_tflops": round(pl_achieved, 1),
             "attention_frac_fp32_peak": round(pl_achieved / PEAK_TFLOPS["fp32"], 4),
+            "tiles": pl["tiles"],
         },
         "roofline": {"bound": "mfma", "kernel": "attention", "achieved": round(achieved, 1),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None, "avg_launch_ms": round(attn_avg_ms, 4)},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in vr["prof"].items()},
     }
+    if args.serve_rates:
+        line["serving"] = bench_serving(args, cfg, w)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, w, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -145,6 +145,23 @@ mlpf_status_t mlpf_reconstruct_events(mlpf_model_t model, const float* x,
                                       int32_t* cls, const float* prim, float* decoded, void* ws,
                                       size_t ws_bytes, void* stream);
 
+/* Captured forward passes (HIP graphs). mlpf_graph_create captures one mlpf_reconstruct_events
+ * call with exactly these arguments on `stream` (which must not be the NULL stream; nothing is
+ * executed during capture) and instantiates it. Every kernel reads the batch description
+ * (row_start, n_valid) and the inputs from the given device buffers when the graph runs, and sizes
+ * its launch from the host values of `batch`, which become capacities: a replay computes any batch
+ * whose buffers are rewritten in place with at most batch->total_rows rows, batch->n_events events
+ * (trailing unused events given zero rows by repeating the last row_start value) and valid counts
+ * <= batch->max_seqlen. Rows beyond the last event cost nothing. The graph borrows all buffers and
+ * the model. Launches of one graph must be serialised (they share the workspace). */
+typedef struct mlpf_graph_s* mlpf_graph_t;
+mlpf_status_t mlpf_graph_create(mlpf_model_t model, const float* x, const mlpf_batch_t* batch,
+                                float* logits, float* reg, int32_t* cls, const float* prim,
+                                float* decoded, void* ws, size_t ws_bytes, void* stream,
+                                mlpf_graph_t* out);
+mlpf_status_t mlpf_graph_launch(mlpf_graph_t graph, void* stream);
+mlpf_status_t mlpf_graph_destroy(mlpf_graph_t graph);
+
 /* Optional per-kernel timing for benchmarks. While enabled on a model, every launch of a kernel
  * class (below) made through that model is bracketed by a pair of HIP events recorded on the launch
  * stream (event objects are created on first use; do not enable it around graph capture).
@@ -182,6 +199,14 @@ typedef enum {
 int32_t mlpf_tune_count(int32_t op);
 mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile);
 int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule */
+
+/* FP8 activation calibration for MLPF_BF16_FP8FFN. Runs the embedding and encoder of `model` (an
+ * FP32 or BF16 model) on the batch and raises amax[2l] to max |LN2 output| and amax[2l+1] to
+ * max |GELU(FFN1)| of block l, over every live row (so calibration batches should carry no padding
+ * rows). amax: device FP32 [2 n_layers] holding non-negative values on entry (zero it before the
+ * first batch; calls accumulate the maximum). The act_scales of mlpf_model_create are amax / 448. */
+mlpf_status_t mlpf_calibrate_fp8(mlpf_model_t model, const float* x, const mlpf_batch_t* batch,
+                                 float* amax, void* ws, size_t ws_bytes, void* stream);
 
 /* Masked variable-length multi-head self-attention alone (Eq. 4): for every event e and head j,
  *   o[rows of e][j*d_head .. (j+1)*d_head-1] = softmax(q_j k_j^T / sqrt(d_head)) v_j

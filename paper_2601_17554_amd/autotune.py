@@ -1,0 +1,107 @@
+"""Tile-shape autotuner for libmlpf.
+
+For one workload (model, device batch), every op's tile shapes (mlpf_tune_count) are timed with the
+library's HIP-event profiler while the other ops keep their current choice; the fastest shape that
+passes the correctness guard is pinned with mlpf_tune_set. The guard compares the final outputs of
+each candidate with the reference run: GEMM tiles must give bitwise identical outputs (every GEMM
+tile sums k in the same order), attention tiles must agree to a relative 1e-3 of the logits scale
+(they change only the order of the online-softmax updates). Choices are cached in a JSON file
+(``MLPF_AUTOTUNE_CACHE``, default ``~/.cache/mlpf_autotune.json``) keyed by GPU architecture,
+precision, model sizes and the batch's size bucket.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Optional
+
+import torch
+
+from . import binding as B
+
+# Profiler class that times each op (ops sharing a class are compared with the others fixed).
+_CLASS = {"embed1": "embed", "embed2": "embed", "qkv": "qkv", "outproj": "outproj", "ffn1": "ffn1",
+          "ffn2": "ffn2", "heads1": "heads", "attention": "attention"}
+
+
+def cache_path() -> str:
+    return os.environ.get("MLPF_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "mlpf_autotune.json"))
+
+
+def cache_key(model: B.Model, batch: B.Batch) -> str:
+    c = model.cfg
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    rows = 1 << max(0, math.ceil(math.log2(max(batch.total_rows, 1))))
+    return (f"{arch}|{model.precision}|d{c.d_model}h{c.n_heads}ff{c.d_ff}L{c.n_layers}{c.topology}"
+            f"|rows{rows}|ev{batch.n_events}")
+
+
+def _run(model, x, batch, ws, out, reps: int) -> Dict[str, float]:
+    model.reconstruct(x, batch, ws=ws, out=out)
+    torch.cuda.synchronize()
+    model.profiler_enable(True)
+    for _ in range(reps):
+        model.reconstruct(x, batch, ws=ws, out=out)
+    torch.cuda.synchronize()
+    prof = model.profiler_read()
+    model.profiler_enable(False)
+    return {k: v[0] / reps for k, v in prof.items()}
+
+
+def _same(a: Dict[str, torch.Tensor], b: Dict[str, torch.Tensor], exact: bool) -> bool:
+    if exact:
+        return all(torch.equal(a[k], b[k]) for k in ("logits", "reg", "cls"))
+    scale = max(float(a["logits"].abs().max()), 1e-6)
+    return float((a["logits"] - b["logits"]).abs().max()) <= 1e-3 * scale and \
+        float((a["reg"] - b["reg"]).abs().max()) <= 1e-3 * max(float(a["reg"].abs().max()), 1e-6)
+
+
+def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Tensor] = None,
+         reps: int = 3, use_cache: bool = True, verbose: bool = False) -> Dict[str, int]:
+    """Chooses and pins a tile shape per op for this workload; returns {op: tile}."""
+    key = cache_key(model, batch)
+    path = cache_path()
+    if use_cache and os.path.exists(path):
+        try:
+            cached = json.load(open(path)).get(key)
+        except (OSError, ValueError):
+            cached = None
+        if cached:
+            for op, t in cached.items():
+                model.tune_set(op, int(t))
+            return {op: int(t) for op, t in cached.items()}
+    if ws is None:
+        ws = model.workspace(batch.total_rows, batch.n_events)
+    out = model.outputs(batch.total_rows)
+    for op in B.OPS:
+        model.tune_set(op, -1)
+    model.reconstruct(x, batch, ws=ws, out=out)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in out.items()}
+    choice: Dict[str, int] = {}
+    for op in B.OPS:
+        best, best_t = None, float("inf")
+        for tile in range(B.Model.tune_count(op)):
+            model.tune_set(op, tile)
+            t = _run(model, x, batch, ws, out, reps)[_CLASS[op]]
+            ok = _same(out, ref, exact=(op != "attention"))
+            if verbose:
+                print(f"autotune {op} tile {tile}: {t:.4f} ms {'ok' if ok else 'REJECTED'}", flush=True)
+            if ok and t < best_t:
+                best, best_t = tile, t
+        model.tune_set(op, best if best is not None else -1)
+        choice[op] = best if best is not None else -1
+    if use_cache:
+        try:
+            data = json.load(open(path)) if os.path.exists(path) else {}
+        except (OSError, ValueError):
+            data = {}
+        data[key] = choice
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return choice

@@ -71,6 +71,10 @@ def load() -> ctypes.CDLL:
         "mlpf_profiler_read": (st, [vp, st, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64)]),
         "mlpf_attention_forward": (st, [vp, vp, vp, vp, vp, bp, vp, sz, vp]),
+        "mlpf_calibrate_fp8": (st, [vp, vp, bp, vp, vp, sz, vp]),
+        "mlpf_graph_create": (st, [vp, vp, bp, vp, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]),
+        "mlpf_graph_launch": (st, [vp, vp]),
+        "mlpf_graph_destroy": (st, [vp]),
         "mlpf_tune_count": (i32, [i32]),
         "mlpf_tune_set": (st, [vp, i32, i32]),
         "mlpf_tune_get": (i32, [vp, i32]),
@@ -88,7 +92,8 @@ def exported_symbols() -> Sequence[str]:
     return ("mlpf_weights_bytes", "mlpf_weights_count", "mlpf_model_create", "mlpf_model_destroy",
             "mlpf_workspace_bytes", "mlpf_embed", "mlpf_encoder_forward", "mlpf_heads",
             "mlpf_reconstruct_events", "mlpf_profiler_enable", "mlpf_profiler_read",
-            "mlpf_attention_forward", "mlpf_tune_count", "mlpf_tune_set", "mlpf_tune_get",
+            "mlpf_attention_forward", "mlpf_calibrate_fp8", "mlpf_graph_create", "mlpf_graph_launch",
+            "mlpf_graph_destroy", "mlpf_tune_count", "mlpf_tune_set", "mlpf_tune_get",
             "mlpf_status_string", "mlpf_last_error")
 
 
@@ -197,6 +202,49 @@ def mlpf_attention_forward(model: "Model", q, k, v, o, batch: Batch, ws, stream=
                                          _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
+def build_fp8_model(cfg, weights: Mapping[str, np.ndarray], calib: Sequence, device: str = "cuda",
+                    calib_precision: str = "fp32") -> "Model":
+    """An MLPF_BF16_FP8FFN model whose activation scales are calibrated on ``calib`` (a sequence of
+    (x [T][F] float32 array, row_start, n_valid) host batches without padding rows): per-tensor
+    amax of each block's FFN inputs on the calibration model, scale = amax / 448."""
+    ref = Model(cfg, weights, calib_precision, device=device)
+    amax = torch.zeros(2 * cfg.n_layers, dtype=torch.float32, device=device)
+    for x, row_start, n_valid in calib:
+        batch = Batch.from_host(row_start, n_valid, device=device)
+        ref.calibrate_fp8(torch.from_numpy(np.ascontiguousarray(x)).to(device), batch, amax)
+    torch.cuda.synchronize()
+    scales = np.maximum(amax.cpu().numpy().astype(np.float64), 1e-30) / 448.0
+    return Model(cfg, weights, "bf16_fp8ffn", act_scales=scales.astype(np.float32), device=device)
+
+
+class Graph:
+    """A captured mlpf_reconstruct_events call (see mlpf_graph_create). Holds references to every
+    buffer it borrows. Capacity = the host sizes of ``batch``; rewrite x / row_start / n_valid /
+    prim in place (same tensors) and call ``launch``."""
+
+    def __init__(self, model: "Model", x, batch: "Batch", out: Dict[str, torch.Tensor], ws,
+                 stream: torch.cuda.Stream, prim=None):
+        self.model, self.x, self.batch, self.out, self.ws, self.prim = model, x, batch, out, ws, prim
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        _check(load().mlpf_graph_create(model.handle, _ptr(x), batch.c, _ptr(out["logits"]),
+                                        _ptr(out["reg"]), _ptr(out["cls"]), _ptr(prim),
+                                        _ptr(out.get("decoded")), _ptr(ws),
+                                        ws.numel() * ws.element_size(), stream.cuda_stream,
+                                        ctypes.byref(handle)))
+        self.handle = handle
+
+    def launch(self, stream: Optional[torch.cuda.Stream] = None) -> None:
+        s = stream if stream is not None else self.stream
+        _check(load().mlpf_graph_launch(self.handle, s.cuda_stream))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.mlpf_graph_destroy(h)
+            self.handle = None
+
+
 class Model:
     """A libmlpf model handle with its device weight buffer (allocated by torch)."""
 
@@ -287,6 +335,14 @@ class Model:
         o = torch.zeros(batch.total_rows, self.cfg.d_model, dtype=q.dtype, device=self.device)
         mlpf_attention_forward(self, q, k, v, o, batch, ws)
         return o
+
+    def calibrate_fp8(self, x, batch: Batch, amax: torch.Tensor, ws=None) -> torch.Tensor:
+        """Raises amax ([2 n_layers] float32, device) to the FFN input maxima on this batch."""
+        if ws is None:
+            ws = self.workspace(batch.total_rows, batch.n_events)
+        _check(load().mlpf_calibrate_fp8(self.handle, _ptr(x), batch.c, _ptr(amax), _ptr(ws),
+                                         ws.numel() * ws.element_size(), _stream(None)))
+        return amax
 
     def embed(self, x, batch: Batch, ws=None) -> torch.Tensor:
         if ws is None:

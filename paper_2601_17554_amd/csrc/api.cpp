@@ -56,6 +56,8 @@ constexpr int kEmbedKp = 64;
 
 struct Layer {
   size_t ln1g, ln1b, wqkv, bqkv, wo, bo, ln2g, ln2b, w1, b1, w2, b2;
+  // FP8 FFN: per-tensor weight scales and activation scales (FFN1 input, FFN2 input).
+  float s_w1 = 1.f, s_w2 = 1.f, s_a1 = 1.f, s_a2 = 1.f;
 };
 
 // Byte offsets of every packed tensor inside the device weight buffer.
@@ -67,9 +69,33 @@ struct WeightPlan {
 };
 
 int elem_bytes(mlpf_precision_t p) { return p == MLPF_FP32 ? 4 : 2; }
+int ffn_elem_bytes(mlpf_precision_t p) { return p == MLPF_BF16_FP8FFN ? 1 : elem_bytes(p); }
+
+// OCP FP8 E4M3 (bias 7, max 448, 0x7f = NaN): value of a non-negative code.
+double e4m3_value(int c) {
+  const int e = c >> 3, m = c & 7;
+  return e == 0 ? (m / 8.0) * std::ldexp(1.0, -6) : (1.0 + m / 8.0) * std::ldexp(1.0, e - 7);
+}
+
+// Round to nearest (ties to even code) with saturation at +-448.
+uint8_t f32_to_e4m3(float x) {
+  if (std::isnan(x)) return 0x7f;
+  const uint8_t sign = std::signbit(x) ? 0x80 : 0;
+  const double a = std::fabs((double)x);
+  if (a >= 448.0) return sign | 0x7e;
+  int lo = 0, hi = 0x7e;
+  while (lo < hi) {  // largest code with value <= a
+    const int mid = (lo + hi + 1) / 2;
+    if (e4m3_value(mid) <= a) lo = mid;
+    else hi = mid - 1;
+  }
+  const double d0 = a - e4m3_value(lo), d1 = e4m3_value(lo + 1) - a;
+  const int c = d0 < d1 ? lo : d0 > d1 ? lo + 1 : ((lo & 1) ? lo + 1 : lo);
+  return sign | (uint8_t)c;
+}
 
 WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
-  const size_t d = c.d_model, ff = c.d_ff, eb = elem_bytes(prec);
+  const size_t d = c.d_model, ff = c.d_ff, eb = elem_bytes(prec), fb = ffn_elem_bytes(prec);
   WeightPlan w{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -91,9 +117,9 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
     L.bo = take(d * 4);
     L.ln2g = take(d * 4);
     L.ln2b = take(d * 4);
-    L.w1 = take(ff * d * eb);
+    L.w1 = take(ff * d * fb);
     L.b1 = take(ff * 4);
-    L.w2 = take(d * ff * eb);
+    L.w2 = take(d * ff * fb);
     L.b2 = take(d * 4);
   }
   w.h_w1 = take(5 * d * d * eb);
@@ -250,6 +276,7 @@ struct Ctx {
   char* ws;
   hipStream_t s;
   const int32_t* n_rows;  // device count of live rows, or NULL
+  float* calib = nullptr; // FP8 calibration: [2 L] running amax of the FFN inputs, or NULL
   void* p(size_t off) const { return ws + off; }
 };
 
@@ -257,16 +284,19 @@ int attn_tile_of(const mlpf_model_s* m) {
   return m->tune[MLPF_OP_ATTENTION] >= 0 ? m->tune[MLPF_OP_ATTENTION] : 0;
 }
 
-mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a) {
+mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a, int prec = -1) {
   a.m_dev = cx.n_rows;
   const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N);
-  HIP_TRY(launch_gemm(cx.m->kprec, al, ep, tile, a, cx.s), "gemm launch");
+  HIP_TRY(launch_gemm(prec >= 0 ? (Prec)prec : cx.m->kprec, al, ep, tile, a, cx.s), "gemm launch");
   return MLPF_OK;
 }
 
 // y = LayerNorm(h) in the operand type (the A operand of the next product).
-mlpf_status_t run_layernorm(const Ctx& cx, const float* h, size_t g_off, size_t b_off) {
+mlpf_status_t run_layernorm(const Ctx& cx, const float* h, size_t g_off, size_t b_off,
+                            int prec = -1, float out_scale = 1.f, float* amax = nullptr) {
   LayerNormArgs a;
+  a.out_scale = out_scale;
+  a.amax = amax;
   a.x = h;
   a.y = cx.p(cx.w.y);
   a.rows = cx.b->total_rows;
@@ -275,7 +305,7 @@ mlpf_status_t run_layernorm(const Ctx& cx, const float* h, size_t g_off, size_t 
   a.gamma = cx.m->atf(g_off);
   a.beta = cx.m->atf(b_off);
   a.eps = cx.m->cfg.ln_eps;
-  HIP_TRY(launch_layernorm(cx.m->kprec, a, cx.s), "layernorm launch");
+  HIP_TRY(launch_layernorm(prec >= 0 ? (Prec)prec : cx.m->kprec, a, cx.s), "layernorm launch");
   return MLPF_OK;
 }
 
@@ -404,7 +434,12 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
     ProfScope prof(cx.m, MLPF_PROF_OUTPROJ, cx.s);
     if ((st = run_gemm(cx, MLPF_OP_OUTPROJ, A_PLAIN, E_RESID, o))) return st;
   }
-  // LN2 + FFN1 + GELU.
+  // LN2 + FFN1 + GELU, FFN2 + residual. FP8 mode: LN2 writes E4M3 (scaled by 1/s_a1), FFN1
+  // dequantises with s_a1 s_w1 and writes GELU output as E4M3 (1/s_a2), FFN2 dequantises with
+  // s_a2 s_w2.
+  const bool fp8 = m->prec == MLPF_BF16_FP8FFN;
+  float* am1 = cx.calib ? cx.calib + 2 * layer : nullptr;
+  float* am2 = cx.calib ? cx.calib + 2 * layer + 1 : nullptr;
   GemmArgs f1;
   f1.a = cx.p(cx.w.y);
   f1.lda = d;
@@ -416,12 +451,17 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
   f1.bias = m->atf(L.b1);
   f1.out = cx.p(cx.w.u);
   f1.ldo = c.d_ff;
+  f1.amax = am2;
+  if (fp8) {
+    f1.acc_scale = L.s_a1 * L.s_w1;
+    f1.out_scale = 1.f / L.s_a2;
+  }
   {
     ProfScope prof(cx.m, MLPF_PROF_FFN1, cx.s);
-    if ((st = run_layernorm(cx, h, L.ln2g, L.ln2b))) return st;
-    if ((st = run_gemm(cx, MLPF_OP_FFN1, A_PLAIN, E_GELU, f1))) return st;
+    if ((st = run_layernorm(cx, h, L.ln2g, L.ln2b, fp8 ? P_FP8 : -1, fp8 ? 1.f / L.s_a1 : 1.f, am1)))
+      return st;
+    if ((st = run_gemm(cx, MLPF_OP_FFN1, A_PLAIN, E_GELU, f1, fp8 ? P_FP8 : -1))) return st;
   }
-  // FFN2 + residual.
   GemmArgs f2;
   f2.a = cx.p(cx.w.u);
   f2.lda = c.d_ff;
@@ -433,8 +473,9 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
   f2.bias = m->atf(L.b2);
   f2.out = h;
   f2.ldo = d;
+  if (fp8) f2.acc_scale = L.s_a2 * L.s_w2;
   ProfScope prof(cx.m, MLPF_PROF_FFN2, cx.s);
-  return run_gemm(cx, MLPF_OP_FFN2, A_PLAIN, E_RESID, f2);
+  return run_gemm(cx, MLPF_OP_FFN2, A_PLAIN, E_RESID, f2, fp8 ? P_FP8 : -1);
 }
 
 mlpf_status_t do_encoder(Ctx& cx, float* h) {
@@ -442,7 +483,7 @@ mlpf_status_t do_encoder(Ctx& cx, float* h) {
   const int64_t td = (int64_t)cx.b->total_rows * m->cfg.d_model;
   if (cx.b->total_rows == 0) return MLPF_OK;
   mlpf_status_t st;
-  if ((st = do_worklist(cx))) return st;
+  if (!cx.n_rows && (st = do_worklist(cx))) return st;
   if (m->stacks == 1) {
     for (int l = 0; l < m->cfg.n_layers; ++l)
       if ((st = do_layer(cx, l, h))) return st;
@@ -525,7 +566,7 @@ extern "C" {
 
 size_t mlpf_weights_bytes(const mlpf_config_t* cfg, mlpf_precision_t precision) {
   if (check_config(cfg) != MLPF_OK) return 0;
-  if (precision != MLPF_FP32 && precision != MLPF_BF16) return 0;
+  if (precision != MLPF_FP32 && precision != MLPF_BF16 && precision != MLPF_BF16_FP8FFN) return 0;
   return plan_weights(*cfg, precision).total;
 }
 
@@ -538,19 +579,22 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
                                 const float* host_weights, size_t n_floats,
                                 const float* act_scales, void* dev_weights, size_t dev_bytes,
                                 void* stream, mlpf_model_t* out) {
-  (void)act_scales;
   if (!out) return fail(MLPF_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   mlpf_status_t st = check_config(cfg);
   if (st) return st;
-  if (precision == MLPF_BF16_FP8FFN)
-    return fail(MLPF_ERR_UNSUPPORTED, "precision MLPF_BF16_FP8FFN is not available in this build");
-  if (precision != MLPF_FP32 && precision != MLPF_BF16)
+  if (precision != MLPF_FP32 && precision != MLPF_BF16 && precision != MLPF_BF16_FP8FFN)
     return fail(MLPF_ERR_INVALID_ARG, "unknown precision %d", (int)precision);
+  if (precision == MLPF_BF16_FP8FFN) {
+    if (!act_scales) return fail(MLPF_ERR_INVALID_ARG, "MLPF_BF16_FP8FFN needs act_scales");
+    for (int i = 0; i < 2 * cfg->n_layers; ++i)
+      if (!(act_scales[i] > 0.f) || !std::isfinite(act_scales[i]))
+        return fail(MLPF_ERR_INVALID_ARG, "act_scales[%d] must be positive and finite", i);
+  }
   if (!host_weights) return fail(MLPF_ERR_INVALID_ARG, "host_weights is NULL");
   if (n_floats != master_count(*cfg))
     return fail(MLPF_ERR_INVALID_ARG, "n_floats=%zu, expected %zu", n_floats, master_count(*cfg));
-  const WeightPlan plan = plan_weights(*cfg, precision);
+  WeightPlan plan = plan_weights(*cfg, precision);
   if (!dev_weights) return fail(MLPF_ERR_INVALID_ARG, "dev_weights is NULL");
   if (dev_bytes < plan.total)
     return fail(MLPF_ERR_INVALID_ARG, "dev_bytes=%zu < %zu", dev_bytes, plan.total);
@@ -579,12 +623,23 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
       }
     src += (size_t)in * outn;
   };
+  // FP8 E4M3 with a per-tensor scale amax / 448; returns the scale.
+  auto put_wt_fp8 = [&](size_t off, int in, int outn, int kp) {
+    float amax = 0.f;
+    for (size_t i = 0; i < (size_t)in * outn; ++i) amax = std::max(amax, std::fabs(src[i]));
+    const float scale = amax > 0.f ? amax / 448.0f : 1.0f;
+    for (int i = 0; i < in; ++i)
+      for (int o = 0; o < outn; ++o)
+        img[off + (size_t)o * kp + i] = f32_to_e4m3(src[(size_t)i * outn + o] / scale);
+    src += (size_t)in * outn;
+    return scale;
+  };
   put_wt(plan.e_w1, f, d, kEmbedKp);
   put_f32(plan.e_b1, d);
   put_wt(plan.e_w2, d, d, d);
   put_f32(plan.e_b2, d);
   for (int l = 0; l < c.n_layers; ++l) {
-    const Layer& L = plan.layers[l];
+    const Layer L = plan.layers[l];
     put_f32(L.ln1g, d);
     put_f32(L.ln1b, d);
     put_wt(L.wqkv, d, 3 * d, d);
@@ -593,10 +648,20 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
     put_f32(L.bo, d);
     put_f32(L.ln2g, d);
     put_f32(L.ln2b, d);
-    put_wt(L.w1, d, ff, d);
-    put_f32(L.b1, ff);
-    put_wt(L.w2, ff, d, ff);
-    put_f32(L.b2, d);
+    if (precision == MLPF_BF16_FP8FFN) {
+      Layer& Lm = plan.layers[l];
+      Lm.s_w1 = put_wt_fp8(L.w1, d, ff, d);
+      put_f32(L.b1, ff);
+      Lm.s_w2 = put_wt_fp8(L.w2, ff, d, ff);
+      put_f32(L.b2, d);
+      Lm.s_a1 = act_scales[2 * l];
+      Lm.s_a2 = act_scales[2 * l + 1];
+    } else {
+      put_wt(L.w1, d, ff, d);
+      put_f32(L.b1, ff);
+      put_wt(L.w2, ff, d, ff);
+      put_f32(L.b2, d);
+    }
   }
   // Heads: W1 of the five heads stacked as rows of W^T [5d][d]; W2 as [d][11].
   static const int widths[5] = {6, 1, 1, 2, 1};
@@ -693,9 +758,74 @@ mlpf_status_t mlpf_reconstruct_events(mlpf_model_t model, const float* x,
   if (batch->total_rows == 0) return MLPF_OK;
   if (!x || !logits || !reg || !cls) return fail(MLPF_ERR_INVALID_ARG, "x or an output is NULL");
   float* h = (float*)cx.p(cx.w.h);
+  // The work list first: it also yields the live row count that lets every kernel skip rows
+  // beyond the last event (a captured graph sized for a capacity then does no dead work).
+  if ((st = do_worklist(cx))) return st;
   if ((st = do_embed(cx, x, h))) return st;
   if ((st = do_encoder(cx, h))) return st;
   return do_heads(cx, h, logits, reg, cls, prim, decoded);
+}
+
+struct mlpf_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+mlpf_status_t mlpf_graph_create(mlpf_model_t model, const float* x, const mlpf_batch_t* batch,
+                                float* logits, float* reg, int32_t* cls, const float* prim,
+                                float* decoded, void* ws, size_t ws_bytes, void* stream,
+                                mlpf_graph_t* out) {
+  if (!out) return fail(MLPF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!stream) return fail(MLPF_ERR_INVALID_ARG, "graph capture needs a non-default stream");
+  if (!model) return fail(MLPF_ERR_INVALID_ARG, "model is NULL");
+  if (model->prof_on) return fail(MLPF_ERR_INVALID_ARG, "disable the profiler before capturing");
+  Ctx cx;
+  mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, true, &cx);
+  if (st) return st;
+  if (batch->total_rows == 0) return fail(MLPF_ERR_INVALID_ARG, "empty capacity");
+  if (!x || !logits || !reg || !cls) return fail(MLPF_ERR_INVALID_ARG, "x or an output is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+  st = mlpf_reconstruct_events(model, x, batch, logits, reg, cls, prim, decoded, ws, ws_bytes,
+                               stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (ec != hipSuccess) return hip_fail(ec, "end capture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(ei, "graph instantiate");
+  }
+  mlpf_graph_s* gr = new (std::nothrow) mlpf_graph_s();
+  if (!gr) {
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
+    return fail(MLPF_ERR_INTERNAL, "out of host memory");
+  }
+  gr->graph = g;
+  gr->exec = ex;
+  *out = gr;
+  return MLPF_OK;
+}
+
+mlpf_status_t mlpf_graph_launch(mlpf_graph_t graph, void* stream) {
+  if (!graph) return fail(MLPF_ERR_INVALID_ARG, "graph is NULL");
+  HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream), "graph launch");
+  return MLPF_OK;
+}
+
+mlpf_status_t mlpf_graph_destroy(mlpf_graph_t graph) {
+  if (!graph) return MLPF_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return MLPF_OK;
 }
 
 int32_t mlpf_tune_count(int32_t op) {
@@ -742,6 +872,22 @@ mlpf_status_t mlpf_profiler_read(mlpf_model_t model, int kernel_class, double* t
   *total_ms = tot;
   *launches = (int64_t)used;
   return MLPF_OK;
+}
+
+mlpf_status_t mlpf_calibrate_fp8(mlpf_model_t model, const float* x, const mlpf_batch_t* batch,
+                                 float* amax, void* ws, size_t ws_bytes, void* stream) {
+  Ctx cx;
+  mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, true, &cx);
+  if (st) return st;
+  if (model->prec == MLPF_BF16_FP8FFN)
+    return fail(MLPF_ERR_INVALID_ARG, "calibrate with an FP32 or BF16 model");
+  if (batch->total_rows == 0) return MLPF_OK;
+  if (!x || !amax) return fail(MLPF_ERR_INVALID_ARG, "x or amax is NULL");
+  cx.calib = amax;
+  float* h = (float*)cx.p(cx.w.h);
+  if ((st = do_worklist(cx))) return st;
+  if ((st = do_embed(cx, x, h))) return st;
+  return do_encoder(cx, h);
 }
 
 mlpf_status_t mlpf_attention_forward(mlpf_model_t model, const void* q, const void* k,

@@ -22,6 +22,28 @@ struct BF16 {
   using storage = __bf16;
   static constexpr int kBytes = 2;
 };
+// FP8 E4M3 (OCP: bias 7, max 448), one raw byte per value.
+struct FP8 {
+  using storage = uint8_t;
+  static constexpr int kBytes = 1;
+};
+constexpr float kFp8Max = 448.0f;
+
+// Rounds to FP8 E4M3 (nearest even) after clamping to +-448, so out-of-range values saturate.
+__device__ __forceinline__ uint8_t to_fp8(float x) {
+  x = fminf(fmaxf(x, -kFp8Max), kFp8Max);
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, x, 0, false) & 0xff);
+}
+// Four floats (already scaled) to four FP8 bytes in one dword.
+__device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float d) {
+  a = fminf(fmaxf(a, -kFp8Max), kFp8Max);
+  b = fminf(fmaxf(b, -kFp8Max), kFp8Max);
+  c = fminf(fmaxf(c, -kFp8Max), kFp8Max);
+  d = fminf(fmaxf(d, -kFp8Max), kFp8Max);
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (uint32_t)w;
+}
 
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -62,6 +84,16 @@ __device__ __forceinline__ void mma_kg<BF16>(const u32x4& a, const u32x4& b, f32
                                               __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// FP8: 2 x v_mfma_f32_32x32x16_fp8_fp8 (group = 32 k-values: half h holds k = 16h .. 16h+15; the
+// first MFMA takes bytes 0..7 of both halves, the second bytes 8..15).
+template <>
+__device__ __forceinline__ void mma_kg<FP8>(const u32x4& a, const u32x4& b, f32x16& c) {
+  const long a0 = (long)a[0] | ((long)a[1] << 32), b0 = (long)b[0] | ((long)b[1] << 32);
+  const long a1 = (long)a[2] | ((long)a[3] << 32), b1 = (long)b[2] | ((long)b[3] << 32);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, c, 0, 0, 0);
+}
+
 // Converts E = 16 / sizeof(T) floats to one 16-byte chunk of T.
 template <class T>
 __device__ __forceinline__ u32x4 to_chunk(const float* v);
@@ -77,6 +109,17 @@ __device__ __forceinline__ u32x4 to_chunk<BF16>(const float* v) {
   u32x2 lo = pack_bf16x4(v[0], v[1], v[2], v[3]);
   u32x2 hi = pack_bf16x4(v[4], v[5], v[6], v[7]);
   return u32x4{lo[0], lo[1], hi[0], hi[1]};
+}
+
+// Raises *dst to v (v >= 0) with an integer atomic max on the float bits (order-independent).
+__device__ __forceinline__ void atomic_max_nonneg(float* dst, float v) {
+  atomicMax((int*)dst, __float_as_int(v));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
 }
 
 // Workgroups of a launch are dealt round-robin to the 8 XCDs (each with its own L2). This maps

@@ -164,6 +164,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
 
   // Epilogue. In a 32x32 accumulator block, lane l holds column l%32 of rows
   // 8*(r/4) + 4*(l/32) + r%4 for r = 0..15.
+  [[maybe_unused]] float amax = 0.f;
 #pragma unroll
   for (int a = 0; a < FM; ++a) {
 #pragma unroll
@@ -184,18 +185,29 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + wm * WTM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
         if (row >= M) continue;
-        const float v = acc[a][b][r] + bias;
+        const float v = (T::kBytes == 1 ? acc[a][b][r] * p.acc_scale : acc[a][b][r]) + bias;
         if constexpr (EPI == E_BIAS) {
           ((float*)p.out)[(int64_t)row * p.ldo + col] = v;
         } else if constexpr (EPI == E_RESID) {
           float* o = (float*)p.out + (int64_t)row * p.ldo + col;
           *o = *o + v;
         } else if constexpr (EPI == E_GELU) {
-          ((S*)p.out)[(int64_t)row * p.ldo + col] = (S)gelu_erf(v);
+          const float g = gelu_erf(v);
+          amax = fmaxf(amax, fabsf(g));
+          if constexpr (T::kBytes == 1)
+            ((S*)p.out)[(int64_t)row * p.ldo + col] = to_fp8(g * p.out_scale);
+          else
+            ((S*)p.out)[(int64_t)row * p.ldo + col] = (S)g;
         } else {
           qkv_base[(int64_t)row * p.dh] = (S)(v * qkv_scale);
         }
       }
+    }
+  }
+  if constexpr (EPI == E_GELU) {
+    if (p.amax) {
+      amax = wave_max(amax);
+      if (lane == 0) atomic_max_nonneg(p.amax, amax);
     }
   }
 }
@@ -211,7 +223,7 @@ constexpr GemmTile kTiles[] = {
 
 template <class T, int ALD, int EPI, int BM, int BN, int WM, int WN>
 hipError_t launch_t(const GemmArgs& p, hipStream_t s) {
-  constexpr int BK = (T::kBytes == 4) ? 32 : 64;
+  constexpr int BK = 128 / T::kBytes;  // 128 bytes of each row per k-tile
   if (p.Kp % BK != 0) return hipErrorInvalidValue;
   const int gm = (p.M + BM - 1) / BM, gn = (p.N + BN - 1) / BN;
   const int64_t grid = (int64_t)gm * gn;
@@ -254,6 +266,11 @@ hipError_t launch_gemm(Prec prec, ALoad aload, Epi epi, int tile, const GemmArgs
                        hipStream_t s) {
   if (prec == P_F32) return launch_prec<F32>(aload, epi, tile, p, s);
   if (prec == P_BF16) return launch_prec<BF16>(aload, epi, tile, p, s);
+  if (prec == P_FP8) {
+    // FP8 runs the two FFN products only (operands quantised by their producers).
+    if (aload == A_PLAIN && epi == E_GELU) return launch_tile<FP8, A_PLAIN, E_GELU>(tile, p, s);
+    if (aload == A_PLAIN && epi == E_RESID) return launch_tile<FP8, A_PLAIN, E_RESID>(tile, p, s);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -6,7 +6,7 @@
 
 namespace mlpf {
 
-enum Prec { P_F32 = 0, P_BF16 = 1 };
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
 
 // How the GEMM's A operand is produced while it is staged into LDS.
 enum ALoad {
@@ -33,6 +33,9 @@ struct GemmArgs {
   const int32_t* m_dev = nullptr;  // optional device count of live rows (rows beyond it are skipped)
   void* out = nullptr;
   int ldo = 0;
+  float acc_scale = 1.f;   // multiplies A W before the bias (FP8 dequantisation s_a * s_w)
+  float out_scale = 1.f;   // E_GELU into FP8: multiplies GELU(...) before rounding (1 / s_out)
+  float* amax = nullptr;   // E_GELU: optional running max |GELU(...)| (calibration; atomic max)
   // E_QKV
   void* q = nullptr;
   void* k = nullptr;
@@ -112,6 +115,8 @@ struct LayerNormArgs {
   const float* gamma = nullptr;
   const float* beta = nullptr;
   float eps = 1e-5f;
+  float out_scale = 1.f;   // FP8 output: multiplies the normalised value before rounding
+  float* amax = nullptr;   // optional running max |LN(x)| (calibration; atomic max)
 };
 hipError_t launch_layernorm(Prec prec, const LayerNormArgs& args, hipStream_t stream);
 

@@ -149,7 +149,8 @@ hipError_t launch_heads2(Prec prec, const Heads2Args& p, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// LayerNorm of FP32 rows into the operand type of the next product (pre-LN transformer block).
+// LayerNorm of FP32 rows into the operand type of the next product (pre-LN transformer block):
+// FP32, BF16, or FP8 E4M3 after multiplying by out_scale (the inverse per-tensor scale).
 // One wave per row; the row stays in registers (d <= 1024: up to 4 float4 per lane), statistics
 // in FP32 with two passes over the registers (mean, then mean squared deviation = biased
 // variance).
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const LayerNormArgs p) {
   }
   const float rs = 1.0f / sqrtf(wave_sum(q) / (float)p.d + p.eps);
   S* y = (S*)p.y + (int64_t)row * p.d;
+  float amax = 0.f;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int c = lane + 64 * t;
@@ -190,10 +192,18 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const LayerNormArgs p) {
     const float o1 = (v[t][1] - mu) * rs * g[1] + b[1];
     const float o2 = (v[t][2] - mu) * rs * g[2] + b[2];
     const float o3 = (v[t][3] - mu) * rs * g[3] + b[3];
+    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(o0), fabsf(o1)), fmaxf(fabsf(o2), fabsf(o3))));
     if constexpr (sizeof(S) == 4)
       *(f32x4*)(y + 4 * c) = f32x4{o0, o1, o2, o3};
-    else
+    else if constexpr (sizeof(S) == 2)
       *(u32x2*)(y + 4 * c) = pack_bf16x4(o0, o1, o2, o3);
+    else
+      *(uint32_t*)(y + 4 * c) = pack_fp8x4(o0 * p.out_scale, o1 * p.out_scale, o2 * p.out_scale,
+                                           o3 * p.out_scale);
+  }
+  if (p.amax) {
+    amax = wave_max(amax);
+    if (lane == 0) atomic_max_nonneg(p.amax, amax);
   }
 }
 
@@ -213,7 +223,9 @@ hipError_t launch_ln_t(const LayerNormArgs& p, hipStream_t s) {
 hipError_t launch_layernorm(Prec prec, const LayerNormArgs& p, hipStream_t s) {
   if (p.rows <= 0) return hipSuccess;
   if (p.d % 4 != 0 || p.d > 1024) return hipErrorInvalidValue;
-  return prec == P_F32 ? launch_ln_t<float>(p, s) : launch_ln_t<__bf16>(p, s);
+  if (prec == P_F32) return launch_ln_t<float>(p, s);
+  if (prec == P_BF16) return launch_ln_t<__bf16>(p, s);
+  return launch_ln_t<uint8_t>(p, s);
 }
 
 // ---------------------------------------------------------------------------------------------

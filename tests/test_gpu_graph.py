@@ -1,0 +1,50 @@
+"""A captured forward (mlpf_graph_create) replays any batch that fits its capacity and gives the
+same bits as the eager call; replays are repeated with eager work and synchronisations between."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_graph_replay_matches_eager(prec):
+    import torch
+    from paper_2601_17554_amd import binding as B
+
+    cfg = synth.FULL
+    m = B.Model(cfg, synth.make_weights(cfg, 21, sharpen=4.0), prec)
+    batches = [synth.pack([synth.make_event(50 + i, n) for i, n in enumerate(sizes)])
+               for sizes in ([700, 31, 1200], [5], [64, 900, 2, 300, 1000, 77])]
+    e_cap = 8
+    t_cap = max(p.total_rows for p in batches) + 100
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        x = torch.zeros(t_cap, cfg.n_features, device="cuda")
+        rs = torch.zeros(e_cap + 1, dtype=torch.int32, device="cuda")
+        nv = torch.zeros(e_cap, dtype=torch.int32, device="cuda")
+        batch = B.Batch(rs, nv, e_cap, t_cap, synth.MAX_SEQLEN)
+        out = m.outputs(t_cap)
+        ws = m.workspace(t_cap, e_cap)
+        graph = B.Graph(m, x, batch, out, ws, s)
+    s.synchronize()
+    for rep in range(2):
+        for pk in batches:
+            # eager reference on exactly this batch (also the eager work between replays)
+            ref = m.reconstruct(torch.from_numpy(pk.x).cuda(), B.Batch.from_host(pk.row_start, pk.n_valid))
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                t, e = pk.total_rows, pk.n_events
+                x[:t].copy_(torch.from_numpy(pk.x))
+                rs_h = np.full(e_cap + 1, t, dtype=np.int32)
+                rs_h[: e + 1] = pk.row_start
+                nv_h = np.zeros(e_cap, dtype=np.int32)
+                nv_h[:e] = pk.n_valid
+                rs.copy_(torch.from_numpy(rs_h))
+                nv.copy_(torch.from_numpy(nv_h))
+                graph.launch()
+            s.synchronize()
+            for k in ("logits", "reg", "cls"):
+                got, want = out[k][:t].cpu().numpy(), ref[k].cpu().numpy()
+                np.testing.assert_array_equal(got, want, err_msg=f"rep {rep} batch {e} events {k}")
