@@ -78,16 +78,20 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
   for (int c = 0; c < QKG; ++c)
     qr[c] = q_ok ? *(const u32x4*)(qb + (int64_t)qi * DH + (2 * c + h) * E) : u32x4{0, 0, 0, 0};
 
+  // K and V of this (event, head) are one contiguous run of n rows each. Buffer loads with the run's
+  // byte length as the bound return zeros past the last key, so the tile loads need no masks.
+  const int run_bytes = n * DH * SZ;
+  const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc((void*)kb, (short)0, run_bytes, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc((void*)vb, (short)0, run_bytes, kBufferWord3);
   u32x4 rk[PT], rv[PT];
   auto load = [&](int kt0) {
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
       const int c = t * NT + tid;
       const int r = c / CH_ROW, ch = c % CH_ROW;
-      const bool ok = (NCH % NT == 0 || c < NCH) && kt0 + r < n;
-      const int64_t off = (int64_t)(kt0 + r) * DH + ch * E;
-      rk[t] = ok ? *(const u32x4*)(kb + off) : u32x4{0, 0, 0, 0};
-      rv[t] = ok ? *(const u32x4*)(vb + off) : u32x4{0, 0, 0, 0};
+      const int off = (kt0 + r) * (DH * SZ) + ch * 16;
+      rk[t] = __builtin_amdgcn_raw_buffer_load_b128(krs, off, 0, 0);
+      rv[t] = __builtin_amdgcn_raw_buffer_load_b128(vrs, off, 0, 0);
     }
   };
   auto store = [&](int buf) {
@@ -110,10 +114,12 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
     }
   };
 
-  // Per-lane softmax state: m = running maximum of the scores (log2 units), l = partial row sum
-  // over this lane's keys (the two lane halves are added at the end), oacc = O^T.
-  float m_run = -INFINITY, l_run = 0.f;
+  // Per-lane softmax state: m = running maximum of the scores (log2 units; BF16: the offset the
+  // scores are computed against), l = partial row sum over this lane's keys (the two lane halves
+  // are added at the end), oacc = O^T.
+  float m_run = kBF16 ? 0.f : -INFINITY, l_run = 0.f;
   f32x16 oacc = f32x16{};
+  [[maybe_unused]] u32x4 qaug = u32x4{0, 0, 0, 0};  // BF16: split of -m_run (lanes of half 0)
   // BF16: the constant A operand (1, 1, 1, 0, ...) in the lanes of k-slots 0..7 (half 0).
   [[maybe_unused]] const u32x4 kaug = h == 0 ? u32x4{0x3F803F80u, 0x3F80u, 0, 0} : u32x4{0, 0, 0, 0};
 
@@ -123,47 +129,21 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
     const char* Ks = smem + (t & 1) * (K_BYTES + V_BYTES);
     const char* Vs = Ks + K_BYTES;
 
-    // S^T = K Q^T for each 32-key block.
+    // S^T = K Q^T for each 32-key block (BF16: minus the current offset m, folded into the
+    // product as an extra k-group: constant rows (1, 1, 1) times the exact 3-term bf16 split of -m).
     u32x4 ka[NB][QKG];
     f32x16 s[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       s[b] = f32x16{};
+      if constexpr (kBF16) mma_kg<T>(kaug, qaug, s[b]);
 #pragma unroll
       for (int c = 0; c < QKG; ++c) {
         ka[b][c] = *(const u32x4*)(Ks + (32 * b + i) * KRS + (2 * c + h) * 16);
         mma_kg<T>(ka[b][c], qr[c], s[b]);
       }
     }
-    if constexpr (kMasked) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-          if (kt0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3) >= n) s[b][r] = -INFINITY;
-    }
-    float mx = -INFINITY;
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[b][r]);
-    mx = fmaxf(mx, other_half(mx));  // finite: every tile holds a valid key
-    const float m_new = fmaxf(m_run, mx);
-    const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);  // 0 on the first tile
-    m_run = m_new;
-
-    if constexpr (kBF16) {
-      // S' = S - m: the products are recomputed with the offset folded in as an extra k-group
-      // (constant rows (1, 1, 1) times the exact 3-term split of -m): MFMA work instead of one
-      // VALU subtraction per score. Masked keys are re-masked.
-      const u32x4 qaug = h == 0 ? neg_split3(m_new) : u32x4{0, 0, 0, 0};
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        s[b] = f32x16{};
-        mma_kg<T>(kaug, qaug, s[b]);
-#pragma unroll
-        for (int c = 0; c < QKG; ++c) mma_kg<T>(ka[b][c], qr[c], s[b]);
-      }
+    auto mask = [&]() {
       if constexpr (kMasked) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -171,9 +151,36 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
           for (int r = 0; r < 16; ++r)
             if (kt0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3) >= n) s[b][r] = -INFINITY;
       }
-      l_run *= alpha;
+    };
+    mask();
+    float mx = -INFINITY;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) oacc[r] *= alpha;
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[b][r]);
+    mx = fmaxf(mx, other_half(mx));  // finite: every tile holds a valid key
+
+    if constexpr (kBF16) {
+      // mx is relative to the offset. The maximum grows on few tiles after the first: only then
+      // move the offset, recompute the scores against it (MFMA work, not a VALU subtraction per
+      // score) and rescale O and l; the branch is wave-uniform.
+      if (t == 0 || __any(mx > 0.f)) {
+        const float m_new = (t == 0) ? m_run + mx : m_run + fmaxf(mx, 0.f);
+        const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);  // 0 on the first tile
+        m_run = m_new;
+        qaug = h == 0 ? neg_split3(m_new) : u32x4{0, 0, 0, 0};
+        l_run *= alpha;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) oacc[r] *= alpha;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          s[b] = f32x16{};
+          mma_kg<T>(kaug, qaug, s[b]);
+#pragma unroll
+          for (int c = 0; c < QKG; ++c) mma_kg<T>(ka[b][c], qr[c], s[b]);
+        }
+        mask();
+      }
       // P = exp2(S'), packed to bf16 for the PV product; the row sum adds the packed values
       // (v_dot2_f32_bf16 against (1, 1)), i.e. exactly the weights the product uses. The dot is
       // written as inline assembly: with this compiler the __builtin_amdgcn_fdot2_f32_bf16 form
@@ -209,8 +216,11 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
         }
       }
     } else {
-      // FP32: P = exp2(S - m); the tile's PV product goes to a fresh partial first (shorter
-      // sequential addition chains over long events).
+      // FP32: exact running maximum, P = exp2(S - m); the tile's PV product goes to a fresh
+      // partial first (shorter sequential addition chains over long events).
+      const float m_new = fmaxf(m_run, mx);
+      const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);  // 0 on the first tile
+      m_run = m_new;
       float ls = 0.f;
 #pragma unroll
       for (int b = 0; b < NB; ++b)

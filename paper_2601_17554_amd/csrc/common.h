@@ -47,14 +47,33 @@ __device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float 
 
 constexpr float kLog2e = 1.4426950408889634f;
 
+// Fourth dword of a raw buffer resource on GFX9-family GPUs (gfx950): untyped 32-bit access,
+// bounds-checked against num_records (loads past it return zero).
+constexpr int kBufferWord3 = 0x00020000;
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
+// GELU(z) = z/2 (1 + erf(z / sqrt 2)), the exact (erf) form. erf is Abramowitz & Stegun's
+// formula 7.1.26 (Handbook of Mathematical Functions, 1964): for x >= 0,
+//   erf(x) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-x^2),  t = 1 / (1 + p x),
+// with |error| <= 1.5e-7, odd-extended to x < 0. Branch-free: one reciprocal, one exp2, five FMAs,
+// about half the issue slots of the library erff.
 __device__ __forceinline__ float gelu_erf(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+  const float x = z * 0.70710678118654752f;
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  float poly = fmaf(1.061405429f, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  poly *= t;
+  const float e = __builtin_amdgcn_exp2f(-(ax * ax) * 1.4426950408889634f);
+  const float erf_abs = fmaf(-poly, e, 1.0f);
+  return 0.5f * z * (1.0f + copysignf(erf_abs, x));
 }
 
 // Rounds 4 floats to bf16 (round to nearest even) and packs them into 2 dwords.

@@ -219,6 +219,8 @@ constexpr GemmTile kTiles[] = {
     {128, 64, 2, 2},
     {128, 128, 2, 2},
     {64, 128, 2, 2},
+    {256, 128, 2, 2},  // wave tile 128x64: fewer LDS bytes per MFMA
+    {128, 256, 2, 2},  // wave tile 64x128
 };
 
 template <class T, int ALD, int EPI, int BM, int BN, int WM, int WN>
@@ -241,6 +243,8 @@ hipError_t launch_tile(int tile, const GemmArgs& p, hipStream_t s) {
     case 1: return launch_t<T, ALD, EPI, 128, 64, 2, 2>(p, s);
     case 2: return launch_t<T, ALD, EPI, 128, 128, 2, 2>(p, s);
     case 3: return launch_t<T, ALD, EPI, 64, 128, 2, 2>(p, s);
+    case 4: return launch_t<T, ALD, EPI, 256, 128, 2, 2>(p, s);
+    case 5: return launch_t<T, ALD, EPI, 128, 256, 2, 2>(p, s);
     default: return hipErrorInvalidValue;
   }
 }
