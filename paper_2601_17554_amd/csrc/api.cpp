@@ -349,7 +349,8 @@ mlpf_status_t do_worklist(Ctx& cx) {
   a.n_events = cx.b->n_events;
   a.total_rows = cx.b->total_rows;
   a.max_seqlen = cx.b->max_seqlen;
-  a.q_tile = 32 * attn_tile(attn_tile_of(m)).waves;
+  const AttnTile at = attn_tile(attn_tile_of(m));
+  a.q_tile = 32 * at.waves * at.qb;
   a.n_heads = m->cfg.n_heads;
   a.cap_items = cx.w.cap_items;
   a.ev_start = (int32_t*)cx.p(cx.w.ev_start);

@@ -1,7 +1,8 @@
 // Masked variable-length multi-head self-attention with online softmax (paper Eq. 4, computed
 // exactly as the FlashAttention kernel the paper uses does: tiled, never materialising A).
 //
-// One workgroup = one work item (event, head, block of 32*NW queries); each wave owns 32 queries.
+// One workgroup = one work item (event, head, block of 32*NW*QB queries); each wave owns QB blocks
+// of 32 queries, which share every K and V fragment the wave reads from LDS.
 // Keys are the event's own valid elements only, so events never see each other and padding rows
 // are never keys. K and V tiles of KT keys are staged through LDS (double buffered) and shared by
 // the workgroup's waves; V is transposed while it is written to LDS.
@@ -40,7 +41,7 @@ __device__ __forceinline__ u32x4 neg_split3(float x) {
   return u32x4{a | (b << 16), c, 0, 0};
 }
 
-template <class T, int DH, int NW, int KT>
+template <class T, int DH, int NW, int KT, int QB>
 __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
   using S = typename T::storage;
   constexpr int NT = NW * 64;
@@ -66,17 +67,22 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane & 31, h = lane >> 5;
-  const int qi = qtile * (32 * NW) + wave * 32 + i;
-  const bool q_ok = qi < n;
 
   const S* qb = (const S*)p.q + (int64_t)head * p.hstride + (int64_t)start * DH;
   const S* kb = (const S*)p.k + (int64_t)head * p.hstride + (int64_t)start * DH;
   const S* vb = (const S*)p.v + (int64_t)head * p.hstride + (int64_t)start * DH;
 
-  u32x4 qr[QKG];
+  // This wave's QB blocks of 32 queries.
+  int qi[QB];
+  u32x4 qr[QB][QKG];
 #pragma unroll
-  for (int c = 0; c < QKG; ++c)
-    qr[c] = q_ok ? *(const u32x4*)(qb + (int64_t)qi * DH + (2 * c + h) * E) : u32x4{0, 0, 0, 0};
+  for (int j = 0; j < QB; ++j) {
+    qi[j] = (qtile * NW + wave) * (32 * QB) + 32 * j + i;
+#pragma unroll
+    for (int c = 0; c < QKG; ++c)
+      qr[j][c] = qi[j] < n ? *(const u32x4*)(qb + (int64_t)qi[j] * DH + (2 * c + h) * E)
+                           : u32x4{0, 0, 0, 0};
+  }
 
   // K and V of this (event, head) are one contiguous run of n rows each. Buffer loads with the run's
   // byte length as the bound return zeros past the last key, so the tile loads need no masks.
@@ -114,12 +120,19 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
     }
   };
 
-  // Per-lane softmax state: m = running maximum of the scores (log2 units; BF16: the offset the
-  // scores are computed against), l = partial row sum over this lane's keys (the two lane halves
-  // are added at the end), oacc = O^T.
-  float m_run = kBF16 ? 0.f : -INFINITY, l_run = 0.f;
-  f32x16 oacc = f32x16{};
-  [[maybe_unused]] u32x4 qaug = u32x4{0, 0, 0, 0};  // BF16: split of -m_run (lanes of half 0)
+  // Per-lane softmax state of each query block: m = running maximum of the scores (log2 units;
+  // BF16: the offset the scores are computed against), l = partial row sum over this lane's keys
+  // (the two lane halves are added at the end), oacc = O^T.
+  float m_run[QB], l_run[QB];
+  f32x16 oacc[QB];
+  [[maybe_unused]] u32x4 qaug[QB];  // BF16: split of -m_run (lanes of half 0)
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    m_run[j] = kBF16 ? 0.f : -INFINITY;
+    l_run[j] = 0.f;
+    oacc[j] = f32x16{};
+    qaug[j] = u32x4{0, 0, 0, 0};
+  }
   // BF16: the constant A operand (1, 1, 1, 0, ...) in the lanes of k-slots 0..7 (half 0).
   [[maybe_unused]] const u32x4 kaug = h == 0 ? u32x4{0x3F803F80u, 0x3F80u, 0, 0} : u32x4{0, 0, 0, 0};
 
@@ -129,121 +142,130 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
     const char* Ks = smem + (t & 1) * (K_BYTES + V_BYTES);
     const char* Vs = Ks + K_BYTES;
 
-    // S^T = K Q^T for each 32-key block (BF16: minus the current offset m, folded into the
-    // product as an extra k-group: constant rows (1, 1, 1) times the exact 3-term bf16 split of -m).
+    // K fragments of the tile, shared by the wave's query blocks.
     u32x4 ka[NB][QKG];
-    f32x16 s[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      s[b] = f32x16{};
-      if constexpr (kBF16) mma_kg<T>(kaug, qaug, s[b]);
-#pragma unroll
-      for (int c = 0; c < QKG; ++c) {
-        ka[b][c] = *(const u32x4*)(Ks + (32 * b + i) * KRS + (2 * c + h) * 16);
-        mma_kg<T>(ka[b][c], qr[c], s[b]);
-      }
-    }
-    auto mask = [&]() {
-      if constexpr (kMasked) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            if (kt0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3) >= n) s[b][r] = -INFINITY;
-      }
-    };
-    mask();
-    float mx = -INFINITY;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[b][r]);
-    mx = fmaxf(mx, other_half(mx));  // finite: every tile holds a valid key
+      for (int c = 0; c < QKG; ++c) ka[b][c] = *(const u32x4*)(Ks + (32 * b + i) * KRS + (2 * c + h) * 16);
+
+    // S^T = K Q^T for each query block and 32-key block (BF16: minus the current offset m, folded
+    // into the product as an extra k-group: constant rows (1, 1, 1) times the exact 3-term bf16
+    // split of -m).
+    f32x16 s[QB][NB];
+    auto scores = [&](const int j) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        s[j][b] = f32x16{};
+        if constexpr (kBF16) mma_kg<T>(kaug, qaug[j], s[j][b]);
+#pragma unroll
+        for (int c = 0; c < QKG; ++c) mma_kg<T>(ka[b][c], qr[j][c], s[j][b]);
+        if constexpr (kMasked) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            if (kt0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3) >= n) s[j][b][r] = -INFINITY;
+        }
+      }
+    };
+    float alpha[QB];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      scores(j);
+      float mx = -INFINITY;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[j][b][r]);
+      mx = fmaxf(mx, other_half(mx));  // finite: every tile holds a valid key
+      if constexpr (kBF16) {
+        // mx is relative to the offset. The maximum grows on few tiles after the first: only then
+        // move the offset, recompute the scores against it (MFMA work, not a VALU subtraction per
+        // score) and rescale O and l; the branch is wave-uniform.
+        alpha[j] = 1.f;
+        if (t == 0 || __any(mx > 0.f)) {
+          const float m_new = (t == 0) ? m_run[j] + mx : m_run[j] + fmaxf(mx, 0.f);
+          const float a = __builtin_amdgcn_exp2f(m_run[j] - m_new);  // 0 on the first tile
+          m_run[j] = m_new;
+          qaug[j] = h == 0 ? neg_split3(m_new) : u32x4{0, 0, 0, 0};
+          l_run[j] *= a;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) oacc[j][r] *= a;
+          scores(j);
+        }
+      } else {
+        const float m_new = fmaxf(m_run[j], mx);
+        alpha[j] = __builtin_amdgcn_exp2f(m_run[j] - m_new);  // 0 on the first tile
+        m_run[j] = m_new;
+      }
+    }
 
     if constexpr (kBF16) {
-      // mx is relative to the offset. The maximum grows on few tiles after the first: only then
-      // move the offset, recompute the scores against it (MFMA work, not a VALU subtraction per
-      // score) and rescale O and l; the branch is wave-uniform.
-      if (t == 0 || __any(mx > 0.f)) {
-        const float m_new = (t == 0) ? m_run + mx : m_run + fmaxf(mx, 0.f);
-        const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);  // 0 on the first tile
-        m_run = m_new;
-        qaug = h == 0 ? neg_split3(m_new) : u32x4{0, 0, 0, 0};
-        l_run *= alpha;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) oacc[r] *= alpha;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          s[b] = f32x16{};
-          mma_kg<T>(kaug, qaug, s[b]);
-#pragma unroll
-          for (int c = 0; c < QKG; ++c) mma_kg<T>(ka[b][c], qr[c], s[b]);
-        }
-        mask();
-      }
-      // P = exp2(S'), packed to bf16 for the PV product; the row sum adds the packed values
-      // (v_dot2_f32_bf16 against (1, 1)), i.e. exactly the weights the product uses. The dot is
-      // written as inline assembly: with this compiler the __builtin_amdgcn_fdot2_f32_bf16 form
-      // (selected as v_dot2c_f32_bf16 with a literal) read the first dword of the packed operand
-      // for all four dwords, which a GPU test caught as l four times too large.
-      uint32_t ones = 0x3F803F80u;
-      asm("" : "+v"(ones));
+      // P = exp2(S') in FP32 (summed into l), packed to bf16 for the PV product.
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          u32x4 pb;
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const u32x2 pk = pack_bf16x4(__builtin_amdgcn_exp2f(s[b][8 * c + 4 * q + 0]),
-                                         __builtin_amdgcn_exp2f(s[b][8 * c + 4 * q + 1]),
-                                         __builtin_amdgcn_exp2f(s[b][8 * c + 4 * q + 2]),
-                                         __builtin_amdgcn_exp2f(s[b][8 * c + 4 * q + 3]));
-            pb[2 * q] = pk[0];
-            pb[2 * q + 1] = pk[1];
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            asm("v_dot2_f32_bf16 %0, %1, %2, %0" : "+v"(l_run) : "v"(pb[q]), "v"(ones));
-          // O^T += V^T P^T: row dh = l%32 of V^T, keys matching the P^T register order.
+          // O^T += V^T P^T: row dh = l%32 of V^T, keys matching the P^T register order; the V^T
+          // fragment is shared by the query blocks.
           u32x4 va = u32x4{0, 0, 0, 0};
           if (i < DH) {
             const u32x2 v0 = *(const u32x2*)(Vs + i * VRS + (32 * b + 16 * c + 4 * h) * 2);
             const u32x2 v1 = *(const u32x2*)(Vs + i * VRS + (32 * b + 16 * c + 8 + 4 * h) * 2);
             va = u32x4{v0[0], v0[1], v1[0], v1[1]};
           }
-          mma_kg<T>(va, pb, oacc);
+#pragma unroll
+          for (int j = 0; j < QB; ++j) {
+            u32x4 pb;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const float e0 = __builtin_amdgcn_exp2f(s[j][b][8 * c + 4 * q + 0]);
+              const float e1 = __builtin_amdgcn_exp2f(s[j][b][8 * c + 4 * q + 1]);
+              const float e2 = __builtin_amdgcn_exp2f(s[j][b][8 * c + 4 * q + 2]);
+              const float e3 = __builtin_amdgcn_exp2f(s[j][b][8 * c + 4 * q + 3]);
+              l_run[j] += (e0 + e1) + (e2 + e3);
+              const u32x2 pk = pack_bf16x4(e0, e1, e2, e3);
+              pb[2 * q] = pk[0];
+              pb[2 * q + 1] = pk[1];
+            }
+            mma_kg<T>(va, pb, oacc[j]);
+          }
         }
       }
     } else {
-      // FP32: exact running maximum, P = exp2(S - m); the tile's PV product goes to a fresh
-      // partial first (shorter sequential addition chains over long events).
-      const float m_new = fmaxf(m_run, mx);
-      const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);  // 0 on the first tile
-      m_run = m_new;
-      float ls = 0.f;
+      // FP32: P = exp2(S - m); the tile's PV product goes to a fresh partial first (shorter
+      // sequential addition chains over long events).
+      f32x16 pv[QB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+      for (int j = 0; j < QB; ++j) {
+        float ls = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float e = __builtin_amdgcn_exp2f(s[b][r] - m_new);
-          s[b][r] = e;
-          ls += e;
-        }
-      l_run = l_run * alpha + ls;
-      f32x16 pv = f32x16{};
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float e = __builtin_amdgcn_exp2f(s[j][b][r] - m_run[j]);
+            s[j][b][r] = e;
+            ls += e;
+          }
+        l_run[j] = l_run[j] * alpha[j] + ls;
+        pv[j] = f32x16{};
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const u32x4 va = (i < DH) ? *(const u32x4*)(Vs + i * VRS + (32 * b + 8 * c + 4 * h) * 4)
                                     : u32x4{0, 0, 0, 0};
-          const u32x4 pb = {__float_as_uint(s[b][4 * c + 0]), __float_as_uint(s[b][4 * c + 1]),
-                            __float_as_uint(s[b][4 * c + 2]), __float_as_uint(s[b][4 * c + 3])};
-          mma_kg<T>(va, pb, pv);
+#pragma unroll
+          for (int j = 0; j < QB; ++j) {
+            const u32x4 pb = {__float_as_uint(s[j][b][4 * c + 0]), __float_as_uint(s[j][b][4 * c + 1]),
+                              __float_as_uint(s[j][b][4 * c + 2]), __float_as_uint(s[j][b][4 * c + 3])};
+            mma_kg<T>(va, pb, pv[j]);
+          }
         }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) oacc[r] = oacc[r] * alpha + pv[r];
+      for (int j = 0; j < QB; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) oacc[j][r] = oacc[j][r] * alpha[j] + pv[j][r];
     }
   };
 
@@ -264,18 +286,21 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
   if (nfull < nkt) tile(nfull, std::true_type{});
 
   // O = O^T / l. Lane l holds dh = 8c + 4*(l/32) + (0..3) of query l%32 in registers 4c..4c+3.
-  const float l_tot = l_run + other_half(l_run);
-  if (q_ok) {
-    const float inv = 1.0f / l_tot;
-    S* orow = (S*)p.o + (int64_t)(start + qi) * p.d + head * DH;
 #pragma unroll
-    for (int c = 0; c < DH / 8; ++c) {
-      const float a0 = oacc[4 * c] * inv, a1 = oacc[4 * c + 1] * inv;
-      const float a2 = oacc[4 * c + 2] * inv, a3 = oacc[4 * c + 3] * inv;
-      if constexpr (SZ == 4) {
-        *(f32x4*)(orow + 8 * c + 4 * h) = f32x4{a0, a1, a2, a3};
-      } else {
-        *(u32x2*)(orow + 8 * c + 4 * h) = pack_bf16x4(a0, a1, a2, a3);
+  for (int j = 0; j < QB; ++j) {
+    const float l_tot = l_run[j] + other_half(l_run[j]);
+    if (qi[j] < n) {
+      const float inv = 1.0f / l_tot;
+      S* orow = (S*)p.o + (int64_t)(start + qi[j]) * p.d + head * DH;
+#pragma unroll
+      for (int c = 0; c < DH / 8; ++c) {
+        const float a0 = oacc[j][4 * c] * inv, a1 = oacc[j][4 * c + 1] * inv;
+        const float a2 = oacc[j][4 * c + 2] * inv, a3 = oacc[j][4 * c + 3] * inv;
+        if constexpr (SZ == 4) {
+          *(f32x4*)(orow + 8 * c + 4 * h) = f32x4{a0, a1, a2, a3};
+        } else {
+          *(u32x2*)(orow + 8 * c + 4 * h) = pack_bf16x4(a0, a1, a2, a3);
+        }
       }
     }
   }
@@ -284,26 +309,30 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
 namespace {
 
 constexpr AttnTile kTiles[] = {
-    {4, 64},
-    {2, 64},
-    {4, 32},
-    {1, 64},
+    {4, 64, 1},
+    {2, 64, 1},
+    {4, 32, 1},
+    {1, 64, 1},
+    {2, 64, 2},
+    {4, 64, 2},
 };
 
-template <class T, int DH, int NW, int KT>
+template <class T, int DH, int NW, int KT, int QB>
 hipError_t launch_t(const AttnArgs& p, hipStream_t s) {
   if (p.cap_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL((attn_kernel<T, DH, NW, KT>), dim3(p.cap_items), dim3(NW * 64), 0, s, p);
+  hipLaunchKernelGGL((attn_kernel<T, DH, NW, KT, QB>), dim3(p.cap_items), dim3(NW * 64), 0, s, p);
   return hipGetLastError();
 }
 
 template <class T, int DH>
 hipError_t launch_dh(int tile, const AttnArgs& p, hipStream_t s) {
   switch (tile) {
-    case 0: return launch_t<T, DH, 4, 64>(p, s);
-    case 1: return launch_t<T, DH, 2, 64>(p, s);
-    case 2: return launch_t<T, DH, 4, 32>(p, s);
-    case 3: return launch_t<T, DH, 1, 64>(p, s);
+    case 0: return launch_t<T, DH, 4, 64, 1>(p, s);
+    case 1: return launch_t<T, DH, 2, 64, 1>(p, s);
+    case 2: return launch_t<T, DH, 4, 32, 1>(p, s);
+    case 3: return launch_t<T, DH, 1, 64, 1>(p, s);
+    case 4: return launch_t<T, DH, 2, 64, 2>(p, s);
+    case 5: return launch_t<T, DH, 4, 64, 2>(p, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -9,7 +9,7 @@
 // elements of A and W^T are staged through LDS (double buffered, one barrier per k-tile): the
 // next tile's global loads are issued before the current tile's MFMAs and written to LDS after
 // them. LDS rows are padded by 16 bytes so that the 32 rows read by one MFMA operand load fall
-// in different banks.
+// in different banks. The epilogue is staged through the same LDS (see below).
 #include "common.h"
 #include "kernels.h"
 
@@ -162,47 +162,86 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
     __syncthreads();
   }
 
-  // Epilogue. In a 32x32 accumulator block, lane l holds column l%32 of rows
-  // 8*(r/4) + 4*(l/32) + r%4 for r = 0..15.
+  // Epilogue, staged through LDS so that global memory sees whole 16-byte row chunks: the waves
+  // write bias + activation (FP32) into an LDS tile, then every thread moves 16-byte chunks of
+  // output rows (read-modify-write of h for the residual update). In a 32x32 accumulator block,
+  // lane l holds column l%32 of rows 8*(r/4) + 4*(l/32) + r%4 for r = 0..15. Tiles whose FP32
+  // image does not fit the LDS of the main loop are staged in two passes (one per wave row).
+  constexpr int SRS = BN * 4 + 16;                       // staging row stride (bytes)
+  constexpr int PASSES = (BM * SRS <= 2 * (A_BYTES + B_BYTES)) ? 1 : WM;
+  constexpr int PROWS = BM / PASSES;                     // rows staged per pass
+  static_assert(PROWS * SRS <= 2 * (A_BYTES + B_BYTES), "epilogue staging does not fit");
+  constexpr int OSZ = (EPI == E_BIAS || EPI == E_RESID) ? 4 : (int)sizeof(S);
+  constexpr int EO = 16 / OSZ;                           // output elements per 16-byte chunk
   [[maybe_unused]] float amax = 0.f;
 #pragma unroll
-  for (int a = 0; a < FM; ++a) {
+  for (int pass = 0; pass < PASSES; ++pass) {
+    if (PASSES == 1 || wm == pass) {
 #pragma unroll
-    for (int b = 0; b < FN; ++b) {
-      const int col = n0 + wn * WTN + b * 32 + i;
-      if (col >= p.N) continue;
-      const float bias = p.bias ? p.bias[col] : 0.f;
-      [[maybe_unused]] S* qkv_base = nullptr;
-      [[maybe_unused]] float qkv_scale = 1.f;
-      if constexpr (EPI == E_QKV) {
-        const int which = col / p.d, rem = col % p.d;
-        const int hh = rem / p.dh, cc = rem % p.dh;
-        S* base = (S*)(which == 0 ? p.q : which == 1 ? p.k : p.v);
-        qkv_base = base + (int64_t)hh * p.hstride + cc;
-        qkv_scale = which == 0 ? p.q_scale : 1.f;
-      }
+      for (int a = 0; a < FM; ++a) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm * WTM + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (row >= M) continue;
-        const float v = (T::kBytes == 1 ? acc[a][b][r] * p.acc_scale : acc[a][b][r]) + bias;
-        if constexpr (EPI == E_BIAS) {
-          ((float*)p.out)[(int64_t)row * p.ldo + col] = v;
-        } else if constexpr (EPI == E_RESID) {
-          float* o = (float*)p.out + (int64_t)row * p.ldo + col;
-          *o = *o + v;
-        } else if constexpr (EPI == E_GELU) {
-          const float g = gelu_erf(v);
-          amax = fmaxf(amax, fabsf(g));
-          if constexpr (T::kBytes == 1)
-            ((S*)p.out)[(int64_t)row * p.ldo + col] = to_fp8(g * p.out_scale);
-          else
-            ((S*)p.out)[(int64_t)row * p.ldo + col] = (S)g;
-        } else {
-          qkv_base[(int64_t)row * p.dh] = (S)(v * qkv_scale);
+        for (int b = 0; b < FN; ++b) {
+          const int lcol = wn * WTN + b * 32 + i;
+          const int col = n0 + lcol;
+          const float bias = (p.bias && col < p.N) ? p.bias[col] : 0.f;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int lrow = (PASSES == 1 ? wm * WTM : 0) + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            float v = (T::kBytes == 1 ? acc[a][b][r] * p.acc_scale : acc[a][b][r]) + bias;
+            if constexpr (EPI == E_GELU) {
+              v = gelu_erf(v);
+              if (m0 + pass * PROWS + lrow < M && col < p.N) amax = fmaxf(amax, fabsf(v));
+            }
+            *(float*)(smem + lrow * SRS + lcol * 4) = v;
+          }
         }
       }
     }
+    __syncthreads();
+    constexpr int CPR = BN / EO;                         // chunks per staged row
+    for (int c = tid; c < PROWS * CPR; c += NT) {
+      const int lrow = c / CPR, lc = (c % CPR) * EO;
+      const int row = m0 + pass * PROWS + lrow, col = n0 + lc;
+      if (row >= M || col >= p.N) continue;
+      const float* src = (const float*)(smem + lrow * SRS + lc * 4);
+      if constexpr (EPI == E_BIAS || EPI == E_RESID) {
+        f32x4 v = *(const f32x4*)src;
+        f32x4* dst = (f32x4*)((float*)p.out + (int64_t)row * p.ldo + col);
+        if constexpr (EPI == E_RESID) v += *dst;
+        *dst = v;
+      } else {
+        float qs = 1.f;
+        S* dst;
+        if constexpr (EPI == E_QKV) {
+          const int which = col / p.d, rem = col % p.d;
+          const int hh = rem / p.dh, cc = rem % p.dh;
+          dst = (S*)(which == 0 ? p.q : which == 1 ? p.k : p.v) + (int64_t)hh * p.hstride +
+                (int64_t)row * p.dh + cc;
+          qs = which == 0 ? p.q_scale : 1.f;
+        } else {
+          dst = (S*)p.out + (int64_t)row * p.ldo + col;
+        }
+        if constexpr (sizeof(S) == 4) {
+          const f32x4 v = *(const f32x4*)src;
+          *(f32x4*)dst = v * qs;
+        } else if constexpr (sizeof(S) == 2) {
+          const f32x4 v0 = *(const f32x4*)src, v1 = *(const f32x4*)(src + 4);
+          const u32x2 lo = pack_bf16x4(v0[0] * qs, v0[1] * qs, v0[2] * qs, v0[3] * qs);
+          const u32x2 hi = pack_bf16x4(v1[0] * qs, v1[1] * qs, v1[2] * qs, v1[3] * qs);
+          *(u32x4*)dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        } else {
+          u32x4 o;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const f32x4 v = *(const f32x4*)(src + 4 * q);
+            o[q] = pack_fp8x4(v[0] * p.out_scale, v[1] * p.out_scale, v[2] * p.out_scale,
+                              v[3] * p.out_scale);
+          }
+          *(u32x4*)dst = o;
+        }
+      }
+    }
+    if (PASSES > 1 && pass + 1 < PASSES) __syncthreads();
   }
   if constexpr (EPI == E_GELU) {
     if (p.amax) {
@@ -226,7 +265,7 @@ constexpr GemmTile kTiles[] = {
 template <class T, int ALD, int EPI, int BM, int BN, int WM, int WN>
 hipError_t launch_t(const GemmArgs& p, hipStream_t s) {
   constexpr int BK = 128 / T::kBytes;  // 128 bytes of each row per k-tile
-  if (p.Kp % BK != 0) return hipErrorInvalidValue;
+  if (p.Kp % BK != 0 || p.N % 16 != 0) return hipErrorInvalidValue;
   const int gm = (p.M + BM - 1) / BM, gn = (p.N + BN - 1) / BN;
   const int64_t grid = (int64_t)gm * gn;
   if (grid == 0) return hipSuccess;

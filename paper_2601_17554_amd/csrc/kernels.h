@@ -70,8 +70,9 @@ struct AttnArgs {
   int cap_items = 0;
 };
 struct AttnTile {
-  int waves;  // queries per work item = 32 * waves
+  int waves;  // waves per workgroup
   int kt;     // keys per LDS tile
+  int qb;     // 32-query blocks per wave; queries per work item = 32 * waves * qb
 };
 int attn_num_tiles();
 AttnTile attn_tile(int id);
