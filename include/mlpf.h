@@ -187,10 +187,11 @@ mlpf_status_t mlpf_profiler_read(mlpf_model_t model, int kernel_class, double* t
 /* Launch-shape choices. Each product of the forward pass (mlpf_op_t) runs with one of a fixed set
  * of tile shapes; by default a size-based rule picks it per call. mlpf_tune_set pins op to tile
  * (0 <= tile < mlpf_tune_count(op)) or restores the rule (tile = -1); this is how the autotuner
- * stores its choice. Tile shapes change speed only: every GEMM tile sums k in the same order, so
- * GEMM results are bitwise identical across tiles; attention tiles change the order of the online
- * softmax updates (results differ by rounding only). Not thread-safe against concurrent forward
- * calls on the same model. */
+ * stores its choice. Tile shapes change speed only: in BF16 and FP8 every GEMM tile sums k in the
+ * same order, so GEMM results are bitwise identical across tiles; in FP32 the k-tile length sets
+ * the grouping of the partial sums, so tiles with equal k-tile lengths agree bitwise and others to
+ * rounding. Attention tiles change the order of the softmax sums (results differ by rounding
+ * only). Not thread-safe against concurrent forward calls on the same model. */
 typedef enum {
   MLPF_OP_EMBED1 = 0, MLPF_OP_EMBED2 = 1, MLPF_OP_QKV = 2, MLPF_OP_OUTPROJ = 3,
   MLPF_OP_FFN1 = 4, MLPF_OP_FFN2 = 5, MLPF_OP_HEADS1 = 6, MLPF_OP_ATTENTION = 7,
@@ -199,6 +200,12 @@ typedef enum {
 int32_t mlpf_tune_count(int32_t op);
 mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile);
 int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule */
+/* Shape of tile `tile` of op, written to shape[6]: GEMM ops {rows, columns, wave rows, wave
+ * columns, bytes per operand row and k-tile, persistent (1) or one workgroup per tile (0)};
+ * MLPF_OP_ATTENTION {waves per workgroup, keys per LDS stage, 32-query blocks per wave, kernel
+ * kind (0: online softmax with running maxima, 1: BF16 score-bound offset; FP32 runs kind 0),
+ * 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
+mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);
 
 /* FP8 activation calibration for MLPF_BF16_FP8FFN. Runs the embedding and encoder of `model` (an
  * FP32 or BF16 model) on the batch and raises amax[2l] to max |LN2 output| and amax[2l+1] to

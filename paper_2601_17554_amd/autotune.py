@@ -3,9 +3,10 @@
 For one workload (model, device batch), every op's tile shapes (mlpf_tune_count) are timed with the
 library's HIP-event profiler while the other ops keep their current choice; the fastest shape that
 passes the correctness guard is pinned with mlpf_tune_set. The guard compares the final outputs of
-each candidate with the reference run: GEMM tiles must give bitwise identical outputs (every GEMM
-tile sums k in the same order), attention tiles must agree to a relative 1e-3 of the logits scale
-(they change only the order of the online-softmax updates). Choices are cached in a JSON file
+each candidate with the reference run: GEMM tiles must give bitwise identical outputs where the
+library guarantees it (BF16 and FP8 always; FP32 for equal k-tile lengths), and otherwise agree to
+the rounding level of the precision (relative to the output scale: 1e-4 in FP32, 2e-2 in BF16 and
+FP8), as attention tiles must (they change only the order and offsets of the softmax sums). Choices are cached in a JSON file
 (``MLPF_AUTOTUNE_CACHE``, default ``~/.cache/mlpf_autotune.json``) keyed by GPU architecture,
 precision, model sizes and the batch's size bucket.
 """
@@ -50,12 +51,12 @@ def _run(model, x, batch, ws, out, reps: int) -> Dict[str, float]:
     return {k: v[0] / reps for k, v in prof.items()}
 
 
-def _same(a: Dict[str, torch.Tensor], b: Dict[str, torch.Tensor], exact: bool) -> bool:
+def _same(a: Dict[str, torch.Tensor], b: Dict[str, torch.Tensor], exact: bool, tol: float) -> bool:
     if exact:
         return all(torch.equal(a[k], b[k]) for k in ("logits", "reg", "cls"))
     scale = max(float(a["logits"].abs().max()), 1e-6)
-    return float((a["logits"] - b["logits"]).abs().max()) <= 1e-3 * scale and \
-        float((a["reg"] - b["reg"]).abs().max()) <= 1e-3 * max(float(a["reg"].abs().max()), 1e-6)
+    return float((a["logits"] - b["logits"]).abs().max()) <= tol * scale and \
+        float((a["reg"] - b["reg"]).abs().max()) <= tol * max(float(a["reg"].abs().max()), 1e-6)
 
 
 def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Tensor] = None,
@@ -80,13 +81,16 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
     model.reconstruct(x, batch, ws=ws, out=out)
     torch.cuda.synchronize()
     ref = {k: v.clone() for k, v in out.items()}
+    ref_bkb = B.Model.tune_shape("qkv", 0)["bkb"]  # FP32: the size-based rule picks among tiles 0..2
     choice: Dict[str, int] = {}
     for op in B.OPS:
         best, best_t = None, float("inf")
         for tile in range(B.Model.tune_count(op)):
             model.tune_set(op, tile)
             t = _run(model, x, batch, ws, out, reps)[_CLASS[op]]
-            ok = _same(out, ref, exact=(op != "attention"))
+            exact = op != "attention" and (model.precision != "fp32" or
+                                           B.Model.tune_shape(op, tile)["bkb"] == ref_bkb)
+            ok = _same(out, ref, exact, 1e-4 if model.precision == "fp32" else 2e-2)
             if verbose:
                 print(f"autotune {op} tile {tile}: {t:.4f} ms {'ok' if ok else 'REJECTED'}", flush=True)
             if ok and t < best_t:

@@ -78,6 +78,7 @@ def load() -> ctypes.CDLL:
         "mlpf_tune_count": (i32, [i32]),
         "mlpf_tune_set": (st, [vp, i32, i32]),
         "mlpf_tune_get": (i32, [vp, i32]),
+        "mlpf_tune_shape": (st, [i32, i32, ctypes.POINTER(ctypes.c_int32)]),
         "mlpf_status_string": (ctypes.c_char_p, [st]),
         "mlpf_last_error": (ctypes.c_char_p, []),
     }
@@ -94,7 +95,7 @@ def exported_symbols() -> Sequence[str]:
             "mlpf_reconstruct_events", "mlpf_profiler_enable", "mlpf_profiler_read",
             "mlpf_attention_forward", "mlpf_calibrate_fp8", "mlpf_graph_create", "mlpf_graph_launch",
             "mlpf_graph_destroy", "mlpf_tune_count", "mlpf_tune_set", "mlpf_tune_get",
-            "mlpf_status_string", "mlpf_last_error")
+            "mlpf_tune_shape", "mlpf_status_string", "mlpf_last_error")
 
 
 PROF_CLASSES = ("embed", "qkv", "attention", "outproj", "ffn1", "ffn2", "heads", "worklist")
@@ -299,6 +300,16 @@ class Model:
     @staticmethod
     def tune_count(op: str) -> int:
         return int(load().mlpf_tune_count(OPS.index(op)))
+
+    @staticmethod
+    def tune_shape(op: str, tile: int) -> Dict[str, int]:
+        """Shape of one tile: GEMM ops {bm, bn, wm, wn, bkb, persist}; attention {waves, kt, qb,
+        kind}."""
+        v = (ctypes.c_int32 * 6)()
+        _check(load().mlpf_tune_shape(OPS.index(op), tile, v))
+        keys = (("waves", "kt", "qb", "kind") if op == "attention"
+                else ("bm", "bn", "wm", "wn", "bkb", "persist"))
+        return {k: int(v[i]) for i, k in enumerate(keys)}
 
     def workspace_bytes(self, total_rows: int, n_events: int) -> int:
         return int(load().mlpf_workspace_bytes(self.handle, total_rows, n_events))

@@ -188,7 +188,7 @@ namespace {
 
 // Workspace layout for a batch of T rows and E events.
 struct WsPlan {
-  size_t ev_start, ev_n, counters, items, q, k, v, o, y, u, h, total;
+  size_t ev_start, ev_n, counters, items, knorm, q, k, v, o, y, u, h, total;
   int cap_items;
 };
 
@@ -209,6 +209,7 @@ WsPlan plan_ws(const mlpf_model_s* m, int64_t T, int64_t E) {
   w.ev_n = take(E * 4);
   w.counters = take(16);
   w.items = take((size_t)w.cap_items * 8);
+  w.knorm = take((size_t)T * c.n_heads * 4);
   const size_t td = (size_t)T * c.d_model;
   w.q = take(td * eb);
   w.k = take(td * eb);
@@ -222,10 +223,13 @@ WsPlan plan_ws(const mlpf_model_s* m, int64_t T, int64_t E) {
   return w;
 }
 
-int pick_gemm_tile(int M, int N) {
+// Size-based default tile: enough workgroups to fill 256 CUs; BF16/FP8 take the 64-byte k-tile
+// shapes (more workgroups resident per CU).
+int pick_gemm_tile(int M, int N, Prec prec) {
   const double wg256 = 256.0;
-  if ((double)((M + 127) / 128) * ((N + 127) / 128) >= 2 * wg256) return 2;
-  if ((double)((M + 127) / 128) * ((N + 63) / 64) >= wg256) return 1;
+  const bool narrow = prec != P_F32;
+  if ((double)((M + 127) / 128) * ((N + 127) / 128) >= 2 * wg256) return narrow ? 6 : 2;
+  if ((double)((M + 127) / 128) * ((N + 63) / 64) >= wg256) return narrow ? 7 : 1;
   return 0;
 }
 
@@ -280,14 +284,18 @@ struct Ctx {
   void* p(size_t off) const { return ws + off; }
 };
 
+// Default attention tile: BF16 takes the score-bound kernel with 8 waves per workgroup.
+constexpr int kDefaultAttnTileBf16 = 10;
 int attn_tile_of(const mlpf_model_s* m) {
-  return m->tune[MLPF_OP_ATTENTION] >= 0 ? m->tune[MLPF_OP_ATTENTION] : 0;
+  if (m->tune[MLPF_OP_ATTENTION] >= 0) return m->tune[MLPF_OP_ATTENTION];
+  return m->kprec == P_BF16 ? kDefaultAttnTileBf16 : 0;
 }
 
 mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a, int prec = -1) {
   a.m_dev = cx.n_rows;
-  const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N);
-  HIP_TRY(launch_gemm(prec >= 0 ? (Prec)prec : cx.m->kprec, al, ep, tile, a, cx.s), "gemm launch");
+  const int pr = prec >= 0 ? prec : (int)cx.m->kprec;
+  const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N, (Prec)pr);
+  HIP_TRY(launch_gemm((Prec)pr, al, ep, tile, a, cx.s), "gemm launch");
   return MLPF_OK;
 }
 
@@ -384,8 +392,14 @@ mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const v
   at.ev_start = (const int32_t*)cx.p(cx.w.ev_start);
   at.ev_n = (const int32_t*)cx.p(cx.w.ev_n);
   at.cap_items = cx.w.cap_items;
+  const int tile = attn_tile_of(m);
   ProfScope prof(cx.m, MLPF_PROF_ATTENTION, cx.s);
-  HIP_TRY(launch_attention(m->kprec, attn_tile_of(m), at, cx.s), "attention launch");
+  if (m->kprec == P_BF16 && attn_tile(tile).kind == 1) {
+    float* kn = (float*)cx.p(cx.w.knorm);
+    HIP_TRY(launch_keynorm(k, kn, (int64_t)cx.b->total_rows * m->cfg.n_heads, m->dh, cx.s), "keynorm launch");
+    at.knorm = kn;
+  }
+  HIP_TRY(launch_attention(m->kprec, tile, at, cx.s), "attention launch");
   return MLPF_OK;
 }
 
@@ -846,6 +860,23 @@ mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile) {
 int32_t mlpf_tune_get(mlpf_model_t model, int32_t op) {
   if (!model || op < 0 || op >= MLPF_OP_COUNT) return -1;
   return model->tune[op];
+}
+
+mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape) {
+  if (!shape) return fail(MLPF_ERR_INVALID_ARG, "shape is NULL");
+  if (op < 0 || op >= MLPF_OP_COUNT) return fail(MLPF_ERR_INVALID_ARG, "op=%d out of range", op);
+  if (tile < 0 || tile >= mlpf_tune_count(op))
+    return fail(MLPF_ERR_INVALID_ARG, "tile=%d out of range for op %d", tile, op);
+  if (op == MLPF_OP_ATTENTION) {
+    const AttnTile t = attn_tile(tile);
+    const int32_t v[6] = {t.waves, t.kt, t.qb, t.kind, 0, 0};
+    for (int i = 0; i < 6; ++i) shape[i] = v[i];
+  } else {
+    const GemmTile t = gemm_tile(tile);
+    const int32_t v[6] = {t.bm, t.bn, t.wm, t.wn, t.bkb, t.persist};
+    for (int i = 0; i < 6; ++i) shape[i] = v[i];
+  }
+  return MLPF_OK;
 }
 
 mlpf_status_t mlpf_profiler_enable(mlpf_model_t model, int enable) {

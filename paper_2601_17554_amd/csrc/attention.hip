@@ -200,7 +200,8 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
     }
 
     if constexpr (kBF16) {
-      // P = exp2(S') in FP32 (summed into l), packed to bf16 for the PV product.
+      // P = exp2(S') in FP32, packed to bf16 for the PV product; l sums the packed values, so
+      // numerator and denominator of O = sum P v / sum P carry the same rounded weights.
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -222,8 +223,8 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
               const float e1 = __builtin_amdgcn_exp2f(s[j][b][8 * c + 4 * q + 1]);
               const float e2 = __builtin_amdgcn_exp2f(s[j][b][8 * c + 4 * q + 2]);
               const float e3 = __builtin_amdgcn_exp2f(s[j][b][8 * c + 4 * q + 3]);
-              l_run[j] += (e0 + e1) + (e2 + e3);
               const u32x2 pk = pack_bf16x4(e0, e1, e2, e3);
+              l_run[j] = add_bf16x4(e0, e1, e2, e3, l_run[j]);
               pb[2 * q] = pk[0];
               pb[2 * q + 1] = pk[1];
             }
@@ -306,15 +307,321 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
   }
 }
 
+// BF16 attention without running maxima. The softmax of Eq. 4 is invariant under a per-query shift
+// of the scores; any shift m_q >= max_k s_qk keeps every exponential at or below 1, and one that is
+// not far above the maximum keeps the largest exponentials in the normal FP32 range. The kernel takes
+// the Cauchy-Schwarz bound m_q = |q| max_k |k| (slightly enlarged to cover the rounding of the FP32
+// dot products), with max_k |k|^2 read from a per-(head, row) table of squared key norms. The shift
+// enters the QK^T MFMA as its C operand (16 accumulator registers holding -m_q), so each score costs
+// one exp2 and half a dot2 into the row sum, with no maximum, comparison or rescaling in the key
+// loop. If the bound exceeds the true maximum by more than 96 (log2 units) for some query, its row
+// sum would lose precision; the workgroup then computes the exact maxima in an extra pass over the
+// keys and runs the key loop again with them.
+//
+// Key loop: 32-key blocks, software pipelined (the QK^T product of block b+1 is issued before the
+// exponentials of block b, with the two score sets in alternating registers). K and V stages of
+// 32*G keys rotate through three LDS slots: while stage s is consumed, stage s+1 is resident (the
+// look-ahead product reads it) and stage s+2 travels from global memory in registers; one barrier
+// per stage. Each wave owns QB blocks of 32 queries.
+template <int DH, int NW, int G, int QB, int OCC>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(OCC)))
+void attn_bf16_kernel(const AttnArgs p) {
+  constexpr int NT = NW * 64;
+  constexpr int KEYS = 32 * G;        // keys per stage
+  constexpr int KRS = DH * 2 + 16;    // LDS row stride of K [KEYS][DH]
+  constexpr int VRS = KEYS * 2 + 16;  // LDS row stride of V^T [DH][KEYS]
+  constexpr int K_BYTES = KEYS * KRS, V_BYTES = DH * VRS, SLOT = K_BYTES + V_BYTES;
+  constexpr int CH_ROW = DH / 8;      // 16-byte chunks per K or V row
+  constexpr int NCH = KEYS * CH_ROW;  // chunks per stage and matrix
+  constexpr int PT = (NCH + NT - 1) / NT;
+  constexpr int QKG = DH / 16;        // k-groups of the QK^T product
+  static_assert((DH == 16 || DH == 32) && G % 2 == 0, "bad attention shape");
+
+  __shared__ __attribute__((aligned(16))) char smem[3 * SLOT];
+
+  if ((int)blockIdx.x >= min(*p.n_items, p.cap_items)) return;
+  const int ev = p.items[2 * blockIdx.x], code = p.items[2 * blockIdx.x + 1];
+  const int head = code & 255, qtile = code >> 8;
+  const int start = p.ev_start[ev], n = p.ev_n[ev];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, h = lane >> 5;
+
+  const __bf16* qb = (const __bf16*)p.q + (int64_t)head * p.hstride + (int64_t)start * DH;
+  const __bf16* kb = (const __bf16*)p.k + (int64_t)head * p.hstride + (int64_t)start * DH;
+  const __bf16* vb = (const __bf16*)p.v + (int64_t)head * p.hstride + (int64_t)start * DH;
+
+  // max_k |k|^2 over the event's keys (workgroup reduction through LDS).
+  float kn2 = 0.f;
+  {
+    const float* kn = p.knorm + (int64_t)head * (p.hstride / DH) + start;
+    for (int r = tid; r < n; r += NT) kn2 = fmaxf(kn2, kn[r]);
+    kn2 = wave_max(kn2);
+    float* red = (float*)smem;
+    if (lane == 0) red[wave] = kn2;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) kn2 = fmaxf(kn2, red[w]);
+    __syncthreads();
+  }
+
+  int qi[QB];
+  u32x4 qr[QB][QKG];
+  f32x16 cneg[QB];
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    qi[j] = (qtile * NW + wave) * (32 * QB) + 32 * j + i;
+    float qn2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < QKG; ++c) {
+      qr[j][c] = qi[j] < n ? *(const u32x4*)(qb + (int64_t)qi[j] * DH + (2 * c + h) * 8)
+                           : u32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float lo = __uint_as_float(qr[j][c][e] << 16), hi = __uint_as_float(qr[j][c][e] & 0xffff0000u);
+        qn2 = fmaf(lo, lo, fmaf(hi, hi, qn2));
+      }
+    }
+    qn2 += other_half(qn2);
+    // Scores are sums of DH exact products in FP32: |s - q.k| <= DH * 2^-24 |q| |k|.
+    const float mq = sqrtf(qn2 * kn2) * (1.f + 0x1p-12f);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) cneg[j][r] = -mq;
+  }
+
+  // Bounded buffer loads: zeros past the event's last key.
+  const int run_bytes = n * DH * 2;
+  const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc((void*)kb, (short)0, run_bytes, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc((void*)vb, (short)0, run_bytes, kBufferWord3);
+  auto load = [&](int st, u32x4 (&rk)[PT], u32x4 (&rv)[PT]) {
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int c = t * NT + tid;
+      const int off = (st * KEYS + c / CH_ROW) * (DH * 2) + (c % CH_ROW) * 16;
+      rk[t] = __builtin_amdgcn_raw_buffer_load_b128(krs, off, 0, 0);
+      rv[t] = __builtin_amdgcn_raw_buffer_load_b128(vrs, off, 0, 0);
+    }
+  };
+  auto store = [&](int slot, const u32x4 (&rk)[PT], const u32x4 (&rv)[PT]) {
+    char* Ks = smem + slot * SLOT;
+    char* Vs = Ks + K_BYTES;
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int c = t * NT + tid;
+      if (NCH % NT != 0 && c >= NCH) break;
+      const int r = c / CH_ROW, ch = c % CH_ROW;
+      *(u32x4*)(Ks + r * KRS + ch * 16) = rk[t];
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        *(uint16_t*)(Vs + (ch * 8 + e) * VRS + r * 2) = (uint16_t)(rv[t][e >> 1] >> (16 * (e & 1)));
+    }
+  };
+
+  float l_run[QB], m_ex[QB];
+  f32x16 oacc[QB];
+
+  // Scores plus C of key block bb of the stage in LDS slot `slot`.
+  auto scores = [&](int slot, int bb, f32x16 (&s)[QB], const f32x16 (&c0)[QB]) {
+    const char* Ks = smem + slot * SLOT;
+    u32x4 ka[QKG];
+#pragma unroll
+    for (int c = 0; c < QKG; ++c) ka[c] = *(const u32x4*)(Ks + (32 * bb + i) * KRS + (2 * c + h) * 16);
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      s[j] = c0[j];
+#pragma unroll
+      for (int c = 0; c < QKG; ++c) mma_kg<BF16>(ka[c], qr[j][c], s[j]);
+    }
+  };
+  // Keys at or past n get -inf (only the event's last block can hold such keys).
+  auto mask = [&](int b, f32x16 (&s)[QB]) {
+    const int lim = n - 32 * b - 4 * h;  // key 32b + 4h + c_r is valid iff c_r < lim
+#pragma unroll
+    for (int j = 0; j < QB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (8 * (r >> 2) + (r & 3) >= lim) s[j][r] = -INFINITY;
+  };
+  // P = exp2(S'), packed to bf16 and summed into l as packed; O^T += V^T P^T.
+  auto consume = [&](int slot, int bb, const f32x16 (&s)[QB]) {
+    const char* Vs = smem + slot * SLOT + K_BYTES;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      u32x4 va = u32x4{0, 0, 0, 0};
+      if (i < DH) {
+        const u32x2 v0 = *(const u32x2*)(Vs + i * VRS + (32 * bb + 16 * c + 4 * h) * 2);
+        const u32x2 v1 = *(const u32x2*)(Vs + i * VRS + (32 * bb + 16 * c + 8 + 4 * h) * 2);
+        va = u32x4{v0[0], v0[1], v1[0], v1[1]};
+      }
+#pragma unroll
+      for (int j = 0; j < QB; ++j) {
+        u32x4 pb;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float e0 = __builtin_amdgcn_exp2f(s[j][8 * c + 4 * q + 0]);
+          const float e1 = __builtin_amdgcn_exp2f(s[j][8 * c + 4 * q + 1]);
+          const float e2 = __builtin_amdgcn_exp2f(s[j][8 * c + 4 * q + 2]);
+          const float e3 = __builtin_amdgcn_exp2f(s[j][8 * c + 4 * q + 3]);
+          const u32x2 pk = pack_bf16x4(e0, e1, e2, e3);
+          l_run[j] = add_bf16x4(e0, e1, e2, e3, l_run[j]);
+          pb[2 * q] = pk[0];
+          pb[2 * q + 1] = pk[1];
+        }
+        mma_kg<BF16>(va, pb, oacc[j]);
+      }
+    }
+  };
+  // Exact-maximum pass: running row maxima of the raw scores.
+  auto take_max = [&](const f32x16 (&s)[QB]) {
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      float a = fmaxf(fmaxf(s[j][0], s[j][1]), s[j][2]), b = fmaxf(fmaxf(s[j][3], s[j][4]), s[j][5]);
+      a = fmaxf(fmaxf(a, s[j][6]), s[j][7]);
+      b = fmaxf(fmaxf(b, s[j][8]), s[j][9]);
+      a = fmaxf(fmaxf(a, s[j][10]), s[j][11]);
+      b = fmaxf(fmaxf(b, s[j][12]), s[j][13]);
+      a = fmaxf(fmaxf(a, s[j][14]), s[j][15]);
+      m_ex[j] = fmaxf(m_ex[j], fmaxf(a, b));
+    }
+  };
+
+  const int nblk = (n + 31) >> 5;
+  const int nst = (nblk + G - 1) / G;
+  // One sweep over the keys through the LDS stages; MAXPASS: maxima only.
+  auto sweep = [&](auto maxpass_tag, const f32x16 (&c0)[QB]) {
+    constexpr bool MAXPASS = decltype(maxpass_tag)::value;
+    {
+      u32x4 rk0[PT], rv0[PT], rk1[PT], rv1[PT];
+      if (nst > 0) load(0, rk0, rv0);
+      if (nst > 1) load(1, rk1, rv1);
+      if (nst > 0) store(0, rk0, rv0);
+      if (nst > 1) store(1, rk1, rv1);
+    }
+    __syncthreads();
+    u32x4 rk[PT], rv[PT];
+    if (nst > 2) load(2, rk, rv);
+
+    f32x16 sa[QB], sb[QB];
+    if (nblk > 0) {
+      scores(0, 0, sa, c0);
+      if (nblk == 1 && (n & 31)) mask(0, sa);
+    }
+    // Block b of stage st (position bb) is in `cur`; the look-ahead product fills `nxt`.
+    auto step = [&](int st, int slot, int bb, f32x16 (&cur)[QB], f32x16 (&nxt)[QB]) {
+      const int b = st * G + bb;
+      if (b + 1 < nblk) {
+        if (bb + 1 < G)
+          scores(slot, bb + 1, nxt, c0);
+        else
+          scores(slot == 2 ? 0 : slot + 1, 0, nxt, c0);
+        if (b + 2 == nblk && (n & 31)) mask(b + 1, nxt);
+      }
+      if constexpr (MAXPASS)
+        take_max(cur);
+      else
+        consume(slot, bb, cur);
+    };
+    int slot = 0;
+    for (int st = 0; st < nst; ++st) {
+#pragma unroll
+      for (int bb = 0; bb < G; bb += 2) {
+        const int b = st * G + bb;
+        if (b < nblk) step(st, slot, bb, sa, sb);
+        if (b + 1 < nblk) step(st, slot, bb + 1, sb, sa);
+      }
+      if (st + 2 < nst) store(slot == 0 ? 2 : slot - 1, rk, rv);
+      __syncthreads();
+      if (st + 3 < nst) load(st + 3, rk, rv);
+      slot = slot == 2 ? 0 : slot + 1;
+    }
+  };
+
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    l_run[j] = 0.f;
+    oacc[j] = f32x16{};
+  }
+  sweep(std::false_type{}, cneg);
+
+  // Fallback when a bound was too loose: l >= 2^-(bound - max) and that fell below 2^-96.
+  bool loose = false;
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    const float l_tot = l_run[j] + other_half(l_run[j]);
+    loose = loose || (qi[j] < n && !(l_tot >= 0x1p-96f) && l_tot == l_tot);
+  }
+  if (__syncthreads_or(loose)) {
+    f32x16 zero[QB];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      zero[j] = f32x16{};
+      m_ex[j] = -INFINITY;
+    }
+    sweep(std::true_type{}, zero);
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      const float mx = fmaxf(m_ex[j], other_half(m_ex[j]));
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cneg[j][r] = -mx;
+      l_run[j] = 0.f;
+      oacc[j] = f32x16{};
+    }
+    sweep(std::false_type{}, cneg);
+  }
+
+  // O = O^T / l. Lane l holds dh = 8c + 4*(l/32) + (0..3) of query l%32 in registers 4c..4c+3.
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    const float l_tot = l_run[j] + other_half(l_run[j]);
+    if (qi[j] < n) {
+      const float inv = 1.0f / l_tot;
+      __bf16* orow = (__bf16*)p.o + (int64_t)(start + qi[j]) * p.d + head * DH;
+#pragma unroll
+      for (int c = 0; c < DH / 8; ++c)
+        *(u32x2*)(orow + 8 * c + 4 * h) = pack_bf16x4(oacc[j][4 * c] * inv, oacc[j][4 * c + 1] * inv,
+                                                     oacc[j][4 * c + 2] * inv, oacc[j][4 * c + 3] * inv);
+    }
+  }
+}
+
+// Squared key norms |k|^2 per (head, row) of a [H][rows][dh] bf16 K, read by the BF16 attention
+// kernel for its score bound. One thread per (head, row).
+template <int DH>
+__global__ __launch_bounds__(256) void keynorm_kernel(const __bf16* k, float* out, int64_t total) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  const u32x4* row = (const u32x4*)(k + t * DH);
+  float acc = 0.f;
+#pragma unroll
+  for (int c = 0; c < DH / 8; ++c) {
+    const u32x4 v = row[c];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float lo = __uint_as_float(v[e] << 16), hi = __uint_as_float(v[e] & 0xffff0000u);
+      acc = fmaf(lo, lo, fmaf(hi, hi, acc));
+    }
+  }
+  out[t] = acc;
+}
+
 namespace {
 
 constexpr AttnTile kTiles[] = {
-    {4, 64, 1},
-    {2, 64, 1},
-    {4, 32, 1},
-    {1, 64, 1},
-    {2, 64, 2},
-    {4, 64, 2},
+    // classic kernel (KT keys per LDS tile, two LDS buffers)
+    {4, 64, 1, 0},
+    {2, 64, 1, 0},
+    {4, 32, 1, 0},
+    {1, 64, 1, 0},
+    {2, 64, 2, 0},
+    {4, 64, 2, 0},
+    // BF16 bound-offset kernel (stages of KT keys, three LDS slots); FP32 runs the two-buffer
+    // kernel of the same shape.
+    {4, 64, 1, 1},
+    {4, 64, 2, 1},
+    {4, 128, 1, 1},
+    {2, 64, 1, 1},
+    {8, 64, 1, 1},
+    {4, 64, 1, 1},  // as 6, registers capped for 4 waves per SIMD
 };
 
 template <class T, int DH, int NW, int KT, int QB>
@@ -322,6 +629,19 @@ hipError_t launch_t(const AttnArgs& p, hipStream_t s) {
   if (p.cap_items <= 0) return hipSuccess;
   hipLaunchKernelGGL((attn_kernel<T, DH, NW, KT, QB>), dim3(p.cap_items), dim3(NW * 64), 0, s, p);
   return hipGetLastError();
+}
+
+template <class T, int DH, int NW, int KT, int QB, int OCC = 1>
+hipError_t launch_b(const AttnArgs& p, hipStream_t s) {
+  if constexpr (!std::is_same_v<T, BF16>) {
+    return launch_t<T, DH, NW, KT, QB>(p, s);
+  } else {
+    if (p.cap_items <= 0) return hipSuccess;
+    if (p.knorm == nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((attn_bf16_kernel<DH, NW, KT / 32, QB, OCC>), dim3(p.cap_items), dim3(NW * 64),
+                       0, s, p);
+    return hipGetLastError();
+  }
 }
 
 template <class T, int DH>
@@ -333,6 +653,12 @@ hipError_t launch_dh(int tile, const AttnArgs& p, hipStream_t s) {
     case 3: return launch_t<T, DH, 1, 64, 1>(p, s);
     case 4: return launch_t<T, DH, 2, 64, 2>(p, s);
     case 5: return launch_t<T, DH, 4, 64, 2>(p, s);
+    case 6: return launch_b<T, DH, 4, 64, 1>(p, s);
+    case 7: return launch_b<T, DH, 4, 64, 2>(p, s);
+    case 8: return launch_b<T, DH, 4, 128, 1>(p, s);
+    case 9: return launch_b<T, DH, 2, 64, 1>(p, s);
+    case 10: return launch_b<T, DH, 8, 64, 1>(p, s);
+    case 11: return launch_b<T, DH, 4, 64, 1, 4>(p, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -348,6 +674,19 @@ hipError_t launch_prec(int tile, const AttnArgs& p, hipStream_t s) {
 
 int attn_num_tiles() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
 AttnTile attn_tile(int id) { return kTiles[id]; }
+
+hipError_t launch_keynorm(const void* k, float* out, int64_t total, int dh, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (dh == 32)
+    hipLaunchKernelGGL(keynorm_kernel<32>, dim3((unsigned)blocks), dim3(256), 0, s, (const __bf16*)k, out, total);
+  else if (dh == 16)
+    hipLaunchKernelGGL(keynorm_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, s, (const __bf16*)k, out, total);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 hipError_t launch_attention(Prec prec, int tile, const AttnArgs& p, hipStream_t s) {
   if (prec == P_F32) return launch_prec<F32>(tile, p, s);

@@ -82,6 +82,18 @@ __device__ __forceinline__ u32x2 pack_bf16x4(float a, float b, float c, float d)
   return __builtin_bit_cast(u32x2, v);
 }
 
+// acc + bf16(a) + bf16(b) + bf16(c) + bf16(d) (two v_dot2 with (1, 1); the products are exact),
+// i.e. the sum of exactly the values pack_bf16x4(a, b, c, d) carries into a bf16 MFMA operand.
+// The pairs are built from the floats: taking them out of an already packed u32x2 has been
+// miscompiled (the second dot read the first pair's register).
+__device__ __forceinline__ float add_bf16x4(float a, float b, float c, float d, float acc) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
+  const bf16x2 ab = {(__bf16)a, (__bf16)b}, cd = {(__bf16)c, (__bf16)d};
+  acc = __builtin_amdgcn_fdot2_f32_bf16(ab, one, acc, false);
+  return __builtin_amdgcn_fdot2_f32_bf16(cd, one, acc, false);
+}
+
 // One 32x32 MFMA "k-group": each lane holds 16 bytes of A (row l%32) and 16 bytes of B
 // (column l%32); lane half h = l/32 holds the h-th half of the group's k-values. The k order
 // inside a group is the same for A and B, so any fixed permutation gives the same sum.

@@ -10,12 +10,14 @@
 // next tile's global loads are issued before the current tile's MFMAs and written to LDS after
 // them. LDS rows are padded by 16 bytes so that the 32 rows read by one MFMA operand load fall
 // in different banks. The epilogue is staged through the same LDS (see below).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace mlpf {
 
-template <class T, int ALD, int EPI, int BM, int BN, int BK, int WM, int WN>
+template <class T, int ALD, int EPI, int BM, int BN, int BK, int WM, int WN, bool PERSIST>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   using S = typename T::storage;
   constexpr int NT = 64 * WM * WN;
@@ -36,18 +38,36 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int ntn = (p.N + BN - 1) / BN;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int tm = bid / ntn, tn = bid % ntn;
   int M = p.M;
   if (p.m_dev) M = min(M, max(*p.m_dev, 0));
-  const int m0 = tm * BM, n0 = tn * BN;
-  if (m0 >= M) return;  // uniform over the workgroup
+  const int ntiles = ((M + BM - 1) / BM) * ntn;
+
+  // Tile schedule. One tile per workgroup: xcd_remap gives each XCD a contiguous range of tiles.
+  // Persistent (grid = a multiple of 8 workgroups resident at once): the tiles are cut into 8
+  // contiguous ranges, one per XCD, and the workgroups of an XCD take its tiles round-robin, so
+  // at any time they work on neighbouring tiles (the column tiles of the same rows, whose A rows
+  // then come from that XCD's L2); the first k-tile of a workgroup's next tile is fetched before
+  // the epilogue of the current one.
+  int tile, tile_end, tile_step;
+  if constexpr (PERSIST) {
+    const int per_xcd = (ntiles + 7) / 8;
+    const int x = blockIdx.x % 8, j = blockIdx.x / 8;
+    tile = x * per_xcd + j;
+    tile_end = min(ntiles, (x + 1) * per_xcd);
+    tile_step = gridDim.x / 8;
+  } else {
+    tile = xcd_remap(blockIdx.x, gridDim.x);
+    tile_end = min(ntiles, tile + 1);
+    tile_step = 1;
+  }
+  if (tile >= tile_end) return;  // uniform over the workgroup
+  int m0 = (tile / ntn) * BM, n0 = (tile % ntn) * BN;
 
   u32x4 ra[A_FROM_F32 ? 1 : A_PT];
   float raf[A_FROM_F32 ? A_PT * E : 1];
   u32x4 rb[B_PT];
 
-  auto load = [&](int k0) {
+  auto load = [&](int m0, int n0, int k0) {
 #pragma unroll
     for (int t = 0; t < A_PT; ++t) {
       const int c = t * NT + tid;
@@ -108,20 +128,22 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
     }
   };
 
+  const int nk = p.Kp / BK;
+  const int i = lane & 31, h = lane >> 5;
+  [[maybe_unused]] float amax = 0.f;  // E_GELU: largest |output| of this workgroup's tiles
+  load(m0, n0, 0);
+  while (true) {
   f32x16 acc[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = f32x16{};
 
-  const int nk = p.Kp / BK;
-  const int i = lane & 31, h = lane >> 5;
-  load(0);
   store(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    if (kt + 1 < nk) load(m0, n0, (kt + 1) * BK);
     const char* As = smem + buf * (A_BYTES + B_BYTES);
     const char* Bs = As + A_BYTES;
     // FP32 operands: each k-tile sums into a fresh partial that is then added to the total, so
@@ -161,6 +183,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
     if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
   }
+  const int next = tile + tile_step;
+  if (PERSIST && next < tile_end) load((next / ntn) * BM, (next % ntn) * BN, 0);
 
   // Epilogue, staged through LDS so that global memory sees whole 16-byte row chunks: the waves
   // write bias + activation (FP32) into an LDS tile, then every thread moves 16-byte chunks of
@@ -173,7 +197,6 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   static_assert(PROWS * SRS <= 2 * (A_BYTES + B_BYTES), "epilogue staging does not fit");
   constexpr int OSZ = (EPI == E_BIAS || EPI == E_RESID) ? 4 : (int)sizeof(S);
   constexpr int EO = 16 / OSZ;                           // output elements per 16-byte chunk
-  [[maybe_unused]] float amax = 0.f;
 #pragma unroll
   for (int pass = 0; pass < PASSES; ++pass) {
     if (PASSES == 1 || wm == pass) {
@@ -243,6 +266,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
     }
     if (PASSES > 1 && pass + 1 < PASSES) __syncthreads();
   }
+  if (!PERSIST || next >= tile_end) break;
+  __syncthreads();  // the staging reads are done before the next tile's first LDS store
+  tile = next;
+  m0 = (tile / ntn) * BM;
+  n0 = (tile % ntn) * BN;
+  }
   if constexpr (EPI == E_GELU) {
     if (p.amax) {
       amax = wave_max(amax);
@@ -254,24 +283,53 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
 namespace {
 
 constexpr GemmTile kTiles[] = {
-    {64, 64, 2, 2},
-    {128, 64, 2, 2},
-    {128, 128, 2, 2},
-    {64, 128, 2, 2},
-    {256, 128, 2, 2},  // wave tile 128x64: fewer LDS bytes per MFMA
-    {128, 256, 2, 2},  // wave tile 64x128
+    {64, 64, 2, 2, 128, 0},
+    {128, 64, 2, 2, 128, 0},
+    {128, 128, 2, 2, 128, 0},
+    {64, 128, 2, 2, 128, 0},
+    {256, 128, 2, 2, 128, 0},  // wave tile 128x64: fewer LDS bytes per MFMA
+    {128, 256, 2, 2, 128, 0},  // wave tile 64x128
+    // 64-byte k-tiles: half the LDS per workgroup, so more workgroups per CU hide load latency
+    {128, 128, 2, 2, 64, 0},
+    {128, 64, 2, 2, 64, 0},
+    {64, 128, 2, 2, 64, 0},
+    // persistent workgroups (next tile's first k-tile fetched during the epilogue)
+    {128, 128, 2, 2, 64, 1},
+    {128, 64, 2, 2, 64, 1},
+    {64, 128, 2, 2, 64, 1},
+    {128, 128, 2, 2, 128, 1},
 };
 
-template <class T, int ALD, int EPI, int BM, int BN, int WM, int WN>
+// Workgroups of one kernel that fit on the device at once (the grid of a persistent launch). The
+// result only sizes the grid: the tile schedule is correct for any grid that is a multiple of 8.
+template <class K>
+int resident_workgroups(K kernel, int threads) {
+  static int cached = 0;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+    return cus * 2;
+  cached = cus * per_cu;
+  return cached;
+}
+
+template <class T, int ALD, int EPI, int BM, int BN, int WM, int WN, int BKB = 128, bool PERSIST = false>
 hipError_t launch_t(const GemmArgs& p, hipStream_t s) {
-  constexpr int BK = 128 / T::kBytes;  // 128 bytes of each row per k-tile
+  constexpr int BK = BKB / T::kBytes;  // BKB bytes of each row per k-tile
   if (p.Kp % BK != 0 || p.N % 16 != 0) return hipErrorInvalidValue;
   const int gm = (p.M + BM - 1) / BM, gn = (p.N + BN - 1) / BN;
-  const int64_t grid = (int64_t)gm * gn;
+  int64_t grid = (int64_t)gm * gn;
   if (grid == 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_kernel<T, ALD, EPI, BM, BN, BK, WM, WN>), dim3((unsigned)grid),
-                     dim3(64 * WM * WN), 0, s, p);
+  auto kernel = gemm_kernel<T, ALD, EPI, BM, BN, BK, WM, WN, PERSIST>;
+  if constexpr (PERSIST) {
+    const int res = std::max(8, resident_workgroups(kernel, 64 * WM * WN));
+    grid = std::min<int64_t>((grid + 7) / 8 * 8, res / 8 * 8);
+  }
+  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(64 * WM * WN), 0, s, p);
   return hipGetLastError();
 }
 
@@ -284,6 +342,13 @@ hipError_t launch_tile(int tile, const GemmArgs& p, hipStream_t s) {
     case 3: return launch_t<T, ALD, EPI, 64, 128, 2, 2>(p, s);
     case 4: return launch_t<T, ALD, EPI, 256, 128, 2, 2>(p, s);
     case 5: return launch_t<T, ALD, EPI, 128, 256, 2, 2>(p, s);
+    case 6: return launch_t<T, ALD, EPI, 128, 128, 2, 2, 64>(p, s);
+    case 7: return launch_t<T, ALD, EPI, 128, 64, 2, 2, 64>(p, s);
+    case 8: return launch_t<T, ALD, EPI, 64, 128, 2, 2, 64>(p, s);
+    case 9: return launch_t<T, ALD, EPI, 128, 128, 2, 2, 64, true>(p, s);
+    case 10: return launch_t<T, ALD, EPI, 128, 64, 2, 2, 64, true>(p, s);
+    case 11: return launch_t<T, ALD, EPI, 64, 128, 2, 2, 64, true>(p, s);
+    case 12: return launch_t<T, ALD, EPI, 128, 128, 2, 2, 128, true>(p, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -49,6 +49,8 @@ struct GemmArgs {
 // elements), waves along M, waves along N.
 struct GemmTile {
   int bm, bn, wm, wn;
+  int bkb;      // bytes of each operand row per k-tile
+  int persist;  // 1: persistent workgroups looping over tiles
 };
 int gemm_num_tiles();
 GemmTile gemm_tile(int id);
@@ -67,16 +69,20 @@ struct AttnArgs {
   const int32_t* n_items = nullptr;  // device count
   const int32_t* ev_start = nullptr;
   const int32_t* ev_n = nullptr;
+  const float* knorm = nullptr;      // BF16 kernel: [H][rows_cap] squared key norms
   int cap_items = 0;
 };
 struct AttnTile {
   int waves;  // waves per workgroup
   int kt;     // keys per LDS tile
   int qb;     // 32-query blocks per wave; queries per work item = 32 * waves * qb
+  int kind;   // 0: two-buffer online-softmax kernel; 1: BF16 bound-offset kernel (needs knorm)
 };
 int attn_num_tiles();
 AttnTile attn_tile(int id);
 hipError_t launch_attention(Prec prec, int tile, const AttnArgs& args, hipStream_t stream);
+// knorm[t] = |k_t|^2 for the total = H * rows_cap rows of a bf16 [H][rows_cap][dh] K.
+hipError_t launch_keynorm(const void* k, float* knorm, int64_t total, int dh, hipStream_t stream);
 
 // Sanitises the batch description and builds the attention work list (one workgroup).
 struct WorklistArgs {

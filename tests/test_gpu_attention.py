@@ -29,21 +29,42 @@ def B():
     return binding
 
 
+def _operands(kind, H, T, dh, spread, rng):
+    """q, k, v of one of the input families: "random" (i.i.d. normal times spread), "shifted" (every
+    query has a large component along a direction no key shares, and one key per event a large
+    norm: the score bound |q| max|k| lies about 70 log2 units above the true maxima), "loose" (the
+    same with the bound more than 96 above, which the BF16 kernel answers with an exact-maximum
+    pass)."""
+    q = rng.standard_normal((H, T, dh)).astype(np.float32) * spread
+    k = rng.standard_normal((H, T, dh)).astype(np.float32) * spread
+    v = rng.standard_normal((H, T, dh)).astype(np.float32)
+    if kind != "random":
+        big_q, big_k = (20.0, 14.0) if kind == "shifted" else (30.0, 16.0)
+        q[:, :, 0] = big_q
+        k[:, :, 0] = 0.0
+        k[:, ::7, 1] = big_k
+    return q, k, v
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("cfg", [synth.FULL, synth.SMALL], ids=["dh32", "dh16"])
-@pytest.mark.parametrize("spread", [1.0, 3.0], ids=["flat", "sharp"])
-def test_attention_alone(B, prec, cfg, spread):
+@pytest.mark.parametrize("kind,spread", [("random", 1.0), ("random", 3.0), ("shifted", 0.5),
+                                         ("loose", 0.5)], ids=["flat", "sharp", "shifted", "loose"])
+def test_attention_alone(B, prec, cfg, kind, spread):
+    _attention_case(B, prec, cfg, kind, spread, tile=-1)
+
+
+def _attention_case(B, prec, cfg, kind, spread, tile):
     import torch
     sizes = [1, 2, 5, 31, 33, 64, 65, 100, 130, 300]
     rs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
     T, H, dh = int(rs[-1]), cfg.n_heads, cfg.d_head
     rng = np.random.default_rng(7)
-    q = rng.standard_normal((H, T, dh)).astype(np.float32) * spread
-    k = rng.standard_normal((H, T, dh)).astype(np.float32) * spread
-    v = rng.standard_normal((H, T, dh)).astype(np.float32)
+    q, k, v = _operands(kind, H, T, dh, spread, rng)
     if prec == "bf16":
         q, k, v = _bf16(q), _bf16(k), _bf16(v)
     m = B.Model(cfg, synth.make_weights(cfg, 0), prec)
+    m.tune_set("attention", tile)
     tdt = torch.float32 if prec == "fp32" else torch.bfloat16
     dq, dk, dv = (torch.from_numpy(a).to(tdt).cuda() for a in (q, k, v))
     batch = B.Batch.from_host(rs, None)
@@ -62,5 +83,14 @@ def test_attention_alone(B, prec, cfg, spread):
             got = o[r, j * dh:(j + 1) * dh]
             err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-6)
             worst = max(worst, err)
-            assert err <= TOL[prec], f"event {e} (n={sizes[e]}) head {j}: {err:.3e}"
-    print(f"{prec} dh={dh} spread={spread}: worst normwise error {worst:.2e}")
+            assert err <= TOL[prec], f"tile {tile} event {e} (n={sizes[e]}) head {j}: {err:.3e}"
+    print(f"{prec} dh={dh} {kind} spread={spread} tile {tile}: worst normwise error {worst:.2e}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("kind,spread", [("random", 3.0), ("loose", 0.5)], ids=["sharp", "loose"])
+def test_attention_every_tile(B, prec, kind, spread):
+    """Every attention kernel shape the tuner may pick, on the head size of the full model."""
+    from paper_2601_17554_amd import binding
+    for tile in range(binding.Model.tune_count("attention")):
+        _attention_case(B, prec, synth.FULL, kind, spread, tile)

@@ -216,3 +216,41 @@ def test_invalid_arguments_rejected(B):
     big = B.Batch(batch.row_start, batch.n_valid, 1, pk.total_rows, 9000)
     with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
         m.reconstruct(x, big)
+
+
+GEMM_OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_every_gemm_tile(B, prec):
+    """Every GEMM tile shape the tuner may pick, for all products at once, against the oracle on
+    the ragged full-model batch."""
+    w, m = _model(B, synth.FULL, 2, prec, sharpen=4.0)
+    evs = [synth.make_event(2000 + i, n) for i, n in enumerate([70, 1, 517, 200, 33])]
+    pk = synth.pack(evs)
+    for tile in range(B.Model.tune_count("qkv")):
+        for op in GEMM_OPS:
+            m.tune_set(op, tile)
+        _check_all(run_gpu(m, pk), pk, w, synth.FULL, TOL[prec], f"gemm tile {tile} {prec}",
+                   keys=[("varlen", i) for i in range(len(evs))])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_persistent_gemm_bitwise(B, prec):
+    """Persistent GEMM workgroups (several tiles each) give the same bits as one workgroup per tile
+    with the same k-tiling, on a batch large enough for every workgroup to loop."""
+    w, m = _model(B, synth.FULL, 14, prec)
+    pk = synth.pack(synth.event_set(400, 12, lo=1500))
+    tiles = [B.Model.tune_shape("qkv", t) for t in range(B.Model.tune_count("qkv"))]
+    results = {}
+    for t, spec in enumerate(tiles):
+        for op in GEMM_OPS:
+            m.tune_set(op, t)
+        results[t] = run_gpu(m, pk)
+    for t, spec in enumerate(tiles):
+        if not spec["persist"]:
+            continue
+        twin = next(u for u, o in enumerate(tiles) if not o["persist"] and
+                    all(o[k] == spec[k] for k in ("bm", "bn", "wm", "wn", "bkb")))
+        for k in ("logits", "reg"):
+            np.testing.assert_array_equal(results[t][k], results[twin][k], err_msg=f"tile {t} vs {twin} {k}")
