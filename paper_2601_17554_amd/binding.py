@@ -99,7 +99,7 @@ def exported_symbols() -> Sequence[str]:
 
 
 PROF_CLASSES = ("embed", "qkv", "attention", "outproj", "ffn1", "ffn2", "heads", "worklist")
-OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1", "attention")
+OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1", "attention", "ffn")
 
 
 def _status_name(s: int) -> str:
@@ -307,7 +307,7 @@ class Model:
         kind}."""
         v = (ctypes.c_int32 * 6)()
         _check(load().mlpf_tune_shape(OPS.index(op), tile, v))
-        keys = (("waves", "kt", "qb", "kind") if op == "attention"
+        keys = (("waves", "kt", "qb", "kind") if op == "attention" else ("fused",) if op == "ffn"
                 else ("bm", "bn", "wm", "wn", "bkb", "persist"))
         return {k: int(v[i]) for i, k in enumerate(keys)}
 

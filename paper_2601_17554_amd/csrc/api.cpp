@@ -56,6 +56,8 @@ constexpr int kEmbedKp = 64;
 
 struct Layer {
   size_t ln1g, ln1b, wqkv, bqkv, wo, bo, ln2g, ln2b, w1, b1, w2, b2;
+  size_t w1p = 0, w2p = 0;  // fused-FFN weight images (ffn_pack), when ffn_fused
+
   // FP8 FFN: per-tensor weight scales and activation scales (FFN1 input, FFN2 input).
   float s_w1 = 1.f, s_w2 = 1.f, s_a1 = 1.f, s_a2 = 1.f;
 };
@@ -63,6 +65,7 @@ struct Layer {
 // Byte offsets of every packed tensor inside the device weight buffer.
 struct WeightPlan {
   size_t e_w1, e_b1, e_w2, e_b2;
+  bool ffn_fused = false;  // the fused BF16 FFN kernel applies (its weight images are packed)
   std::vector<Layer> layers;
   size_t h_w1, h_b1, h_w2, h_b2;
   size_t total;
@@ -108,6 +111,7 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
   w.e_w2 = take(d * d * eb);
   w.e_b2 = take(d * 4);
   w.layers.resize(c.n_layers);
+  w.ffn_fused = prec == MLPF_BF16 && ffn_fused_supported(c.d_model, c.d_ff);
   for (auto& L : w.layers) {
     L.ln1g = take(d * 4);
     L.ln1b = take(d * 4);
@@ -121,6 +125,10 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
     L.b1 = take(ff * 4);
     L.w2 = take(d * ff * fb);
     L.b2 = take(d * 4);
+    if (w.ffn_fused) {
+      L.w1p = take(ffn_pack_bytes(c.d_model, c.d_ff, 1));
+      L.w2p = take(ffn_pack_bytes(c.d_model, c.d_ff, 2));
+    }
   }
   w.h_w1 = take(5 * d * d * eb);
   w.h_b1 = take(5 * d * 4);
@@ -403,6 +411,11 @@ mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const v
   return MLPF_OK;
 }
 
+// The fused FFN kernel runs unless the model cannot use it or MLPF_OP_FFN is pinned to 0.
+bool ffn_fused_on(const mlpf_model_s* m) {
+  return m->plan.ffn_fused && m->tune[MLPF_OP_FFN] != 0;
+}
+
 mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
   const mlpf_model_s* m = cx.m;
   const mlpf_config_t& c = m->cfg;
@@ -470,6 +483,24 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
   if (fp8) {
     f1.acc_scale = L.s_a1 * L.s_w1;
     f1.out_scale = 1.f / L.s_a2;
+  }
+  if (ffn_fused_on(m) && !cx.calib) {
+    // One kernel: the d_ff-wide intermediate stays on chip (timed in the FFN1 class).
+    ProfScope prof(cx.m, MLPF_PROF_FFN1, cx.s);
+    if ((st = run_layernorm(cx, h, L.ln2g, L.ln2b))) return st;
+    FfnArgs a;
+    a.y = cx.p(cx.w.y);
+    a.M = T;
+    a.m_dev = cx.n_rows;
+    a.d_model = d;
+    a.d_ff = c.d_ff;
+    a.w1p = m->at(L.w1p);
+    a.b1 = m->atf(L.b1);
+    a.w2p = m->at(L.w2p);
+    a.b2 = m->atf(L.b2);
+    a.h = h;
+    HIP_TRY(launch_ffn_fused(a, cx.s), "fused FFN launch");
+    return MLPF_OK;
   }
   {
     ProfScope prof(cx.m, MLPF_PROF_FFN1, cx.s);
@@ -676,6 +707,9 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
       put_f32(L.b1, ff);
       put_wt(L.w2, ff, d, ff);
       put_f32(L.b2, d);
+      if (plan.ffn_fused)
+        ffn_pack((const uint16_t*)(img.data() + L.w1), (const uint16_t*)(img.data() + L.w2), d, ff,
+                 (uint16_t*)(img.data() + L.w1p), (uint16_t*)(img.data() + L.w2p));
     }
   }
   // Heads: W1 of the five heads stacked as rows of W^T [5d][d]; W2 as [d][11].
@@ -845,6 +879,7 @@ mlpf_status_t mlpf_graph_destroy(mlpf_graph_t graph) {
 
 int32_t mlpf_tune_count(int32_t op) {
   if (op < 0 || op >= MLPF_OP_COUNT) return 0;
+  if (op == MLPF_OP_FFN) return 2;
   return op == MLPF_OP_ATTENTION ? attn_num_tiles() : gemm_num_tiles();
 }
 
@@ -853,6 +888,8 @@ mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile) {
   if (op < 0 || op >= MLPF_OP_COUNT) return fail(MLPF_ERR_INVALID_ARG, "op=%d out of range", op);
   if (tile < -1 || tile >= mlpf_tune_count(op))
     return fail(MLPF_ERR_INVALID_ARG, "tile=%d out of range for op %d", tile, op);
+  if (op == MLPF_OP_FFN && tile == 1 && !model->plan.ffn_fused)
+    return fail(MLPF_ERR_UNSUPPORTED, "the fused FFN needs an MLPF_BF16 model with d_model 64, 128 or 256");
   model->tune[op] = tile;
   return MLPF_OK;
 }
@@ -871,6 +908,8 @@ mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape) {
     const AttnTile t = attn_tile(tile);
     const int32_t v[6] = {t.waves, t.kt, t.qb, t.kind, 0, 0};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
+  } else if (op == MLPF_OP_FFN) {
+    for (int i = 0; i < 6; ++i) shape[i] = i == 0 ? tile : 0;
   } else {
     const GemmTile t = gemm_tile(tile);
     const int32_t v[6] = {t.bm, t.bn, t.wm, t.wn, t.bkb, t.persist};

@@ -322,15 +322,20 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
 // exponentials of block b, with the two score sets in alternating registers). K and V stages of
 // 32*G keys rotate through three LDS slots: while stage s is consumed, stage s+1 is resident (the
 // look-ahead product reads it) and stage s+2 travels from global memory in registers; one barrier
-// per stage. Each wave owns QB blocks of 32 queries.
+// per stage. Each wave owns QB blocks of 32 queries. V stays row-major in LDS (one 16-byte store
+// per chunk); the V^T operand of O^T = V^T P^T is read with the transposing ds_read_b64_tr_b16: in
+// each 16-lane group, lane j receives element j%4 of the 8-byte chunks addressed by lanes j/4,
+// j/4+4, j/4+8 and j/4+12 of the group, so lane s addresses row (key) s/4 and dh columns
+// 4(s%4)..4(s%4)+3 and every lane gets one dh column of four consecutive keys.
 template <int DH, int NW, int G, int QB, int OCC>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(OCC)))
 void attn_bf16_kernel(const AttnArgs p) {
   constexpr int NT = NW * 64;
   constexpr int KEYS = 32 * G;        // keys per stage
   constexpr int KRS = DH * 2 + 16;    // LDS row stride of K [KEYS][DH]
-  constexpr int VRS = KEYS * 2 + 16;  // LDS row stride of V^T [DH][KEYS]
-  constexpr int K_BYTES = KEYS * KRS, V_BYTES = DH * VRS, SLOT = K_BYTES + V_BYTES;
+  constexpr int VRS = DH * 2 + 32;    // LDS row stride of V [KEYS][DH]: the 4 rows x 32 bytes a
+                                      // transposing read touches per lane group hit distinct banks
+  constexpr int K_BYTES = KEYS * KRS, V_BYTES = KEYS * VRS, SLOT = K_BYTES + V_BYTES;
   constexpr int CH_ROW = DH / 8;      // 16-byte chunks per K or V row
   constexpr int NCH = KEYS * CH_ROW;  // chunks per stage and matrix
   constexpr int PT = (NCH + NT - 1) / NT;
@@ -411,9 +416,7 @@ void attn_bf16_kernel(const AttnArgs p) {
       if (NCH % NT != 0 && c >= NCH) break;
       const int r = c / CH_ROW, ch = c % CH_ROW;
       *(u32x4*)(Ks + r * KRS + ch * 16) = rk[t];
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        *(uint16_t*)(Vs + (ch * 8 + e) * VRS + r * 2) = (uint16_t)(rv[t][e >> 1] >> (16 * (e & 1)));
+      *(u32x4*)(Vs + r * VRS + ch * 16) = rv[t];
     }
   };
 
@@ -443,16 +446,21 @@ void attn_bf16_kernel(const AttnArgs p) {
         if (8 * (r >> 2) + (r & 3) >= lim) s[j][r] = -INFINITY;
   };
   // P = exp2(S'), packed to bf16 and summed into l as packed; O^T += V^T P^T.
+  typedef short tr4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) tr4 lds_tr4;
+  const int j16 = i & 15;
+  const int vcol = ((DH == 32 ? (i & 16) : 0) + 4 * (j16 & 3)) * 2;  // byte column this lane addresses
   auto consume = [&](int slot, int bb, const f32x16 (&s)[QB]) {
     const char* Vs = smem + slot * SLOT + K_BYTES;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      u32x4 va = u32x4{0, 0, 0, 0};
-      if (i < DH) {
-        const u32x2 v0 = *(const u32x2*)(Vs + i * VRS + (32 * bb + 16 * c + 4 * h) * 2);
-        const u32x2 v1 = *(const u32x2*)(Vs + i * VRS + (32 * bb + 16 * c + 8 + 4 * h) * 2);
-        va = u32x4{v0[0], v0[1], v1[0], v1[1]};
-      }
+      // Keys 16c + 4h + (0..3) and 16c + 8 + 4h + (0..3) of the block, the order of P^T's registers.
+      const char* vp = Vs + (32 * bb + 16 * c + 4 * h + (j16 >> 2)) * VRS + vcol;
+      const tr4 v0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_tr4*)vp);
+      const tr4 v1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_tr4*)(vp + 8 * VRS));
+      const u32x2 w0 = __builtin_bit_cast(u32x2, v0), w1 = __builtin_bit_cast(u32x2, v1);
+      u32x4 va = u32x4{w0[0], w0[1], w1[0], w1[1]};
+      if (DH < 32 && i >= DH) va = u32x4{0, 0, 0, 0};
 #pragma unroll
       for (int j = 0; j < QB; ++j) {
         u32x4 pb;

@@ -1,0 +1,214 @@
+// Fused position-wise feed-forward block of one encoder layer, BF16 (paper Sec. 5.3):
+//   h[M][D] += GELU(y W1 + b1) W2 + b2,   y = LN2(h) in bf16, W1 [D][d_ff], W2 [d_ff][D].
+// The d_ff-wide intermediate never leaves the workgroup: it is produced and consumed in chunks of
+// kFfnHC hidden units. A workgroup owns kFfnBM rows; per chunk
+//   phase 1: U^T = W1_c^T y^T (32x32 MFMA blocks; y's fragments stay in registers for the whole
+//            workgroup) -> + b1 -> GELU -> bf16, written to LDS as U [row][hidden]; the transposed
+//            product puts each lane on one row with the hidden units of that row in its registers,
+//            so the LDS writes are 8-byte runs;
+//   phase 2: O += U W2_c (U and W2_c^T fragments from LDS).
+// The weight chunks are stored pre-tiled in HBM exactly as their LDS images (padded rows, see
+// ffn_pack_bytes) and copied linearly with direct-to-LDS loads, double buffered: chunk c+1 travels
+// while chunk c is computed. The summation order over k (D in phase 1, d_ff in phase 2) is the order
+// of the unfused products, so the results match the two-GEMM path bit for bit.
+#include "common.h"
+#include "kernels.h"
+
+namespace mlpf {
+
+namespace {
+
+constexpr int kFfnBM = 128;  // rows per workgroup
+constexpr int kFfnHC = 64;   // hidden units per chunk
+constexpr int kFfnNW = 8;    // waves per workgroup
+constexpr int kFfnNT = kFfnNW * 64;
+
+template <int D>
+struct FfnLayout {
+  static constexpr int W1RS = 2 * D + 16;       // W1 chunk row: one hidden unit, D k-values
+  static constexpr int W1CH = kFfnHC * W1RS;
+  static constexpr int W2RS = 2 * kFfnHC + 16;  // W2^T chunk row: one output, kFfnHC k-values
+  static constexpr int W2CH = D * W2RS;
+  static constexpr int URS = 2 * kFfnHC + 16;   // U row: one token row, kFfnHC hidden units
+  static constexpr int U_BYTES = kFfnBM * URS;
+  static constexpr int LDS = 2 * W1CH + 2 * W2CH + U_BYTES;
+  static constexpr int SRS = 4 * D + 16;        // epilogue staging row (FP32)
+  static_assert(kFfnBM * SRS <= LDS, "epilogue staging does not fit");
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void gbl_void;
+
+// Copies `bytes` (a multiple of 16) from global src to LDS dst: round r, wave w, lane l moves the
+// 16 bytes at offset r * 16 * kFfnNT + 1024 w + 16 l (direct-to-LDS loads write lane l's data at
+// the wave's LDS base + 16 l).
+__device__ __forceinline__ void copy_to_lds(const char* src, char* dst, int bytes, int wave, int lane) {
+  for (int base = wave * 1024; base < bytes; base += 16 * kFfnNT) {
+    const int off = base + 16 * lane;
+    if (off < bytes)
+      __builtin_amdgcn_global_load_lds((gbl_void*)(src + off), (lds_void*)(dst + base), 16, 0, 0);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
+  using L = FfnLayout<D>;
+  constexpr int KG1 = D / 16;                    // k-groups of phase 1
+  constexpr int KG2 = kFfnHC / 16;               // k-groups of phase 2
+  constexpr int WN2 = D / 32 < 4 ? D / 32 : 4;   // phase-2 wave grid (rows x columns)
+  constexpr int WM2 = kFfnNW / WN2;
+  constexpr int FM2 = (kFfnBM / 32) / WM2, FN2 = (D / 32) / WN2;
+  static_assert(FM2 >= 1 && FN2 >= 1 && (kFfnBM / 32) * (kFfnHC / 32) == kFfnNW, "bad FFN shape");
+
+  __shared__ __attribute__((aligned(16))) char smem[L::LDS];
+  char* const w1buf = smem;                      // [2][W1CH]
+  char* const w2buf = smem + 2 * L::W1CH;        // [2][W2CH]
+  char* const ubuf = w2buf + 2 * L::W2CH;        // [kFfnBM][URS]
+
+  int M = p.M;
+  if (p.m_dev) M = min(M, max(*p.m_dev, 0));
+  const int m0 = blockIdx.x * kFfnBM;
+  if (m0 >= M) return;  // uniform over the workgroup
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, h = lane >> 5;
+  const int nch = p.d_ff / kFfnHC;
+  const char* w1p = (const char*)p.w1p;
+  const char* w2p = (const char*)p.w2p;
+
+  copy_to_lds(w1p, w1buf, L::W1CH, wave, lane);
+  copy_to_lds(w2p, w2buf, L::W2CH, wave, lane);
+
+  // Phase-1 role: hidden block hb (32 units of the chunk) x token block tb (32 rows).
+  const int hb = wave / (kFfnBM / 32), tb = wave % (kFfnBM / 32);
+  // y fragments (B operand of U^T = W1^T y^T): lane holds row 32 tb + i, k = 16 g + 8 h .. + 7.
+  u32x4 yf[KG1];
+  {
+    const int row = m0 + 32 * tb + i;
+    const __bf16* yr = (const __bf16*)p.y + (int64_t)row * D;
+#pragma unroll
+    for (int g = 0; g < KG1; ++g)
+      yf[g] = row < M ? *(const u32x4*)(yr + 16 * g + 8 * h) : u32x4{0, 0, 0, 0};
+  }
+  // Phase-2 role: FM2 x FN2 blocks of 32x32 outputs.
+  const int wm2 = wave / WN2, wn2 = wave % WN2;
+  f32x16 acc[FM2][FN2];
+#pragma unroll
+  for (int a = 0; a < FM2; ++a)
+#pragma unroll
+    for (int b = 0; b < FN2; ++b) acc[a][b] = f32x16{};
+
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) {
+      copy_to_lds(w1p + (size_t)(c + 1) * L::W1CH, w1buf + (buf ^ 1) * L::W1CH, L::W1CH, wave, lane);
+      copy_to_lds(w2p + (size_t)(c + 1) * L::W2CH, w2buf + (buf ^ 1) * L::W2CH, L::W2CH, wave, lane);
+    }
+    // Phase 1: this wave's 32x32 block of U^T, summed over k = 0 .. D-1 in order.
+    {
+      const char* w1 = w1buf + buf * L::W1CH + (32 * hb + i) * L::W1RS + 16 * h;
+      f32x16 u = f32x16{};
+#pragma unroll
+      for (int g = 0; g < KG1; ++g) mma_kg<BF16>(*(const u32x4*)(w1 + 32 * g), yf[g], u);
+      // Lane holds row 32 tb + i and hidden units 32 hb + 8 q + 4 h + (0..3) in registers 4q..4q+3.
+      const float* b1 = p.b1 + c * kFfnHC + 32 * hb + 4 * h;
+      char* urow = ubuf + (32 * tb + i) * L::URS + (32 * hb + 4 * h) * 2;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bq = *(const f32x4*)(b1 + 8 * q);
+        *(u32x2*)(urow + 16 * q) =
+            pack_bf16x4(gelu_erf(u[4 * q] + bq[0]), gelu_erf(u[4 * q + 1] + bq[1]),
+                        gelu_erf(u[4 * q + 2] + bq[2]), gelu_erf(u[4 * q + 3] + bq[3]));
+      }
+    }
+    __syncthreads();
+    // Phase 2: O += U W2_c over the chunk's k-groups in order.
+    {
+      const char* w2 = w2buf + buf * L::W2CH;
+#pragma unroll
+      for (int g = 0; g < KG2; ++g) {
+        u32x4 af[FM2], bf[FN2];
+#pragma unroll
+        for (int a = 0; a < FM2; ++a)
+          af[a] = *(const u32x4*)(ubuf + (32 * (wm2 * FM2 + a) + i) * L::URS + 32 * g + 16 * h);
+#pragma unroll
+        for (int b = 0; b < FN2; ++b)
+          bf[b] = *(const u32x4*)(w2 + (32 * (wn2 * FN2 + b) + i) * L::W2RS + 32 * g + 16 * h);
+#pragma unroll
+        for (int a = 0; a < FM2; ++a)
+#pragma unroll
+          for (int b = 0; b < FN2; ++b) mma_kg<BF16>(af[a], bf[b], acc[a][b]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk c+1 have landed
+    __syncthreads();
+  }
+
+  // Epilogue: out + b2 staged through LDS as FP32 rows, then h += out in 16-byte row chunks.
+  // Lane l of a 32x32 block holds column l%32 of rows 8*(r/4) + 4*(l/32) + r%4.
+#pragma unroll
+  for (int a = 0; a < FM2; ++a)
+#pragma unroll
+    for (int b = 0; b < FN2; ++b) {
+      const int col = 32 * (wn2 * FN2 + b) + i;
+      const float bias = p.b2[col];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * (wm2 * FM2 + a) + 8 * (r >> 2) + 4 * h + (r & 3);
+        *(float*)(smem + row * L::SRS + col * 4) = acc[a][b][r] + bias;
+      }
+    }
+  __syncthreads();
+  constexpr int CPR = D / 4;
+  for (int t = tid; t < kFfnBM * CPR; t += kFfnNT) {
+    const int row = t / CPR, col = (t % CPR) * 4;
+    if (m0 + row >= M) continue;
+    f32x4* dst = (f32x4*)(p.h + (int64_t)(m0 + row) * D + col);
+    const f32x4 v = *(const f32x4*)(smem + row * L::SRS + col * 4);
+    *dst = v + *dst;
+  }
+}
+
+}  // namespace
+
+int ffn_fused_supported(int d_model, int d_ff) {
+  return (d_model == 64 || d_model == 128 || d_model == 256) && d_ff % kFfnHC == 0 && d_ff > 0;
+}
+
+size_t ffn_pack_bytes(int d_model, int d_ff, int which) {
+  const size_t chunks = (size_t)d_ff / kFfnHC;
+  return which == 1 ? chunks * kFfnHC * (2 * (size_t)d_model + 16)
+                    : chunks * (size_t)d_model * (2 * kFfnHC + 16);
+}
+
+void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, uint16_t* w1p,
+              uint16_t* w2p) {
+  const int D = d_model, HC = kFfnHC;
+  const size_t w1rs = (2 * (size_t)D + 16) / 2, w2rs = (2 * (size_t)HC + 16) / 2;  // in bf16 units
+  for (int c = 0; c < d_ff / HC; ++c) {
+    uint16_t* b1 = w1p + (size_t)c * HC * w1rs;
+    for (int r = 0; r < HC; ++r)
+      for (int k = 0; k < w1rs; ++k) b1[r * w1rs + k] = k < D ? w1t[(size_t)(c * HC + r) * D + k] : 0;
+    uint16_t* b2 = w2p + (size_t)c * D * w2rs;
+    for (int o = 0; o < D; ++o)
+      for (int k = 0; k < w2rs; ++k) b2[o * w2rs + k] = k < HC ? w2t[(size_t)o * d_ff + c * HC + k] : 0;
+  }
+}
+
+hipError_t launch_ffn_fused(const FfnArgs& p, hipStream_t s) {
+  if (!ffn_fused_supported(p.d_model, p.d_ff)) return hipErrorInvalidValue;
+  const int64_t grid = ((int64_t)p.M + kFfnBM - 1) / kFfnBM;
+  if (grid == 0) return hipSuccess;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  switch (p.d_model) {
+    case 64: hipLaunchKernelGGL(ffn_fused_kernel<64>, dim3((unsigned)grid), dim3(kFfnNT), 0, s, p); break;
+    case 128: hipLaunchKernelGGL(ffn_fused_kernel<128>, dim3((unsigned)grid), dim3(kFfnNT), 0, s, p); break;
+    default: hipLaunchKernelGGL(ffn_fused_kernel<256>, dim3((unsigned)grid), dim3(kFfnNT), 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mlpf

@@ -57,6 +57,27 @@ GemmTile gemm_tile(int id);
 hipError_t launch_gemm(Prec prec, ALoad aload, Epi epi, int tile, const GemmArgs& args,
                        hipStream_t stream);
 
+// Fused BF16 FFN block: h[M][d_model] += GELU(y W1 + b1) W2 + b2 with the weights pre-tiled by
+// ffn_pack (W1 and W2 chunks of 64 hidden units as their LDS images).
+struct FfnArgs {
+  const void* y = nullptr;      // bf16 [M][d_model]
+  int M = 0;
+  const int32_t* m_dev = nullptr;
+  int d_model = 0, d_ff = 0;
+  const void* w1p = nullptr;    // ffn_pack layout
+  const float* b1 = nullptr;
+  const void* w2p = nullptr;
+  const float* b2 = nullptr;
+  float* h = nullptr;           // FP32 [M][d_model], updated in place
+};
+int ffn_fused_supported(int d_model, int d_ff);
+// Bytes of the packed W1 (which = 1) or W2 (which = 2) image.
+size_t ffn_pack_bytes(int d_model, int d_ff, int which);
+// Packs W1^T [d_ff][d_model] and W2^T [d_model][d_ff] (bf16 bits) into the chunked images.
+void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, uint16_t* w1p,
+              uint16_t* w2p);
+hipError_t launch_ffn_fused(const FfnArgs& args, hipStream_t stream);
+
 // Attention over a device work list (see worklist).
 struct AttnArgs {
   const void* q = nullptr;  // [H][rows_cap][dh], pre-scaled by log2(e)/sqrt(dh)

@@ -228,6 +228,7 @@ def test_every_gemm_tile(B, prec):
     w, m = _model(B, synth.FULL, 2, prec, sharpen=4.0)
     evs = [synth.make_event(2000 + i, n) for i, n in enumerate([70, 1, 517, 200, 33])]
     pk = synth.pack(evs)
+    m.tune_set("ffn", 0)  # the FFN as two products, so that their tiles apply
     for tile in range(B.Model.tune_count("qkv")):
         for op in GEMM_OPS:
             m.tune_set(op, tile)
@@ -242,6 +243,7 @@ def test_persistent_gemm_bitwise(B, prec):
     w, m = _model(B, synth.FULL, 14, prec)
     pk = synth.pack(synth.event_set(400, 12, lo=1500))
     tiles = [B.Model.tune_shape("qkv", t) for t in range(B.Model.tune_count("qkv"))]
+    m.tune_set("ffn", 0)
     results = {}
     for t, spec in enumerate(tiles):
         for op in GEMM_OPS:
@@ -254,3 +256,26 @@ def test_persistent_gemm_bitwise(B, prec):
                     all(o[k] == spec[k] for k in ("bm", "bn", "wm", "wn", "bkb")))
         for k in ("logits", "reg"):
             np.testing.assert_array_equal(results[t][k], results[twin][k], err_msg=f"tile {t} vs {twin} {k}")
+
+
+@pytest.mark.parametrize("cfg", [synth.FULL, synth.SMALL,
+                                 synth.Config(d_model=128, n_heads=4, d_ff=192, n_layers=2)],
+                         ids=["d256", "d64", "d128"])
+def test_fused_ffn_bitwise(B, cfg):
+    """The fused FFN kernel (BF16) gives the same bits as the two-product FFN, on ragged events
+    with garbage padding; both paths are also within tolerance of the oracle elsewhere."""
+    w, m = _model(B, cfg, 15, "bf16", sharpen=2.0)
+    evs = [synth.make_event(5000 + i, n) for i, n in enumerate([300, 1, 129, 64, 1000])]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=9)
+    fused = run_gpu(m, pk)
+    m.tune_set("ffn", 0)
+    for tile in (-1, 6, 9):
+        for op in ("ffn1", "ffn2"):
+            m.tune_set(op, tile)
+        two = run_gpu(m, pk)
+        for e in range(pk.n_events):
+            r = pk.event_rows(e)
+            for k in ("logits", "reg", "cls"):
+                np.testing.assert_array_equal(fused[k][r], two[k][r], err_msg=f"tile {tile} {k}")
+    with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
+        B.Model(cfg, w, "fp32").tune_set("ffn", 1)
