@@ -27,6 +27,22 @@ METRIC = "events/sec + p50/p99 ms/event, BF16 varlen vs FP32 plain, 1 MI355X"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 EVENTS_PER_BATCH = 64
 
+# HBM bytes per launch of the BF16 attention kernel on these batches, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) of paper_2601_17554_amd/profile_run.py scaled by a 256 MiB copy
+# (profiles/attention_bf16_varlen64_hbm_traffic.md). Valid only for the kernel source it was
+# measured on: reported as null once attention.hip, common.h or kernels.h change.
+ATTN_TRAFFIC = {"sha256": "e3582b704d452b163062cd022738067d51df5d1978f7957bbd8b3a564f7570be",
+                "bytes_per_launch": 453141111.7}
+
+
+def attention_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("attention.hip", "common.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2601_17554_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return ATTN_TRAFFIC["bytes_per_launch"] if h.hexdigest() == ATTN_TRAFFIC["sha256"] else None
+
 
 def attention_flops(n: np.ndarray, cfg) -> float:
     """Algorithmic FLOPs of one attention launch (one layer): 4 d sum_e n_e^2."""
@@ -248,7 +264,8 @@ def main():
         },
         "roofline": {"bound": "mfma", "kernel": "attention", "achieved": round(achieved, 1),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": None, "avg_launch_ms": round(attn_avg_ms, 4)},
+                     "traffic": attention_traffic() if args.precision == "bf16" else None,
+                     "traffic_unit": "bytes per launch (HBM)", "avg_launch_ms": round(attn_avg_ms, 4)},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in vr["prof"].items()},
     }
     if args.serve_rates:

@@ -401,12 +401,14 @@ mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const v
   at.ev_n = (const int32_t*)cx.p(cx.w.ev_n);
   at.cap_items = cx.w.cap_items;
   const int tile = attn_tile_of(m);
-  ProfScope prof(cx.m, MLPF_PROF_ATTENTION, cx.s);
   if (m->kprec == P_BF16 && attn_tile(tile).kind == 1) {
+    // Squared key norms for the score bound (timed with the QKV projection that produces K).
+    ProfScope prof(cx.m, MLPF_PROF_QKV, cx.s);
     float* kn = (float*)cx.p(cx.w.knorm);
     HIP_TRY(launch_keynorm(k, kn, (int64_t)cx.b->total_rows * m->cfg.n_heads, m->dh, cx.s), "keynorm launch");
     at.knorm = kn;
   }
+  ProfScope prof(cx.m, MLPF_PROF_ATTENTION, cx.s);
   HIP_TRY(launch_attention(m->kprec, tile, at, cx.s), "attention launch");
   return MLPF_OK;
 }
