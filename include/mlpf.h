@@ -119,22 +119,27 @@ mlpf_status_t mlpf_model_destroy(mlpf_model_t model); /* does not touch dev_weig
  * n_events events. A workspace may be reused by consecutive calls on one stream. */
 size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t n_events);
 
-/* Element embedding FFN (Sec. 5.3): h[T][d] (FP32) = GELU(x W_e1 + b_e1) W_e2 + b_e2 for every row,
+/* The residual stream h ([S][T][d] below) is held in the model's activation type: FP32 for
+ * MLPF_FP32, bf16 (raw 16-bit values) for MLPF_BF16 and MLPF_BF16_FP8FFN, as in a BF16
+ * mixed-precision pre-LN block, whose embedding and residual branches all end in a bf16 product;
+ * every residual sum is taken in FP32 and rounded once. */
+
+/* Element embedding FFN (Sec. 5.3): h[T][d] = GELU(x W_e1 + b_e1) W_e2 + b_e2 for every row,
  * x[T][F] FP32. */
-mlpf_status_t mlpf_embed(mlpf_model_t model, const float* x, const mlpf_batch_t* batch, float* h,
+mlpf_status_t mlpf_embed(mlpf_model_t model, const float* x, const mlpf_batch_t* batch, void* h,
                          void* ws, size_t ws_bytes, void* stream);
 
-/* The transformer encoder (Sec. 5.3, Eq. 4), in place on h, FP32 [S][T][d]: S = 1 for
+/* The transformer encoder (Sec. 5.3, Eq. 4), in place on h [S][T][d]: S = 1 for
  * MLPF_TOPO_SERIAL, 2 for MLPF_TOPO_PARALLEL2. On entry h[0] holds the embedding; on return h[s]
  * holds stack s's output (h[1] is overwritten for PARALLEL2). */
-mlpf_status_t mlpf_encoder_forward(mlpf_model_t model, float* h, const mlpf_batch_t* batch,
+mlpf_status_t mlpf_encoder_forward(mlpf_model_t model, void* h, const mlpf_batch_t* batch,
                                    void* ws, size_t ws_bytes, void* stream);
 
-/* Output heads and the inference rule (Sec. 5.3, Eq. 2): from h (FP32 [S][T][d], as left by
+/* Output heads and the inference rule (Sec. 5.3, Eq. 2): from h ([S][T][d], as left by
  * mlpf_encoder_forward) writes logits[T][6], reg[T][5] (pT', eta, sin phi, cos phi, E'), and
  * cls[T] = argmax of the logits (int32). If prim (FP32 [T][2]: primary pT, E) and decoded
  * (FP32 [T][4]) are both non-NULL, decoded gets (pT, eta, phi, E). */
-mlpf_status_t mlpf_heads(mlpf_model_t model, const float* h, const mlpf_batch_t* batch,
+mlpf_status_t mlpf_heads(mlpf_model_t model, const void* h, const mlpf_batch_t* batch,
                          float* logits, float* reg, int32_t* cls, const float* prim,
                          float* decoded, void* ws, size_t ws_bytes, void* stream);
 

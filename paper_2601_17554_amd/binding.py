@@ -358,10 +358,15 @@ class Model:
     def embed(self, x, batch: Batch, ws=None) -> torch.Tensor:
         if ws is None:
             ws = self.workspace(batch.total_rows, batch.n_events)
-        h = torch.empty(self.stacks, batch.total_rows, self.cfg.d_model, dtype=torch.float32,
+        h = torch.empty(self.stacks, batch.total_rows, self.cfg.d_model, dtype=self.residual_dtype,
                         device=self.device)
         mlpf_embed(self, x, batch, h, ws)
         return h
+
+    @property
+    def residual_dtype(self) -> torch.dtype:
+        """Element type of the residual stream h: float32 for fp32 models, bfloat16 otherwise."""
+        return torch.float32 if self.precision == "fp32" else torch.bfloat16
 
     def encoder(self, h: torch.Tensor, batch: Batch, ws=None) -> torch.Tensor:
         if ws is None:

@@ -178,6 +178,7 @@ struct mlpf_model_s {
   Prec kprec;
   int dh;
   int stacks;
+  int hbytes;  // bytes per residual-stream element: 4 (MLPF_FP32) or 2 (bf16, the BF16 modes)
   WeightPlan plan;
   const char* base;  // device weight buffer
   // Launch choices (tile ids, -1 = size-based rule), set by mlpf_tune_set.
@@ -226,7 +227,7 @@ WsPlan plan_ws(const mlpf_model_s* m, int64_t T, int64_t E) {
   w.y = take(td * eb);
   const size_t uw = std::max<size_t>((size_t)c.d_ff, 5 * (size_t)c.d_model);
   w.u = take((size_t)T * uw * eb);
-  w.h = take((size_t)m->stacks * td * 4);
+  w.h = take((size_t)m->stacks * td * m->hbytes);
   w.total = off;
   return w;
 }
@@ -308,12 +309,13 @@ mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a, int 
 }
 
 // y = LayerNorm(h) in the operand type (the A operand of the next product).
-mlpf_status_t run_layernorm(const Ctx& cx, const float* h, size_t g_off, size_t b_off,
+mlpf_status_t run_layernorm(const Ctx& cx, const void* h, size_t g_off, size_t b_off,
                             int prec = -1, float out_scale = 1.f, float* amax = nullptr) {
   LayerNormArgs a;
   a.out_scale = out_scale;
   a.amax = amax;
   a.x = h;
+  a.x_bf16 = cx.m->hbytes == 2;
   a.y = cx.p(cx.w.y);
   a.rows = cx.b->total_rows;
   a.d = cx.m->cfg.d_model;
@@ -325,7 +327,7 @@ mlpf_status_t run_layernorm(const Ctx& cx, const float* h, size_t g_off, size_t 
   return MLPF_OK;
 }
 
-mlpf_status_t do_embed(const Ctx& cx, const float* x, float* h) {
+mlpf_status_t do_embed(const Ctx& cx, const float* x, void* h) {
   const mlpf_model_s* m = cx.m;
   ProfScope prof(cx.m, MLPF_PROF_EMBED, cx.s);
   const int T = cx.b->total_rows, d = m->cfg.d_model;
@@ -354,7 +356,7 @@ mlpf_status_t do_embed(const Ctx& cx, const float* x, float* h) {
   b.bias = m->atf(m->plan.e_b2);
   b.out = h;
   b.ldo = d;
-  return run_gemm(cx, MLPF_OP_EMBED2, A_PLAIN, E_BIAS, b);
+  return run_gemm(cx, MLPF_OP_EMBED2, A_PLAIN, m->hbytes == 2 ? E_BIAS_B : E_BIAS, b);
 }
 
 mlpf_status_t do_worklist(Ctx& cx) {
@@ -418,7 +420,7 @@ bool ffn_fused_on(const mlpf_model_s* m) {
   return m->plan.ffn_fused && m->tune[MLPF_OP_FFN] != 0;
 }
 
-mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
+mlpf_status_t do_layer(const Ctx& cx, int layer, void* h) {
   const mlpf_model_s* m = cx.m;
   const mlpf_config_t& c = m->cfg;
   const Layer& L = m->plan.layers[layer];
@@ -462,7 +464,7 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
   o.ldo = d;
   {
     ProfScope prof(cx.m, MLPF_PROF_OUTPROJ, cx.s);
-    if ((st = run_gemm(cx, MLPF_OP_OUTPROJ, A_PLAIN, E_RESID, o))) return st;
+    if ((st = run_gemm(cx, MLPF_OP_OUTPROJ, A_PLAIN, m->hbytes == 2 ? E_RESID_B : E_RESID, o))) return st;
   }
   // LN2 + FFN1 + GELU, FFN2 + residual. FP8 mode: LN2 writes E4M3 (scaled by 1/s_a1), FFN1
   // dequantises with s_a1 s_w1 and writes GELU output as E4M3 (1/s_a2), FFN2 dequantises with
@@ -523,10 +525,10 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, float* h) {
   f2.ldo = d;
   if (fp8) f2.acc_scale = L.s_a2 * L.s_w2;
   ProfScope prof(cx.m, MLPF_PROF_FFN2, cx.s);
-  return run_gemm(cx, MLPF_OP_FFN2, A_PLAIN, E_RESID, f2, fp8 ? P_FP8 : -1);
+  return run_gemm(cx, MLPF_OP_FFN2, A_PLAIN, m->hbytes == 2 ? E_RESID_B : E_RESID, f2, fp8 ? P_FP8 : -1);
 }
 
-mlpf_status_t do_encoder(Ctx& cx, float* h) {
+mlpf_status_t do_encoder(Ctx& cx, void* h) {
   const mlpf_model_s* m = cx.m;
   const int64_t td = (int64_t)cx.b->total_rows * m->cfg.d_model;
   if (cx.b->total_rows == 0) return MLPF_OK;
@@ -536,17 +538,18 @@ mlpf_status_t do_encoder(Ctx& cx, float* h) {
     for (int l = 0; l < m->cfg.n_layers; ++l)
       if ((st = do_layer(cx, l, h))) return st;
   } else {
-    HIP_TRY(launch_copy_f32(h + td, h, td, cx.s), "copy launch");
+    void* h1 = (char*)h + td * m->hbytes;
+    HIP_TRY(launch_copy_f32((float*)h1, (const float*)h, td * m->hbytes / 4, cx.s), "copy launch");
     const int half = m->cfg.n_layers / 2;
     for (int l = 0; l < half; ++l)
       if ((st = do_layer(cx, l, h))) return st;
     for (int l = half; l < m->cfg.n_layers; ++l)
-      if ((st = do_layer(cx, l, h + td))) return st;
+      if ((st = do_layer(cx, l, h1))) return st;
   }
   return MLPF_OK;
 }
 
-mlpf_status_t do_heads(const Ctx& cx, const float* h, float* logits, float* reg, int32_t* cls,
+mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, int32_t* cls,
                        const float* prim, float* decoded) {
   const mlpf_model_s* m = cx.m;
   const int T = cx.b->total_rows, d = m->cfg.d_model;
@@ -562,7 +565,7 @@ mlpf_status_t do_heads(const Ctx& cx, const float* h, float* logits, float* reg,
     const int c0 = (groups == 1) ? 0 : (g == 0 ? 0 : d);
     const int nc = (groups == 1) ? 5 * d : (g == 0 ? d : 4 * d);
     GemmArgs a;
-    a.a = h + (g == 0 ? 0 : td);
+    a.a = (const char*)h + (g == 0 ? 0 : td * m->hbytes);
     a.lda = d;
     a.M = T;
     a.N = nc;
@@ -572,7 +575,7 @@ mlpf_status_t do_heads(const Ctx& cx, const float* h, float* logits, float* reg,
     a.bias = m->atf(m->plan.h_b1) + c0;
     a.out = (char*)cx.p(cx.w.u) + (size_t)c0 * eb;
     a.ldo = 5 * d;
-    if ((st = run_gemm(cx, MLPF_OP_HEADS1, A_F32, E_GELU, a))) return st;
+    if ((st = run_gemm(cx, MLPF_OP_HEADS1, m->hbytes == 2 ? A_PLAIN : A_F32, E_GELU, a))) return st;
   }
   Heads2Args p;
   p.uh = cx.p(cx.w.u);
@@ -747,6 +750,7 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
   m->kprec = precision == MLPF_FP32 ? P_F32 : P_BF16;
   m->dh = d / c.n_heads;
   m->stacks = c.topology == MLPF_TOPO_PARALLEL2 ? 2 : 1;
+  m->hbytes = precision == MLPF_FP32 ? 4 : 2;
   m->plan = plan;
   m->base = (const char*)dev_weights;
   for (int& t : m->tune) t = -1;
@@ -770,7 +774,7 @@ size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t n_ev
   return plan_ws(model, total_rows, n_events).total;
 }
 
-mlpf_status_t mlpf_embed(mlpf_model_t model, const float* x, const mlpf_batch_t* batch, float* h,
+mlpf_status_t mlpf_embed(mlpf_model_t model, const float* x, const mlpf_batch_t* batch, void* h,
                          void* ws, size_t ws_bytes, void* stream) {
   Ctx cx;
   mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, false, &cx);
@@ -779,7 +783,7 @@ mlpf_status_t mlpf_embed(mlpf_model_t model, const float* x, const mlpf_batch_t*
   return do_embed(cx, x, h);
 }
 
-mlpf_status_t mlpf_encoder_forward(mlpf_model_t model, float* h, const mlpf_batch_t* batch,
+mlpf_status_t mlpf_encoder_forward(mlpf_model_t model, void* h, const mlpf_batch_t* batch,
                                    void* ws, size_t ws_bytes, void* stream) {
   Ctx cx;
   mlpf_status_t st = make_ctx(model, batch, ws, ws_bytes, stream, false, &cx);
@@ -788,7 +792,7 @@ mlpf_status_t mlpf_encoder_forward(mlpf_model_t model, float* h, const mlpf_batc
   return do_encoder(cx, h);
 }
 
-mlpf_status_t mlpf_heads(mlpf_model_t model, const float* h, const mlpf_batch_t* batch,
+mlpf_status_t mlpf_heads(mlpf_model_t model, const void* h, const mlpf_batch_t* batch,
                          float* logits, float* reg, int32_t* cls, const float* prim,
                          float* decoded, void* ws, size_t ws_bytes, void* stream) {
   Ctx cx;
@@ -808,7 +812,7 @@ mlpf_status_t mlpf_reconstruct_events(mlpf_model_t model, const float* x,
   if (st) return st;
   if (batch->total_rows == 0) return MLPF_OK;
   if (!x || !logits || !reg || !cls) return fail(MLPF_ERR_INVALID_ARG, "x or an output is NULL");
-  float* h = (float*)cx.p(cx.w.h);
+  void* h = cx.p(cx.w.h);
   // The work list first: it also yields the live row count that lets every kernel skip rows
   // beyond the last event (a captured graph sized for a capacity then does no dead work).
   if ((st = do_worklist(cx))) return st;
@@ -957,7 +961,7 @@ mlpf_status_t mlpf_calibrate_fp8(mlpf_model_t model, const float* x, const mlpf_
   if (batch->total_rows == 0) return MLPF_OK;
   if (!x || !amax) return fail(MLPF_ERR_INVALID_ARG, "x or amax is NULL");
   cx.calib = amax;
-  float* h = (float*)cx.p(cx.w.h);
+  void* h = cx.p(cx.w.h);
   if ((st = do_worklist(cx))) return st;
   if ((st = do_embed(cx, x, h))) return st;
   return do_encoder(cx, h);

@@ -1,5 +1,5 @@
 // Fused position-wise feed-forward block of one encoder layer, BF16 (paper Sec. 5.3):
-//   h[M][D] += GELU(y W1 + b1) W2 + b2,   y = LN2(h) in bf16, W1 [D][d_ff], W2 [d_ff][D].
+//   h[M][D] += GELU(y W1 + b1) W2 + b2,   y = LN2(h), h and y in bf16, W1 [D][d_ff], W2 [d_ff][D].
 // The d_ff-wide intermediate never leaves the workgroup: it is produced and consumed in chunks of
 // kFfnHC hidden units. A workgroup owns kFfnBM rows; per chunk
 //   phase 1: U^T = W1_c^T y^T (32x32 MFMA blocks; y's fragments stay in registers for the whole
@@ -147,8 +147,9 @@ __global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
     __syncthreads();
   }
 
-  // Epilogue: out + b2 staged through LDS as FP32 rows, then h += out in 16-byte row chunks.
-  // Lane l of a 32x32 block holds column l%32 of rows 8*(r/4) + 4*(l/32) + r%4.
+  // Epilogue: out + b2 staged through LDS as FP32 rows, then h = bf16(h + out) in 16-byte row
+  // chunks (8 values; the sum in FP32). Lane l of a 32x32 block holds column l%32 of rows
+  // 8*(r/4) + 4*(l/32) + r%4.
 #pragma unroll
   for (int a = 0; a < FM2; ++a)
 #pragma unroll
@@ -162,13 +163,19 @@ __global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
       }
     }
   __syncthreads();
-  constexpr int CPR = D / 4;
+  constexpr int CPR = D / 8;
   for (int t = tid; t < kFfnBM * CPR; t += kFfnNT) {
-    const int row = t / CPR, col = (t % CPR) * 4;
+    const int row = t / CPR, col = (t % CPR) * 8;
     if (m0 + row >= M) continue;
-    f32x4* dst = (f32x4*)(p.h + (int64_t)(m0 + row) * D + col);
-    const f32x4 v = *(const f32x4*)(smem + row * L::SRS + col * 4);
-    *dst = v + *dst;
+    u32x4* dst = (u32x4*)((__bf16*)p.h + (int64_t)(m0 + row) * D + col);
+    const u32x4 o = *dst;
+    const f32x4 v0 = *(const f32x4*)(smem + row * L::SRS + col * 4);
+    const f32x4 v1 = *(const f32x4*)(smem + row * L::SRS + col * 4 + 16);
+    const u32x2 lo = pack_bf16x4(v0[0] + __uint_as_float(o[0] << 16), v0[1] + __uint_as_float(o[0] & 0xffff0000u),
+                                 v0[2] + __uint_as_float(o[1] << 16), v0[3] + __uint_as_float(o[1] & 0xffff0000u));
+    const u32x2 hi = pack_bf16x4(v1[0] + __uint_as_float(o[2] << 16), v1[1] + __uint_as_float(o[2] & 0xffff0000u),
+                                 v1[2] + __uint_as_float(o[3] << 16), v1[3] + __uint_as_float(o[3] & 0xffff0000u));
+    *dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
   }
 }
 

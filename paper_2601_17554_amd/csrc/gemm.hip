@@ -11,6 +11,7 @@
 // them. LDS rows are padded by 16 bytes so that the 32 rows read by one MFMA operand load fall
 // in different banks. The epilogue is staged through the same LDS (see below).
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -195,7 +196,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   constexpr int PASSES = (BM * SRS <= 2 * (A_BYTES + B_BYTES)) ? 1 : WM;
   constexpr int PROWS = BM / PASSES;                     // rows staged per pass
   static_assert(PROWS * SRS <= 2 * (A_BYTES + B_BYTES), "epilogue staging does not fit");
-  constexpr int OSZ = (EPI == E_BIAS || EPI == E_RESID) ? 4 : (int)sizeof(S);
+  constexpr bool kResF32 = (EPI == E_BIAS || EPI == E_RESID);
+  constexpr bool kResB16 = (EPI == E_BIAS_B || EPI == E_RESID_B);
+  constexpr int OSZ = kResF32 ? 4 : kResB16 ? 2 : (int)sizeof(S);
   constexpr int EO = 16 / OSZ;                           // output elements per 16-byte chunk
 #pragma unroll
   for (int pass = 0; pass < PASSES; ++pass) {
@@ -227,11 +230,24 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
       const int row = m0 + pass * PROWS + lrow, col = n0 + lc;
       if (row >= M || col >= p.N) continue;
       const float* src = (const float*)(smem + lrow * SRS + lc * 4);
-      if constexpr (EPI == E_BIAS || EPI == E_RESID) {
+      if constexpr (kResF32) {
         f32x4 v = *(const f32x4*)src;
         f32x4* dst = (f32x4*)((float*)p.out + (int64_t)row * p.ldo + col);
         if constexpr (EPI == E_RESID) v += *dst;
         *dst = v;
+      } else if constexpr (kResB16) {
+        f32x4 v0 = *(const f32x4*)src, v1 = *(const f32x4*)(src + 4);
+        u32x4* dst = (u32x4*)((__bf16*)p.out + (int64_t)row * p.ldo + col);
+        if constexpr (EPI == E_RESID_B) {
+          const u32x4 o = *dst;
+          v0 += f32x4{__uint_as_float(o[0] << 16), __uint_as_float(o[0] & 0xffff0000u),
+                      __uint_as_float(o[1] << 16), __uint_as_float(o[1] & 0xffff0000u)};
+          v1 += f32x4{__uint_as_float(o[2] << 16), __uint_as_float(o[2] & 0xffff0000u),
+                      __uint_as_float(o[3] << 16), __uint_as_float(o[3] & 0xffff0000u)};
+        }
+        const u32x2 lo = pack_bf16x4(v0[0], v0[1], v0[2], v0[3]);
+        const u32x2 hi = pack_bf16x4(v1[0], v1[1], v1[2], v1[3]);
+        *dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
       } else {
         float qs = 1.f;
         S* dst;
@@ -361,6 +377,10 @@ hipError_t launch_prec(ALoad aload, Epi epi, int tile, const GemmArgs& p, hipStr
   if (aload == A_PLAIN && epi == E_QKV) return launch_tile<T, A_PLAIN, E_QKV>(tile, p, s);
   if (aload == A_PLAIN && epi == E_RESID) return launch_tile<T, A_PLAIN, E_RESID>(tile, p, s);
   if (aload == A_PLAIN && epi == E_GELU) return launch_tile<T, A_PLAIN, E_GELU>(tile, p, s);
+  if constexpr (!std::is_same_v<T, F32>) {
+    if (aload == A_PLAIN && epi == E_BIAS_B) return launch_tile<T, A_PLAIN, E_BIAS_B>(tile, p, s);
+    if (aload == A_PLAIN && epi == E_RESID_B) return launch_tile<T, A_PLAIN, E_RESID_B>(tile, p, s);
+  }
   if (aload == A_F32 && epi == E_GELU) return launch_tile<T, A_F32, E_GELU>(tile, p, s);
   return hipErrorInvalidValue;
 }
@@ -378,6 +398,7 @@ hipError_t launch_gemm(Prec prec, ALoad aload, Epi epi, int tile, const GemmArgs
     // FP8 runs the two FFN products only (operands quantised by their producers).
     if (aload == A_PLAIN && epi == E_GELU) return launch_tile<FP8, A_PLAIN, E_GELU>(tile, p, s);
     if (aload == A_PLAIN && epi == E_RESID) return launch_tile<FP8, A_PLAIN, E_RESID>(tile, p, s);
+    if (aload == A_PLAIN && epi == E_RESID_B) return launch_tile<FP8, A_PLAIN, E_RESID_B>(tile, p, s);
   }
   return hipErrorInvalidValue;
 }

@@ -17,10 +17,12 @@ enum ALoad {
 
 // What the GEMM does with acc = A W (+ bias) for each output element.
 enum Epi {
-  E_BIAS = 0,   // out_f32[row][col] = acc + bias
-  E_RESID = 1,  // out_f32[row][col] += acc + bias           (residual update, in place)
-  E_GELU = 2,   // out_T[row][col] = GELU(acc + bias)
-  E_QKV = 3,    // Q (scaled), K, V written head-major [head][row][d_head] in the operand type
+  E_BIAS = 0,    // out_f32[row][col] = acc + bias
+  E_RESID = 1,   // out_f32[row][col] += acc + bias           (residual update, in place)
+  E_GELU = 2,    // out_T[row][col] = GELU(acc + bias)
+  E_QKV = 3,     // Q (scaled), K, V written head-major [head][row][d_head] in the operand type
+  E_BIAS_B = 4,  // out_bf16[row][col] = acc + bias            (bf16 residual stream)
+  E_RESID_B = 5, // out_bf16[row][col] = bf16(out + acc + bias), the sum taken in FP32
 };
 
 struct GemmArgs {
@@ -68,7 +70,7 @@ struct FfnArgs {
   const float* b1 = nullptr;
   const void* w2p = nullptr;
   const float* b2 = nullptr;
-  float* h = nullptr;           // FP32 [M][d_model], updated in place
+  void* h = nullptr;            // bf16 [M][d_model], updated in place (sum taken in FP32)
 };
 int ffn_fused_supported(int d_model, int d_ff);
 // Bytes of the packed W1 (which = 1) or W2 (which = 2) image.
@@ -134,9 +136,10 @@ struct Heads2Args {
 };
 hipError_t launch_heads2(Prec prec, const Heads2Args& args, hipStream_t stream);
 
-// LayerNorm of FP32 rows [rows][d] into y [rows][d] of the operand type.
+// LayerNorm of FP32 or bf16 rows [rows][d] into y [rows][d] of the operand type.
 struct LayerNormArgs {
-  const float* x = nullptr;
+  const void* x = nullptr;
+  int x_bf16 = 0;          // 1: x holds bf16 values
   void* y = nullptr;
   int rows = 0, d = 0;
   const int32_t* m_dev = nullptr;
@@ -152,7 +155,7 @@ hipError_t launch_layernorm(Prec prec, const LayerNormArgs& args, hipStream_t st
 hipError_t launch_scale(Prec prec, void* dst, const void* src, int64_t n, float scale,
                         hipStream_t stream);
 
-// Copies n floats (used to duplicate the embedding into the second stack of PARALLEL2).
+// Copies n 4-byte words (duplicates the embedding into the second stack of PARALLEL2).
 hipError_t launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t stream);
 
 }  // namespace mlpf

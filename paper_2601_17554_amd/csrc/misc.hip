@@ -154,20 +154,28 @@ hipError_t launch_heads2(Prec prec, const Heads2Args& p, hipStream_t s) {
 // One wave per row; the row stays in registers (d <= 1024: up to 4 float4 per lane), statistics
 // in FP32 with two passes over the registers (mean, then mean squared deviation = biased
 // variance).
-template <class S, int V>  // V = float4 chunks per lane
+template <class S, int V, int XB>  // V = 4-element chunks per lane, XB = bytes per input element
 __global__ __launch_bounds__(256) void layernorm_kernel(const LayerNormArgs p) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   int M = p.rows;
   if (p.m_dev) M = min(M, max(*p.m_dev, 0));
   if (row >= M) return;
-  const f32x4* x = (const f32x4*)(p.x + (int64_t)row * p.d);
   f32x4 v[V];
   float s = 0.f;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int c = lane + 64 * t;
-    v[t] = (4 * c < p.d) ? x[c] : f32x4{0.f, 0.f, 0.f, 0.f};
+    v[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (4 * c < p.d) {
+      if constexpr (XB == 4) {
+        v[t] = ((const f32x4*)((const float*)p.x + (int64_t)row * p.d))[c];
+      } else {
+        const u32x2 w = ((const u32x2*)((const __bf16*)p.x + (int64_t)row * p.d))[c];
+        v[t] = f32x4{__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xffff0000u),
+                     __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xffff0000u)};
+      }
+    }
     s += (v[t][0] + v[t][1]) + (v[t][2] + v[t][3]);
   }
   const float mu = wave_sum(s) / (float)p.d;
@@ -211,12 +219,21 @@ template <class S>
 hipError_t launch_ln_t(const LayerNormArgs& p, hipStream_t s) {
   const int grid = (p.rows + 3) / 4;
   const int v = (p.d + 255) / 256;
-  if (v <= 1)
-    hipLaunchKernelGGL((layernorm_kernel<S, 1>), dim3(grid), dim3(256), 0, s, p);
-  else if (v <= 2)
-    hipLaunchKernelGGL((layernorm_kernel<S, 2>), dim3(grid), dim3(256), 0, s, p);
-  else
-    hipLaunchKernelGGL((layernorm_kernel<S, 4>), dim3(grid), dim3(256), 0, s, p);
+  if (p.x_bf16) {
+    if (v <= 1)
+      hipLaunchKernelGGL((layernorm_kernel<S, 1, 2>), dim3(grid), dim3(256), 0, s, p);
+    else if (v <= 2)
+      hipLaunchKernelGGL((layernorm_kernel<S, 2, 2>), dim3(grid), dim3(256), 0, s, p);
+    else
+      hipLaunchKernelGGL((layernorm_kernel<S, 4, 2>), dim3(grid), dim3(256), 0, s, p);
+  } else {
+    if (v <= 1)
+      hipLaunchKernelGGL((layernorm_kernel<S, 1, 4>), dim3(grid), dim3(256), 0, s, p);
+    else if (v <= 2)
+      hipLaunchKernelGGL((layernorm_kernel<S, 2, 4>), dim3(grid), dim3(256), 0, s, p);
+    else
+      hipLaunchKernelGGL((layernorm_kernel<S, 4, 4>), dim3(grid), dim3(256), 0, s, p);
+  }
   return hipGetLastError();
 }
 

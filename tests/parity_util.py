@@ -56,6 +56,8 @@ def argmax_agreement(got_cls: np.ndarray, ref_logits: np.ndarray, tol: float):
 def check_event(got_all, ref, rows, tol: float, label: str = ""):
     got = {k: v[rows] for k, v in got_all.items()}
     e = errors(got, ref)
+    print(f"{label}: " + ", ".join(f"{k} {v:.2e}" for k, v in e.items() if not k.startswith("diag_")),
+          flush=True)
     bad = {k: v for k, v in e.items() if not k.startswith("diag_") and not v <= tol}
     assert not bad, f"{label}: errors above {tol}: {bad} (all: {e})"
     agree, raw, ties = argmax_agreement(got["cls"], ref["logits"], tol)
