@@ -201,10 +201,11 @@ typedef enum {
   MLPF_OP_EMBED1 = 0, MLPF_OP_EMBED2 = 1, MLPF_OP_QKV = 2, MLPF_OP_OUTPROJ = 3,
   MLPF_OP_FFN1 = 4, MLPF_OP_FFN2 = 5, MLPF_OP_HEADS1 = 6, MLPF_OP_ATTENTION = 7,
   /* How the feed-forward block runs: tile 0 = two products (FFN1 with GELU, FFN2 with the residual
-   * update, tiles of MLPF_OP_FFN1/FFN2 apply); tile 1 = one fused kernel that keeps the d_ff-wide
-   * intermediate on chip (MLPF_BF16 models with d_model 64, 128 or 256; their default, bitwise
-   * equal to tile 0 with any GEMM tiles). Setting 1 on another model returns
-   * MLPF_ERR_UNSUPPORTED. FP8 calibration always runs the two products. */
+   * update, tiles of MLPF_OP_FFN1/FFN2 apply); tiles 1 and 2 = one fused kernel that keeps the
+   * d_ff-wide intermediate on chip (1: 128 rows per workgroup, double-buffered weights, the
+   * default; 2: 64 rows, single-buffered, two workgroups per CU), for MLPF_BF16 models with d_model
+   * 64, 128 or 256, bitwise equal to tile 0 with any GEMM tiles. Setting 1 or 2 on another model
+   * returns MLPF_ERR_UNSUPPORTED. FP8 calibration always runs the two products. */
   MLPF_OP_FFN = 8,
   MLPF_OP_COUNT = 9
 } mlpf_op_t;
@@ -215,7 +216,8 @@ int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule *
  * columns, bytes per operand row and k-tile, persistent (1) or one workgroup per tile (0)};
  * MLPF_OP_ATTENTION {waves per workgroup, keys per LDS stage, 32-query blocks per wave, kernel
  * kind (0: online softmax with running maxima, 1: BF16 score-bound offset; FP32 runs kind 0),
- * 0, 0}; MLPF_OP_FFN {fused (1) or two products (0), 0, 0, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
+ * 0, 0}; MLPF_OP_FFN {fused (1) or two products (0), rows per workgroup, waves, double buffered,
+ * 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
 mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);
 
 /* FP8 activation calibration for MLPF_BF16_FP8FFN. Runs the embedding and encoder of `model` (an

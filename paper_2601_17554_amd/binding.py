@@ -307,7 +307,8 @@ class Model:
         kind}."""
         v = (ctypes.c_int32 * 6)()
         _check(load().mlpf_tune_shape(OPS.index(op), tile, v))
-        keys = (("waves", "kt", "qb", "kind") if op == "attention" else ("fused",) if op == "ffn"
+        keys = (("waves", "kt", "qb", "kind") if op == "attention" else
+                ("fused", "rows", "waves", "double_buffered") if op == "ffn"
                 else ("bm", "bn", "wm", "wn", "bkb", "persist"))
         return {k: int(v[i]) for i, k in enumerate(keys)}
 

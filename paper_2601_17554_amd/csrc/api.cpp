@@ -503,7 +503,8 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h) {
     a.w2p = m->at(L.w2p);
     a.b2 = m->atf(L.b2);
     a.h = h;
-    HIP_TRY(launch_ffn_fused(a, cx.s), "fused FFN launch");
+    HIP_TRY(launch_ffn_fused(a, m->tune[MLPF_OP_FFN] > 0 ? m->tune[MLPF_OP_FFN] : 1, cx.s),
+            "fused FFN launch");
     return MLPF_OK;
   }
   {
@@ -885,7 +886,7 @@ mlpf_status_t mlpf_graph_destroy(mlpf_graph_t graph) {
 
 int32_t mlpf_tune_count(int32_t op) {
   if (op < 0 || op >= MLPF_OP_COUNT) return 0;
-  if (op == MLPF_OP_FFN) return 2;
+  if (op == MLPF_OP_FFN) return 3;
   return op == MLPF_OP_ATTENTION ? attn_num_tiles() : gemm_num_tiles();
 }
 
@@ -894,7 +895,7 @@ mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile) {
   if (op < 0 || op >= MLPF_OP_COUNT) return fail(MLPF_ERR_INVALID_ARG, "op=%d out of range", op);
   if (tile < -1 || tile >= mlpf_tune_count(op))
     return fail(MLPF_ERR_INVALID_ARG, "tile=%d out of range for op %d", tile, op);
-  if (op == MLPF_OP_FFN && tile == 1 && !model->plan.ffn_fused)
+  if (op == MLPF_OP_FFN && tile >= 1 && !model->plan.ffn_fused)
     return fail(MLPF_ERR_UNSUPPORTED, "the fused FFN needs an MLPF_BF16 model with d_model 64, 128 or 256");
   model->tune[op] = tile;
   return MLPF_OK;
@@ -915,7 +916,9 @@ mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape) {
     const int32_t v[6] = {t.waves, t.kt, t.qb, t.kind, 0, 0};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else if (op == MLPF_OP_FFN) {
-    for (int i = 0; i < 6; ++i) shape[i] = i == 0 ? tile : 0;
+    const int32_t v[6] = {tile > 0, tile == 1 ? 128 : tile == 2 ? 64 : 0, tile == 1 ? 8 : tile == 2 ? 4 : 0,
+                          tile == 1, 0, 0};
+    for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else {
     const GemmTile t = gemm_tile(tile);
     const int32_t v[6] = {t.bm, t.bn, t.wm, t.wn, t.bkb, t.persist};

@@ -10,7 +10,9 @@
 // The weight chunks are stored pre-tiled in HBM exactly as their LDS images (padded rows, see
 // ffn_pack_bytes) and copied linearly with direct-to-LDS loads, double buffered: chunk c+1 travels
 // while chunk c is computed. The summation order over k (D in phase 1, d_ff in phase 2) is the order
-// of the unfused products, so the results match the two-GEMM path bit for bit.
+// of the unfused products, so the results match the two-GEMM path bit for bit. Two shapes: 128 rows
+// per workgroup of 8 waves with double-buffered weights, or 64 rows per workgroup of 4 waves with
+// single-buffered weights (two workgroups per CU).
 #include "common.h"
 #include "kernels.h"
 
@@ -18,56 +20,63 @@ namespace mlpf {
 
 namespace {
 
-constexpr int kFfnBM = 128;  // rows per workgroup
-constexpr int kFfnHC = 64;   // hidden units per chunk
-constexpr int kFfnNW = 8;    // waves per workgroup
-constexpr int kFfnNT = kFfnNW * 64;
+constexpr int kFfnHC = 64;  // hidden units per chunk
 
-template <int D>
+// LDS image of one workgroup: W1 and W2^T chunk buffers (two of each when double buffered), the U
+// tile, and (reusing the same bytes after the chunk loop) the FP32 epilogue staging.
+template <int D, int BM, bool DBUF>
 struct FfnLayout {
   static constexpr int W1RS = 2 * D + 16;       // W1 chunk row: one hidden unit, D k-values
   static constexpr int W1CH = kFfnHC * W1RS;
   static constexpr int W2RS = 2 * kFfnHC + 16;  // W2^T chunk row: one output, kFfnHC k-values
   static constexpr int W2CH = D * W2RS;
+  static constexpr int NBUF = DBUF ? 2 : 1;
   static constexpr int URS = 2 * kFfnHC + 16;   // U row: one token row, kFfnHC hidden units
-  static constexpr int U_BYTES = kFfnBM * URS;
-  static constexpr int LDS = 2 * W1CH + 2 * W2CH + U_BYTES;
+  static constexpr int U_BYTES = BM * URS;
+  static constexpr int LDS = NBUF * (W1CH + W2CH) + U_BYTES;
   static constexpr int SRS = 4 * D + 16;        // epilogue staging row (FP32)
-  static_assert(kFfnBM * SRS <= LDS, "epilogue staging does not fit");
+  static_assert(BM * SRS <= LDS, "epilogue staging does not fit");
 };
 
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) const void gbl_void;
 
-// Copies `bytes` (a multiple of 16) from global src to LDS dst: round r, wave w, lane l moves the
-// 16 bytes at offset r * 16 * kFfnNT + 1024 w + 16 l (direct-to-LDS loads write lane l's data at
-// the wave's LDS base + 16 l).
+// Copies `bytes` (a multiple of 16) from global src to LDS dst with NT threads: round r, wave w,
+// lane l moves the 16 bytes at offset 16 NT r + 1024 w + 16 l (direct-to-LDS loads write lane l's
+// data at the wave's LDS base + 16 l).
+template <int NT>
 __device__ __forceinline__ void copy_to_lds(const char* src, char* dst, int bytes, int wave, int lane) {
-  for (int base = wave * 1024; base < bytes; base += 16 * kFfnNT) {
+  for (int base = wave * 1024; base < bytes; base += 16 * NT) {
     const int off = base + 16 * lane;
     if (off < bytes)
       __builtin_amdgcn_global_load_lds((gbl_void*)(src + off), (lds_void*)(dst + base), 16, 0, 0);
   }
 }
 
-template <int D>
-__global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
-  using L = FfnLayout<D>;
+// BM rows per workgroup of NW waves. DBUF: the next chunk's W1 and W2 travel during the current
+// chunk (one workgroup per CU at d_model 256). Single buffered: W1 of chunk c+1 is fetched during
+// phase 2 of chunk c, W2 after it, and the LDS image is small enough for two workgroups per CU,
+// which then hide each other's waits.
+template <int D, int BM, int NW, bool DBUF>
+__global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
+  using L = FfnLayout<D, BM, DBUF>;
+  constexpr int NT = NW * 64;
   constexpr int KG1 = D / 16;                    // k-groups of phase 1
   constexpr int KG2 = kFfnHC / 16;               // k-groups of phase 2
   constexpr int WN2 = D / 32 < 4 ? D / 32 : 4;   // phase-2 wave grid (rows x columns)
-  constexpr int WM2 = kFfnNW / WN2;
-  constexpr int FM2 = (kFfnBM / 32) / WM2, FN2 = (D / 32) / WN2;
-  static_assert(FM2 >= 1 && FN2 >= 1 && (kFfnBM / 32) * (kFfnHC / 32) == kFfnNW, "bad FFN shape");
+  constexpr int WM2 = NW / WN2;
+  constexpr int FM2 = (BM / 32) / WM2, FN2 = (D / 32) / WN2;
+  static_assert(FM2 >= 1 && FN2 >= 1 && WM2 * FM2 * 32 == BM && (BM / 32) * (kFfnHC / 32) == NW,
+                "bad FFN shape");
 
   __shared__ __attribute__((aligned(16))) char smem[L::LDS];
-  char* const w1buf = smem;                      // [2][W1CH]
-  char* const w2buf = smem + 2 * L::W1CH;        // [2][W2CH]
-  char* const ubuf = w2buf + 2 * L::W2CH;        // [kFfnBM][URS]
+  char* const w1buf = smem;                      // [NBUF][W1CH]
+  char* const w2buf = smem + L::NBUF * L::W1CH;  // [NBUF][W2CH]
+  char* const ubuf = w2buf + L::NBUF * L::W2CH;  // [BM][URS]
 
   int M = p.M;
   if (p.m_dev) M = min(M, max(*p.m_dev, 0));
-  const int m0 = blockIdx.x * kFfnBM;
+  const int m0 = blockIdx.x * BM;
   if (m0 >= M) return;  // uniform over the workgroup
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -76,11 +85,11 @@ __global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
   const char* w1p = (const char*)p.w1p;
   const char* w2p = (const char*)p.w2p;
 
-  copy_to_lds(w1p, w1buf, L::W1CH, wave, lane);
-  copy_to_lds(w2p, w2buf, L::W2CH, wave, lane);
+  copy_to_lds<NT>(w1p, w1buf, L::W1CH, wave, lane);
+  copy_to_lds<NT>(w2p, w2buf, L::W2CH, wave, lane);
 
   // Phase-1 role: hidden block hb (32 units of the chunk) x token block tb (32 rows).
-  const int hb = wave / (kFfnBM / 32), tb = wave % (kFfnBM / 32);
+  const int hb = wave / (BM / 32), tb = wave % (BM / 32);
   // y fragments (B operand of U^T = W1^T y^T): lane holds row 32 tb + i, k = 16 g + 8 h .. + 7.
   u32x4 yf[KG1];
   {
@@ -102,10 +111,10 @@ __global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
   __syncthreads();
 
   for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) {
-      copy_to_lds(w1p + (size_t)(c + 1) * L::W1CH, w1buf + (buf ^ 1) * L::W1CH, L::W1CH, wave, lane);
-      copy_to_lds(w2p + (size_t)(c + 1) * L::W2CH, w2buf + (buf ^ 1) * L::W2CH, L::W2CH, wave, lane);
+    const int buf = DBUF ? (c & 1) : 0;
+    if (DBUF && c + 1 < nch) {
+      copy_to_lds<NT>(w1p + (size_t)(c + 1) * L::W1CH, w1buf + (buf ^ 1) * L::W1CH, L::W1CH, wave, lane);
+      copy_to_lds<NT>(w2p + (size_t)(c + 1) * L::W2CH, w2buf + (buf ^ 1) * L::W2CH, L::W2CH, wave, lane);
     }
     // Phase 1: this wave's 32x32 block of U^T, summed over k = 0 .. D-1 in order.
     {
@@ -125,6 +134,8 @@ __global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
       }
     }
     __syncthreads();
+    if (!DBUF && c + 1 < nch)  // W1 is free once every wave is past phase 1
+      copy_to_lds<NT>(w1p + (size_t)(c + 1) * L::W1CH, w1buf, L::W1CH, wave, lane);
     // Phase 2: O += U W2_c over the chunk's k-groups in order.
     {
       const char* w2 = w2buf + buf * L::W2CH;
@@ -143,7 +154,11 @@ __global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
           for (int b = 0; b < FN2; ++b) mma_kg<BF16>(af[a], bf[b], acc[a][b]);
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk c+1 have landed
+    if (!DBUF && c + 1 < nch) {
+      __syncthreads();  // W2 is free once every wave is past phase 2
+      copy_to_lds<NT>(w2p + (size_t)(c + 1) * L::W2CH, w2buf, L::W2CH, wave, lane);
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies for chunk c+1 have landed
     __syncthreads();
   }
 
@@ -164,7 +179,7 @@ __global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
     }
   __syncthreads();
   constexpr int CPR = D / 8;
-  for (int t = tid; t < kFfnBM * CPR; t += kFfnNT) {
+  for (int t = tid; t < BM * CPR; t += NT) {
     const int row = t / CPR, col = (t % CPR) * 8;
     if (m0 + row >= M) continue;
     u32x4* dst = (u32x4*)((__bf16*)p.h + (int64_t)(m0 + row) * D + col);
@@ -177,6 +192,19 @@ __global__ __launch_bounds__(kFfnNT) void ffn_fused_kernel(const FfnArgs p) {
                                  v1[2] + __uint_as_float(o[3] << 16), v1[3] + __uint_as_float(o[3] & 0xffff0000u));
     *dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
   }
+}
+
+template <int BM, int NW, bool DBUF>
+hipError_t launch_v(const FfnArgs& p, hipStream_t s) {
+  const int64_t grid = ((int64_t)p.M + BM - 1) / BM;
+  if (grid == 0) return hipSuccess;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  switch (p.d_model) {
+    case 64: hipLaunchKernelGGL((ffn_fused_kernel<64, BM, NW, DBUF>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
+    case 128: hipLaunchKernelGGL((ffn_fused_kernel<128, BM, NW, DBUF>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
+    default: hipLaunchKernelGGL((ffn_fused_kernel<256, BM, NW, DBUF>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -205,17 +233,11 @@ void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, u
   }
 }
 
-hipError_t launch_ffn_fused(const FfnArgs& p, hipStream_t s) {
+hipError_t launch_ffn_fused(const FfnArgs& p, int variant, hipStream_t s) {
   if (!ffn_fused_supported(p.d_model, p.d_ff)) return hipErrorInvalidValue;
-  const int64_t grid = ((int64_t)p.M + kFfnBM - 1) / kFfnBM;
-  if (grid == 0) return hipSuccess;
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  switch (p.d_model) {
-    case 64: hipLaunchKernelGGL(ffn_fused_kernel<64>, dim3((unsigned)grid), dim3(kFfnNT), 0, s, p); break;
-    case 128: hipLaunchKernelGGL(ffn_fused_kernel<128>, dim3((unsigned)grid), dim3(kFfnNT), 0, s, p); break;
-    default: hipLaunchKernelGGL(ffn_fused_kernel<256>, dim3((unsigned)grid), dim3(kFfnNT), 0, s, p); break;
-  }
-  return hipGetLastError();
+  if (variant == 1) return launch_v<128, 8, true>(p, s);
+  if (variant == 2) return launch_v<64, 4, false>(p, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace mlpf

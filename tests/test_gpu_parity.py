@@ -268,6 +268,10 @@ def test_fused_ffn_bitwise(B, cfg):
     evs = [synth.make_event(5000 + i, n) for i, n in enumerate([300, 1, 129, 64, 1000])]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=9)
     fused = run_gpu(m, pk)
+    m.tune_set("ffn", 2)
+    fused2 = run_gpu(m, pk)
+    for k in ("logits", "reg", "cls"):
+        np.testing.assert_array_equal(fused[k], fused2[k], err_msg=f"fused shapes {k}")
     m.tune_set("ffn", 0)
     for tile in (-1, 6, 9):
         for op in ("ffn1", "ffn2"):
