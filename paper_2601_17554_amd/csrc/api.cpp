@@ -386,7 +386,8 @@ mlpf_status_t do_worklist(Ctx& cx) {
 }
 
 // Attention over the work list built by do_worklist; q is pre-scaled by log2(e)/sqrt(d_head).
-mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const void* v, void* o) {
+mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const void* v, void* o,
+                            bool knorm_ready = false) {
   const mlpf_model_s* m = cx.m;
   AttnArgs at;
   at.q = q;
@@ -404,10 +405,14 @@ mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const v
   at.cap_items = cx.w.cap_items;
   const int tile = attn_tile_of(m);
   if (m->kprec == P_BF16 && attn_tile(tile).kind == 1) {
-    // Squared key norms for the score bound (timed with the QKV projection that produces K).
-    ProfScope prof(cx.m, MLPF_PROF_QKV, cx.s);
+    // Squared key norms for the score bound: written by the QKV projection in the forward pass,
+    // computed here for mlpf_attention_forward (timed with the QKV class).
     float* kn = (float*)cx.p(cx.w.knorm);
-    HIP_TRY(launch_keynorm(k, kn, (int64_t)cx.b->total_rows * m->cfg.n_heads, m->dh, cx.s), "keynorm launch");
+    if (!knorm_ready) {
+      ProfScope prof(cx.m, MLPF_PROF_QKV, cx.s);
+      HIP_TRY(launch_keynorm(k, kn, (int64_t)cx.b->total_rows * m->cfg.n_heads, m->dh, cx.s),
+              "keynorm launch");
+    }
     at.knorm = kn;
   }
   ProfScope prof(cx.m, MLPF_PROF_ATTENTION, cx.s);
@@ -443,13 +448,17 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h) {
   q.d = d;
   q.dh = dh;
   q.q_scale = (float)(1.4426950408889634 / std::sqrt((double)dh));
+  // The BF16 score-bound attention reads squared key norms: the projection's epilogue writes them.
+  const bool kn_fused = m->kprec == P_BF16 && attn_tile(attn_tile_of(m)).kind == 1;
+  if (kn_fused) q.knorm = (float*)cx.p(cx.w.knorm);
   {
     ProfScope prof(cx.m, MLPF_PROF_QKV, cx.s);
     if ((st = run_layernorm(cx, h, L.ln1g, L.ln1b))) return st;
     if ((st = run_gemm(cx, MLPF_OP_QKV, A_PLAIN, E_QKV, q))) return st;
   }
   // Attention.
-  if ((st = run_attention(cx, cx.p(cx.w.q), cx.p(cx.w.k), cx.p(cx.w.v), cx.p(cx.w.o)))) return st;
+  if ((st = run_attention(cx, cx.p(cx.w.q), cx.p(cx.w.k), cx.p(cx.w.v), cx.p(cx.w.o), kn_fused)))
+    return st;
   // Output projection + residual.
   GemmArgs o;
   o.a = cx.p(cx.w.o);

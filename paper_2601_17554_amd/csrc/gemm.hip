@@ -228,7 +228,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
     for (int c = tid; c < PROWS * CPR; c += NT) {
       const int lrow = c / CPR, lc = (c % CPR) * EO;
       const int row = m0 + pass * PROWS + lrow, col = n0 + lc;
-      if (row >= M || col >= p.N) continue;
+      const bool live = row < M && col < p.N;
+      [[maybe_unused]] float ss = 0.f;  // E_QKV with knorm: sum of squares of this K chunk
+      if (live) {
       const float* src = (const float*)(smem + lrow * SRS + lc * 4);
       if constexpr (kResF32) {
         f32x4 v = *(const f32x4*)src;
@@ -268,6 +270,16 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
           const u32x2 lo = pack_bf16x4(v0[0] * qs, v0[1] * qs, v0[2] * qs, v0[3] * qs);
           const u32x2 hi = pack_bf16x4(v1[0] * qs, v1[1] * qs, v1[2] * qs, v1[3] * qs);
           *(u32x4*)dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
+          if constexpr (EPI == E_QKV) {
+            if (p.knorm && col >= p.d && col < 2 * p.d) {
+              const u32x4 w = {lo[0], lo[1], hi[0], hi[1]};
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const float a = __uint_as_float(w[e] << 16), b = __uint_as_float(w[e] & 0xffff0000u);
+                ss = fmaf(a, a, fmaf(b, b, ss));
+              }
+            }
+          }
         } else {
           u32x4 o;
 #pragma unroll
@@ -277,6 +289,18 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
                               v[3] * p.out_scale);
           }
           *(u32x4*)dst = o;
+        }
+      }
+      }
+      if constexpr (EPI == E_QKV && sizeof(S) == 2) {
+        // Squared norm of each (row, head) of K from its bf16 values: the dh/8 chunks of one head
+        // are consecutive threads (the tile's columns start on a head boundary).
+        if (p.knorm) {
+          ss += __shfl_xor(ss, 1, 64);
+          if (p.dh == 32) ss += __shfl_xor(ss, 2, 64);
+          const int rem = col - p.d;
+          if (live && rem >= 0 && rem < p.d && rem % p.dh == 0)
+            p.knorm[(int64_t)(rem / p.dh) * (p.hstride / p.dh) + row] = ss;
         }
       }
     }

@@ -45,6 +45,7 @@ struct GemmArgs {
   int64_t hstride = 0;  // elements between heads in q/k/v (= rows capacity * d_head)
   int d = 0, dh = 0;
   float q_scale = 1.f;
+  float* knorm = nullptr;  // bf16 E_QKV: also write |k|^2 per (head, row), [H][hstride / dh]
 };
 
 // Tile shapes available to the GEMM (index = tile id). Each entry: BM, BN, BK(bytes-agnostic
