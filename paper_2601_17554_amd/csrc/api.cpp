@@ -425,7 +425,10 @@ bool ffn_fused_on(const mlpf_model_s* m) {
   return m->plan.ffn_fused && m->tune[MLPF_OP_FFN] != 0;
 }
 
-mlpf_status_t do_layer(const Ctx& cx, int layer, void* h) {
+// One encoder block. y_ready: y already holds LN1(h) (written by the previous block's fused FFN).
+// *y_next_out: set when this block's fused FFN also wrote the next block's LN1 into y.
+mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
+                       bool fuse_next_ln = false, bool* y_next_out = nullptr) {
   const mlpf_model_s* m = cx.m;
   const mlpf_config_t& c = m->cfg;
   const Layer& L = m->plan.layers[layer];
@@ -453,7 +456,7 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h) {
   if (kn_fused) q.knorm = (float*)cx.p(cx.w.knorm);
   {
     ProfScope prof(cx.m, MLPF_PROF_QKV, cx.s);
-    if ((st = run_layernorm(cx, h, L.ln1g, L.ln1b))) return st;
+    if (!y_ready && (st = run_layernorm(cx, h, L.ln1g, L.ln1b))) return st;
     if ((st = run_gemm(cx, MLPF_OP_QKV, A_PLAIN, E_QKV, q))) return st;
   }
   // Attention.
@@ -512,6 +515,14 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h) {
     a.w2p = m->at(L.w2p);
     a.b2 = m->atf(L.b2);
     a.h = h;
+    if (fuse_next_ln) {
+      const Layer& Ln = m->plan.layers[layer + 1];
+      a.y_next = cx.p(cx.w.y);
+      a.ln_g = m->atf(Ln.ln1g);
+      a.ln_b = m->atf(Ln.ln1b);
+      a.ln_eps = c.ln_eps;
+      if (y_next_out) *y_next_out = true;
+    }
     HIP_TRY(launch_ffn_fused(a, m->tune[MLPF_OP_FFN] > 0 ? m->tune[MLPF_OP_FFN] : 1, cx.s),
             "fused FFN launch");
     return MLPF_OK;
@@ -545,16 +556,24 @@ mlpf_status_t do_encoder(Ctx& cx, void* h) {
   mlpf_status_t st;
   if (!cx.n_rows && (st = do_worklist(cx))) return st;
   if (m->stacks == 1) {
-    for (int l = 0; l < m->cfg.n_layers; ++l)
-      if ((st = do_layer(cx, l, h))) return st;
+    bool y_ready = false;
+    for (int l = 0; l < m->cfg.n_layers; ++l) {
+      bool next = false;
+      if ((st = do_layer(cx, l, h, y_ready, l + 1 < m->cfg.n_layers, &next))) return st;
+      y_ready = next;
+    }
   } else {
     void* h1 = (char*)h + td * m->hbytes;
     HIP_TRY(launch_copy_f32((float*)h1, (const float*)h, td * m->hbytes / 4, cx.s), "copy launch");
     const int half = m->cfg.n_layers / 2;
-    for (int l = 0; l < half; ++l)
-      if ((st = do_layer(cx, l, h))) return st;
-    for (int l = half; l < m->cfg.n_layers; ++l)
-      if ((st = do_layer(cx, l, h1))) return st;
+    bool y_ready = false;
+    for (int l = 0; l < m->cfg.n_layers; ++l) {
+      // The next block's LN1 can only be fused within a stack (stack 1 starts from the embedding).
+      const bool same_stack_next = l + 1 < m->cfg.n_layers && l + 1 != half;
+      bool next = false;
+      if ((st = do_layer(cx, l, l < half ? h : h1, y_ready, same_stack_next, &next))) return st;
+      y_ready = next;
+    }
   }
   return MLPF_OK;
 }

@@ -147,6 +147,31 @@ __device__ __forceinline__ void atomic_max_nonneg(float* dst, float v) {
   atomicMax((int*)dst, __float_as_int(v));
 }
 
+// LayerNorm arithmetic (biased variance, Sec. 5.3), with floating-point contraction switched off so
+// that the LayerNorm kernel and the epilogues that fuse a LayerNorm produce the same bits.
+__device__ __forceinline__ float ln_sum4(float a, float b, float c, float d) {
+#pragma clang fp contract(off)
+  return (a + b) + (c + d);
+}
+__device__ __forceinline__ float ln_sq4(float a, float b, float c, float d, float mu) {
+#pragma clang fp contract(off)
+  const float x = a - mu, y = b - mu, z = c - mu, w = d - mu;
+  return (x * x + y * y) + (z * z + w * w);
+}
+__device__ __forceinline__ float ln_mean(float sum, int d) { return sum / (float)d; }
+__device__ __forceinline__ float ln_rstd(float sumsq, int d, float eps) {
+#pragma clang fp contract(off)
+  return 1.0f / sqrtf(sumsq / (float)d + eps);
+}
+__device__ __forceinline__ float ln_out(float v, float mu, float rs, float g, float b) {
+#pragma clang fp contract(off)
+  return __builtin_fmaf((v - mu) * rs, g, b);
+}
+__device__ __forceinline__ float add_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));

@@ -178,19 +178,53 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
       }
     }
   __syncthreads();
+  // CPR consecutive threads own one row (8 values each); they share the row's LayerNorm
+  // statistics when the next block's LN1 is fused here (y_next), with the reduction tree of the
+  // LayerNorm kernel (its lane l holds values 4l..4l+3: thread j = its lanes 2j, 2j+1), so the
+  // output matches that kernel bit for bit.
   constexpr int CPR = D / 8;
   for (int t = tid; t < BM * CPR; t += NT) {
     const int row = t / CPR, col = (t % CPR) * 8;
-    if (m0 + row >= M) continue;
+    const bool live = m0 + row < M;
     u32x4* dst = (u32x4*)((__bf16*)p.h + (int64_t)(m0 + row) * D + col);
-    const u32x4 o = *dst;
+    const u32x4 o = live ? *dst : u32x4{0, 0, 0, 0};
     const f32x4 v0 = *(const f32x4*)(smem + row * L::SRS + col * 4);
     const f32x4 v1 = *(const f32x4*)(smem + row * L::SRS + col * 4 + 16);
     const u32x2 lo = pack_bf16x4(v0[0] + __uint_as_float(o[0] << 16), v0[1] + __uint_as_float(o[0] & 0xffff0000u),
                                  v0[2] + __uint_as_float(o[1] << 16), v0[3] + __uint_as_float(o[1] & 0xffff0000u));
     const u32x2 hi = pack_bf16x4(v1[0] + __uint_as_float(o[2] << 16), v1[1] + __uint_as_float(o[2] & 0xffff0000u),
                                  v1[2] + __uint_as_float(o[3] << 16), v1[3] + __uint_as_float(o[3] & 0xffff0000u));
-    *dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
+    const u32x4 hn = u32x4{lo[0], lo[1], hi[0], hi[1]};
+    if (live) *dst = hn;
+    if (p.y_next) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        x[2 * e] = __uint_as_float(hn[e] << 16);
+        x[2 * e + 1] = __uint_as_float(hn[e] & 0xffff0000u);
+      }
+      float se = add_nc(0.f, ln_sum4(x[0], x[1], x[2], x[3])), so = add_nc(0.f, ln_sum4(x[4], x[5], x[6], x[7]));
+#pragma unroll
+      for (int off = CPR / 2; off >= 1; off >>= 1) {
+        se = add_nc(se, __shfl_xor(se, off, 64));
+        so = add_nc(so, __shfl_xor(so, off, 64));
+      }
+      const float mu = ln_mean(add_nc(se, so), D);
+      float qe = add_nc(0.f, ln_sq4(x[0], x[1], x[2], x[3], mu)), qo = add_nc(0.f, ln_sq4(x[4], x[5], x[6], x[7], mu));
+#pragma unroll
+      for (int off = CPR / 2; off >= 1; off >>= 1) {
+        qe = add_nc(qe, __shfl_xor(qe, off, 64));
+        qo = add_nc(qo, __shfl_xor(qo, off, 64));
+      }
+      const float rs = ln_rstd(add_nc(qe, qo), D, p.ln_eps);
+      const f32x4 g0 = *(const f32x4*)(p.ln_g + col), g1 = *(const f32x4*)(p.ln_g + col + 4);
+      const f32x4 b0 = *(const f32x4*)(p.ln_b + col), b1 = *(const f32x4*)(p.ln_b + col + 4);
+      const u32x2 ylo = pack_bf16x4(ln_out(x[0], mu, rs, g0[0], b0[0]), ln_out(x[1], mu, rs, g0[1], b0[1]),
+                                    ln_out(x[2], mu, rs, g0[2], b0[2]), ln_out(x[3], mu, rs, g0[3], b0[3]));
+      const u32x2 yhi = pack_bf16x4(ln_out(x[4], mu, rs, g1[0], b1[0]), ln_out(x[5], mu, rs, g1[1], b1[1]),
+                                    ln_out(x[6], mu, rs, g1[2], b1[2]), ln_out(x[7], mu, rs, g1[3], b1[3]));
+      if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)(m0 + row) * D + col) = u32x4{ylo[0], ylo[1], yhi[0], yhi[1]};
+    }
   }
 }
 

@@ -72,6 +72,12 @@ struct FfnArgs {
   const void* w2p = nullptr;
   const float* b2 = nullptr;
   void* h = nullptr;            // bf16 [M][d_model], updated in place (sum taken in FP32)
+  // Optional: the next block's LN1 of the updated h, written as bf16 [M][d_model] (the operand of
+  // the next QKV projection), bitwise equal to the LayerNorm kernel's output.
+  void* y_next = nullptr;
+  const float* ln_g = nullptr;
+  const float* ln_b = nullptr;
+  float ln_eps = 1e-5f;
 };
 int ffn_fused_supported(int d_model, int d_ff);
 // Bytes of the packed W1 (which = 1) or W2 (which = 2) image.

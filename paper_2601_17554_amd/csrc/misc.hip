@@ -176,19 +176,16 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const LayerNormArgs p) {
                      __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xffff0000u)};
       }
     }
-    s += (v[t][0] + v[t][1]) + (v[t][2] + v[t][3]);
+    s = add_nc(s, ln_sum4(v[t][0], v[t][1], v[t][2], v[t][3]));
   }
-  const float mu = wave_sum(s) / (float)p.d;
+  const float mu = ln_mean(wave_sum(s), p.d);
   float q = 0.f;
 #pragma unroll
   for (int t = 0; t < V; ++t) {
     const int c = lane + 64 * t;
-    if (4 * c < p.d) {
-      const float a = v[t][0] - mu, b = v[t][1] - mu, cc = v[t][2] - mu, dd = v[t][3] - mu;
-      q += (a * a + b * b) + (cc * cc + dd * dd);
-    }
+    if (4 * c < p.d) q = add_nc(q, ln_sq4(v[t][0], v[t][1], v[t][2], v[t][3], mu));
   }
-  const float rs = 1.0f / sqrtf(wave_sum(q) / (float)p.d + p.eps);
+  const float rs = ln_rstd(wave_sum(q), p.d, p.eps);
   S* y = (S*)p.y + (int64_t)row * p.d;
   float amax = 0.f;
 #pragma unroll
@@ -196,10 +193,10 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const LayerNormArgs p) {
     const int c = lane + 64 * t;
     if (4 * c >= p.d) continue;
     const f32x4 g = ((const f32x4*)p.gamma)[c], b = ((const f32x4*)p.beta)[c];
-    const float o0 = (v[t][0] - mu) * rs * g[0] + b[0];
-    const float o1 = (v[t][1] - mu) * rs * g[1] + b[1];
-    const float o2 = (v[t][2] - mu) * rs * g[2] + b[2];
-    const float o3 = (v[t][3] - mu) * rs * g[3] + b[3];
+    const float o0 = ln_out(v[t][0], mu, rs, g[0], b[0]);
+    const float o1 = ln_out(v[t][1], mu, rs, g[1], b[1]);
+    const float o2 = ln_out(v[t][2], mu, rs, g[2], b[2]);
+    const float o3 = ln_out(v[t][3], mu, rs, g[3], b[3]);
     amax = fmaxf(amax, fmaxf(fmaxf(fabsf(o0), fabsf(o1)), fmaxf(fabsf(o2), fabsf(o3))));
     if constexpr (sizeof(S) == 4)
       *(f32x4*)(y + 4 * c) = f32x4{o0, o1, o2, o3};
