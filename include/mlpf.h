@@ -178,8 +178,8 @@ typedef enum {
   MLPF_PROF_EMBED = 0,     /* both products of the embedding FFN */
   MLPF_PROF_QKV = 1,       /* LN1 + Q/K/V projection */
   MLPF_PROF_ATTENTION = 2, /* fused masked varlen attention */
-  MLPF_PROF_OUTPROJ = 3,   /* attention output projection + residual */
-  MLPF_PROF_FFN1 = 4,      /* LN2 + FFN1 + GELU */
+  MLPF_PROF_OUTPROJ = 3,   /* attention output projection + residual + LN2 */
+  MLPF_PROF_FFN1 = 4,      /* FFN1 + GELU (the whole fused FFN when it runs) */
   MLPF_PROF_FFN2 = 5,      /* FFN2 + residual */
   MLPF_PROF_HEADS = 6,     /* both head layers, argmax, decode */
   MLPF_PROF_WORKLIST = 7,  /* batch sanitising and attention work list */
@@ -207,7 +207,14 @@ typedef enum {
    * 64, 128 or 256, bitwise equal to tile 0 with any GEMM tiles. Setting 1 or 2 on another model
    * returns MLPF_ERR_UNSUPPORTED. FP8 calibration always runs the two products. */
   MLPF_OP_FFN = 8,
-  MLPF_OP_COUNT = 9
+  /* How the output heads run: tile 0 = the first-layer product (tiles of MLPF_OP_HEADS1 apply)
+   * writing the five GELU hidden layers, then a kernel for the second layer, argmax and decode;
+   * tile 1 = the first-layer product with 64 x 256 tiles whose epilogue also takes the second
+   * layer of its head (the hidden layer never leaves the chip), then a per-row kernel for the
+   * biases, argmax and decode (the default; bf16 models with d_model 256 only, else
+   * MLPF_ERR_UNSUPPORTED). The two differ by the order of the second-layer sums (rounding). */
+  MLPF_OP_HEADS = 9,
+  MLPF_OP_COUNT = 10
 } mlpf_op_t;
 int32_t mlpf_tune_count(int32_t op);
 mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile);
@@ -217,7 +224,7 @@ int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule *
  * MLPF_OP_ATTENTION {waves per workgroup, keys per LDS stage, 32-query blocks per wave, kernel
  * kind (0: online softmax with running maxima, 1: BF16 score-bound offset; FP32 runs kind 0),
  * 0, 0}; MLPF_OP_FFN {fused (1) or two products (0), rows per workgroup, waves, double buffered,
- * 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
+ * 0, 0}; MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
 mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);
 
 /* FP8 activation calibration for MLPF_BF16_FP8FFN. Runs the embedding and encoder of `model` (an

@@ -6,7 +6,8 @@ passes the correctness guard is pinned with mlpf_tune_set. The guard compares th
 each candidate with the reference run: GEMM tiles must give bitwise identical outputs where the
 library guarantees it (BF16 and FP8 always; FP32 for equal k-tile lengths), and otherwise agree to
 the rounding level of the precision (relative to the output scale: 1e-4 in FP32, 2e-2 in BF16 and
-FP8), as attention tiles must (they change only the order and offsets of the softmax sums). Choices are cached in a JSON file
+FP8), as attention tiles must (they change only the order and offsets of the softmax sums) and
+the fused heads (the order of the second-layer sums). Choices are cached in a JSON file
 (``MLPF_AUTOTUNE_CACHE``, default ``~/.cache/mlpf_autotune.json``) keyed by GPU architecture,
 precision, model sizes and the batch's size bucket.
 """
@@ -24,7 +25,11 @@ from . import binding as B
 # Profiler class that times each op (ops sharing a class are compared with the others fixed).
 _CLASS = {"embed1": ("embed",), "embed2": ("embed",), "qkv": ("qkv",), "outproj": ("outproj",),
           "ffn1": ("ffn1",), "ffn2": ("ffn2",), "heads1": ("heads",), "attention": ("attention",),
-          "ffn": ("ffn1", "ffn2")}
+          "ffn": ("ffn1", "ffn2"), "heads": ("heads",)}
+
+# Products that a fused kernel replaces by default: (product -> op whose tile 0 runs them unfused).
+# The ops are tuned in B.OPS order, so each fused op is decided after its products' tiles.
+_UNFUSED = {"ffn1": "ffn", "ffn2": "ffn", "heads1": "heads"}
 
 
 def cache_path() -> str:
@@ -86,6 +91,9 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
     choice: Dict[str, int] = {}
     for op in B.OPS:
         best, best_t = None, float("inf")
+        parent = _UNFUSED.get(op)
+        if parent:  # time the product's tiles with the fused kernel that replaces it switched off
+            model.tune_set(parent, 0)
         for tile in range(B.Model.tune_count(op)):
             try:
                 model.tune_set(op, tile)
@@ -93,7 +101,8 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
                 continue
             prof = _run(model, x, batch, ws, out, reps)
             t = sum(prof[c] for c in _CLASS[op])
-            exact = op == "ffn" or (op != "attention" and (
+            # (the reference ran the fused heads, whose sums the unfused heads1 tiles reorder)
+            exact = op == "ffn" or (op not in ("attention", "heads", "heads1") and (
                 model.precision != "fp32" or B.Model.tune_shape(op, tile)["bkb"] == ref_bkb))
             ok = _same(out, ref, exact, 1e-4 if model.precision == "fp32" else 2e-2)
             if verbose:
@@ -102,6 +111,8 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
                 best, best_t = tile, t
         model.tune_set(op, best if best is not None else -1)
         choice[op] = best if best is not None else -1
+        if parent:
+            model.tune_set(parent, -1)
     if use_cache:
         try:
             data = json.load(open(path)) if os.path.exists(path) else {}

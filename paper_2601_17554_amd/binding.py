@@ -99,7 +99,8 @@ def exported_symbols() -> Sequence[str]:
 
 
 PROF_CLASSES = ("embed", "qkv", "attention", "outproj", "ffn1", "ffn2", "heads", "worklist")
-OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1", "attention", "ffn")
+OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1", "attention", "ffn",
+       "heads")
 
 
 def _status_name(s: int) -> str:
@@ -304,11 +305,12 @@ class Model:
     @staticmethod
     def tune_shape(op: str, tile: int) -> Dict[str, int]:
         """Shape of one tile: GEMM ops {bm, bn, wm, wn, bkb, persist}; attention {waves, kt, qb,
-        kind}."""
+        kind}; ffn {fused, rows, waves, double_buffered}; heads {fused, bm, bn}."""
         v = (ctypes.c_int32 * 6)()
         _check(load().mlpf_tune_shape(OPS.index(op), tile, v))
         keys = (("waves", "kt", "qb", "kind") if op == "attention" else
-                ("fused", "rows", "waves", "double_buffered") if op == "ffn"
+                ("fused", "rows", "waves", "double_buffered") if op == "ffn" else
+                ("fused", "bm", "bn") if op == "heads"
                 else ("bm", "bn", "wm", "wn", "bkb", "persist"))
         return {k: int(v[i]) for i, k in enumerate(keys)}
 

@@ -53,6 +53,7 @@ uint16_t f32_to_bf16_rne(float f) {
 
 // Padded reduction length of the embedding's first product (F <= 32 features, k-tiles <= 64).
 constexpr int kEmbedKp = 64;
+constexpr int kHeadsTile = 13;  // the 64 x 256 GEMM tile (whole heads per column tile)
 
 struct Layer {
   size_t ln1g, ln1b, wqkv, bqkv, wo, bo, ln2g, ln2b, w1, b1, w2, b2;
@@ -66,6 +67,7 @@ struct Layer {
 struct WeightPlan {
   size_t e_w1, e_b1, e_w2, e_b2;
   bool ffn_fused = false;  // the fused BF16 FFN kernel applies (its weight images are packed)
+  bool heads_fused = false;  // the head GEMM can take the second head layer into its epilogue
   std::vector<Layer> layers;
   size_t h_w1, h_b1, h_w2, h_b2;
   size_t total;
@@ -112,6 +114,7 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
   w.e_b2 = take(d * 4);
   w.layers.resize(c.n_layers);
   w.ffn_fused = prec == MLPF_BF16 && ffn_fused_supported(c.d_model, c.d_ff);
+  w.heads_fused = prec != MLPF_FP32 && c.d_model == 256;
   for (auto& L : w.layers) {
     L.ln1g = take(d * 4);
     L.ln1b = take(d * 4);
@@ -300,10 +303,16 @@ int attn_tile_of(const mlpf_model_s* m) {
   return m->kprec == P_BF16 ? kDefaultAttnTileBf16 : 0;
 }
 
+// The GEMM tile op runs with: the pinned one, else the size-based rule.
+int gemm_tile_of(const Ctx& cx, int op, int M, int N, int prec = -1) {
+  const int pr = prec >= 0 ? prec : (int)cx.m->kprec;
+  return cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(M, N, (Prec)pr);
+}
+
 mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a, int prec = -1) {
   a.m_dev = cx.n_rows;
   const int pr = prec >= 0 ? prec : (int)cx.m->kprec;
-  const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N, (Prec)pr);
+  const int tile = gemm_tile_of(cx, op, a.M, a.N, pr);
   HIP_TRY(launch_gemm((Prec)pr, al, ep, tile, a, cx.s), "gemm launch");
   return MLPF_OK;
 }
@@ -474,16 +483,30 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
   o.bias = m->atf(L.bo);
   o.out = h;
   o.ldo = d;
+  // LN2 follows the residual update (timed with it). With the fused FFN and a projection tile one
+  // row wide, the projection's epilogue writes LN2(h) itself (bitwise equal to the LayerNorm).
+  const bool fp8 = m->prec == MLPF_BF16_FP8FFN;
+  const bool ffn_one = ffn_fused_on(m) && !cx.calib;
+  const bool ln2_fused = ffn_one && gemm_tile(gemm_tile_of(cx, MLPF_OP_OUTPROJ, T, d)).bn == d;
+  if (ln2_fused) {
+    o.y_next = cx.p(cx.w.y);
+    o.ln_g = m->atf(L.ln2g);
+    o.ln_b = m->atf(L.ln2b);
+    o.ln_eps = c.ln_eps;
+  }
+  float* am1 = cx.calib ? cx.calib + 2 * layer : nullptr;
+  float* am2 = cx.calib ? cx.calib + 2 * layer + 1 : nullptr;
   {
     ProfScope prof(cx.m, MLPF_PROF_OUTPROJ, cx.s);
     if ((st = run_gemm(cx, MLPF_OP_OUTPROJ, A_PLAIN, m->hbytes == 2 ? E_RESID_B : E_RESID, o))) return st;
+    if (!ln2_fused &&
+        (st = run_layernorm(cx, h, L.ln2g, L.ln2b, fp8 && !ffn_one ? P_FP8 : -1,
+                            fp8 && !ffn_one ? 1.f / L.s_a1 : 1.f, am1)))
+      return st;
   }
   // LN2 + FFN1 + GELU, FFN2 + residual. FP8 mode: LN2 writes E4M3 (scaled by 1/s_a1), FFN1
   // dequantises with s_a1 s_w1 and writes GELU output as E4M3 (1/s_a2), FFN2 dequantises with
   // s_a2 s_w2.
-  const bool fp8 = m->prec == MLPF_BF16_FP8FFN;
-  float* am1 = cx.calib ? cx.calib + 2 * layer : nullptr;
-  float* am2 = cx.calib ? cx.calib + 2 * layer + 1 : nullptr;
   GemmArgs f1;
   f1.a = cx.p(cx.w.y);
   f1.lda = d;
@@ -500,10 +523,9 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
     f1.acc_scale = L.s_a1 * L.s_w1;
     f1.out_scale = 1.f / L.s_a2;
   }
-  if (ffn_fused_on(m) && !cx.calib) {
+  if (ffn_one) {
     // One kernel: the d_ff-wide intermediate stays on chip (timed in the FFN1 class).
     ProfScope prof(cx.m, MLPF_PROF_FFN1, cx.s);
-    if ((st = run_layernorm(cx, h, L.ln2g, L.ln2b))) return st;
     FfnArgs a;
     a.y = cx.p(cx.w.y);
     a.M = T;
@@ -529,8 +551,6 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
   }
   {
     ProfScope prof(cx.m, MLPF_PROF_FFN1, cx.s);
-    if ((st = run_layernorm(cx, h, L.ln2g, L.ln2b, fp8 ? P_FP8 : -1, fp8 ? 1.f / L.s_a1 : 1.f, am1)))
-      return st;
     if ((st = run_gemm(cx, MLPF_OP_FFN1, A_PLAIN, E_GELU, f1, fp8 ? P_FP8 : -1))) return st;
   }
   GemmArgs f2;
@@ -590,6 +610,9 @@ mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, 
   // First layer of the five heads: [T][d] -> GELU -> [T][5d]. For PARALLEL2 the classification
   // head reads stack 0 and the regression heads stack 1.
   const int groups = m->stacks == 1 ? 1 : 2;
+  // Fused (d_model 256, bf16 operands): 64 x 256 tiles, one head per column tile; the epilogue
+  // keeps GELU(first layer) on chip and writes only the 11 second-layer sums per row (into u).
+  const bool fused = m->plan.heads_fused && m->tune[MLPF_OP_HEADS] != 0;
   for (int g = 0; g < groups; ++g) {
     const int c0 = (groups == 1) ? 0 : (g == 0 ? 0 : d);
     const int nc = (groups == 1) ? 5 * d : (g == 0 ? d : 4 * d);
@@ -604,6 +627,14 @@ mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, 
     a.bias = m->atf(m->plan.h_b1) + c0;
     a.out = (char*)cx.p(cx.w.u) + (size_t)c0 * eb;
     a.ldo = 5 * d;
+    if (fused) {
+      a.m_dev = cx.n_rows;
+      a.w2 = m->atf(m->plan.h_w2);
+      a.hout = (float*)cx.p(cx.w.u);
+      a.head0 = c0 / d;
+      HIP_TRY(launch_gemm(P_BF16, A_PLAIN, E_HEADS, kHeadsTile, a, cx.s), "gemm launch");
+      continue;
+    }
     if ((st = run_gemm(cx, MLPF_OP_HEADS1, m->hbytes == 2 ? A_PLAIN : A_F32, E_GELU, a))) return st;
   }
   Heads2Args p;
@@ -618,7 +649,11 @@ mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, 
   p.cls = cls;
   p.prim = prim;
   p.decoded = decoded;
-  HIP_TRY(launch_heads2(m->kprec, p, cx.s), "heads launch");
+  if (fused) {
+    HIP_TRY(launch_heads_finish(p, cx.s), "heads launch");
+  } else {
+    HIP_TRY(launch_heads2(m->kprec, p, cx.s), "heads launch");
+  }
   return MLPF_OK;
 }
 
@@ -915,6 +950,7 @@ mlpf_status_t mlpf_graph_destroy(mlpf_graph_t graph) {
 int32_t mlpf_tune_count(int32_t op) {
   if (op < 0 || op >= MLPF_OP_COUNT) return 0;
   if (op == MLPF_OP_FFN) return 3;
+  if (op == MLPF_OP_HEADS) return 2;
   return op == MLPF_OP_ATTENTION ? attn_num_tiles() : gemm_num_tiles();
 }
 
@@ -925,6 +961,8 @@ mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile) {
     return fail(MLPF_ERR_INVALID_ARG, "tile=%d out of range for op %d", tile, op);
   if (op == MLPF_OP_FFN && tile >= 1 && !model->plan.ffn_fused)
     return fail(MLPF_ERR_UNSUPPORTED, "the fused FFN needs an MLPF_BF16 model with d_model 64, 128 or 256");
+  if (op == MLPF_OP_HEADS && tile == 1 && !model->plan.heads_fused)
+    return fail(MLPF_ERR_UNSUPPORTED, "the fused heads need a bf16 model with d_model 256");
   model->tune[op] = tile;
   return MLPF_OK;
 }
@@ -942,6 +980,10 @@ mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape) {
   if (op == MLPF_OP_ATTENTION) {
     const AttnTile t = attn_tile(tile);
     const int32_t v[6] = {t.waves, t.kt, t.qb, t.kind, 0, 0};
+    for (int i = 0; i < 6; ++i) shape[i] = v[i];
+  } else if (op == MLPF_OP_HEADS) {
+    const GemmTile t = gemm_tile(kHeadsTile);
+    const int32_t v[6] = {tile, tile ? t.bm : 0, tile ? t.bn : 0, 0, 0, 0};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else if (op == MLPF_OP_FFN) {
     const int32_t v[6] = {tile > 0, tile == 1 ? 128 : tile == 2 ? 64 : 0, tile == 1 ? 8 : tile == 2 ? 4 : 0,

@@ -630,6 +630,8 @@ constexpr AttnTile kTiles[] = {
     {2, 64, 1, 1},
     {8, 64, 1, 1},
     {4, 64, 1, 1},  // as 6, registers capped for 4 waves per SIMD
+    {2, 64, 2, 1},
+    {4, 128, 2, 1},
 };
 
 template <class T, int DH, int NW, int KT, int QB>
@@ -667,6 +669,8 @@ hipError_t launch_dh(int tile, const AttnArgs& p, hipStream_t s) {
     case 9: return launch_b<T, DH, 2, 64, 1>(p, s);
     case 10: return launch_b<T, DH, 8, 64, 1>(p, s);
     case 11: return launch_b<T, DH, 4, 64, 1, 4>(p, s);
+    case 12: return launch_b<T, DH, 2, 64, 2>(p, s);
+    case 13: return launch_b<T, DH, 4, 128, 2>(p, s);
     default: return hipErrorInvalidValue;
   }
 }

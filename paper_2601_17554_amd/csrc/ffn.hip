@@ -198,32 +198,9 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
     if (live) *dst = hn;
     if (p.y_next) {
       float x[8];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        x[2 * e] = __uint_as_float(hn[e] << 16);
-        x[2 * e + 1] = __uint_as_float(hn[e] & 0xffff0000u);
-      }
-      float se = add_nc(0.f, ln_sum4(x[0], x[1], x[2], x[3])), so = add_nc(0.f, ln_sum4(x[4], x[5], x[6], x[7]));
-#pragma unroll
-      for (int off = CPR / 2; off >= 1; off >>= 1) {
-        se = add_nc(se, __shfl_xor(se, off, 64));
-        so = add_nc(so, __shfl_xor(so, off, 64));
-      }
-      const float mu = ln_mean(add_nc(se, so), D);
-      float qe = add_nc(0.f, ln_sq4(x[0], x[1], x[2], x[3], mu)), qo = add_nc(0.f, ln_sq4(x[4], x[5], x[6], x[7], mu));
-#pragma unroll
-      for (int off = CPR / 2; off >= 1; off >>= 1) {
-        qe = add_nc(qe, __shfl_xor(qe, off, 64));
-        qo = add_nc(qo, __shfl_xor(qo, off, 64));
-      }
-      const float rs = ln_rstd(add_nc(qe, qo), D, p.ln_eps);
-      const f32x4 g0 = *(const f32x4*)(p.ln_g + col), g1 = *(const f32x4*)(p.ln_g + col + 4);
-      const f32x4 b0 = *(const f32x4*)(p.ln_b + col), b1 = *(const f32x4*)(p.ln_b + col + 4);
-      const u32x2 ylo = pack_bf16x4(ln_out(x[0], mu, rs, g0[0], b0[0]), ln_out(x[1], mu, rs, g0[1], b0[1]),
-                                    ln_out(x[2], mu, rs, g0[2], b0[2]), ln_out(x[3], mu, rs, g0[3], b0[3]));
-      const u32x2 yhi = pack_bf16x4(ln_out(x[4], mu, rs, g1[0], b1[0]), ln_out(x[5], mu, rs, g1[1], b1[1]),
-                                    ln_out(x[6], mu, rs, g1[2], b1[2]), ln_out(x[7], mu, rs, g1[3], b1[3]));
-      if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)(m0 + row) * D + col) = u32x4{ylo[0], ylo[1], yhi[0], yhi[1]};
+      unpack_bf16x8(hn, x);
+      const u32x4 yn = ln_row_chunk8<CPR>(x, col, p.ln_g, p.ln_b, p.ln_eps);
+      if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)(m0 + row) * D + col) = yn;
     }
   }
 }

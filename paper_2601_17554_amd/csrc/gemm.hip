@@ -1,7 +1,7 @@
 // Tiled MFMA GEMM with a fused conversion prologue and fused epilogues (bias, GELU,
 // residual update, head-major Q/K/V scatter). All dense products of the MLPF forward pass run
 // here: embedding FFN, Q/K/V projection, attention output projection, both FFN layers and the
-// first layer of the output heads (paper Sec. 5.3).
+// output heads (first layer, with the second one optionally in the epilogue; paper Sec. 5.3).
 //
 // C[M][N] = op_A(A)[M][K] * W[K][N], with W stored transposed (W^T [N][Kp], the operand type) so
 // that both operands are k-contiguous rows. A workgroup owns a BM x BN output tile; its waves
@@ -17,6 +17,11 @@
 #include "kernels.h"
 
 namespace mlpf {
+
+// E_HEADS staging: 64 rows of 256 bf16 hidden units (row stride 528 bytes: 16-byte reads of 16
+// consecutive rows hit distinct banks), then W2^T hi and lo, 16 rows each of the same stride.
+constexpr int kHeadsRS = 528;
+constexpr int kHeadsHid = 64 * kHeadsRS;
 
 template <class T, int ALD, int EPI, int BM, int BN, int BK, int WM, int WN, bool PERSIST>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
@@ -34,7 +39,16 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   constexpr bool kSplit = (T::kBytes == 4);
   static_assert(C % 2 == 0 && FM >= 1 && FN >= 1, "bad tile");
 
-  __shared__ __attribute__((aligned(16))) char smem[2 * (A_BYTES + B_BYTES)];
+  // Epilogue staging (FP32 rows of the tile): one pass, or one pass per wave row when the full tile
+  // does not fit the main loop's LDS. E_HEADS stages bf16 rows and the head's slice of W2 instead.
+  constexpr int SRS = BN * 4 + 16;                       // staging row stride (bytes)
+  constexpr int MAIN = 2 * (A_BYTES + B_BYTES);
+  constexpr int PASSES = (BM * SRS <= MAIN || WM == 1) ? 1 : WM;
+  constexpr int PROWS = BM / PASSES;                     // rows staged per pass
+  constexpr int STAGE = EPI == E_HEADS ? kHeadsHid + 32 * kHeadsRS : PROWS * SRS;
+  constexpr int SMEM = MAIN > STAGE ? MAIN : STAGE;
+  static_assert(EPI != E_HEADS || (BM == 64 && BN == 256 && NT == 256), "E_HEADS tile is 64 x 256, 4 waves");
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
@@ -192,10 +206,6 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   // output rows (read-modify-write of h for the residual update). In a 32x32 accumulator block,
   // lane l holds column l%32 of rows 8*(r/4) + 4*(l/32) + r%4 for r = 0..15. Tiles whose FP32
   // image does not fit the LDS of the main loop are staged in two passes (one per wave row).
-  constexpr int SRS = BN * 4 + 16;                       // staging row stride (bytes)
-  constexpr int PASSES = (BM * SRS <= 2 * (A_BYTES + B_BYTES)) ? 1 : WM;
-  constexpr int PROWS = BM / PASSES;                     // rows staged per pass
-  static_assert(PROWS * SRS <= 2 * (A_BYTES + B_BYTES), "epilogue staging does not fit");
   constexpr bool kResF32 = (EPI == E_BIAS || EPI == E_RESID);
   constexpr bool kResB16 = (EPI == E_BIAS_B || EPI == E_RESID_B);
   constexpr int OSZ = kResF32 ? 4 : kResB16 ? 2 : (int)sizeof(S);
@@ -218,10 +228,59 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
               v = gelu_erf(v);
               if (m0 + pass * PROWS + lrow < M && col < p.N) amax = fmaxf(amax, fabsf(v));
             }
-            *(float*)(smem + lrow * SRS + lcol * 4) = v;
+            if constexpr (EPI == E_HEADS)  // the hidden layer, bf16 rows of kHeadsRS bytes
+              *(__bf16*)(smem + lrow * kHeadsRS + lcol * 2) = (__bf16)gelu_erf(v);
+            else
+              *(float*)(smem + lrow * SRS + lcol * 4) = v;
           }
         }
       }
+    }
+    if constexpr (EPI == E_HEADS) {
+      // Second layer of head k = head0 + n0 / 256 on the 64 x 256 bf16 hidden tile staged above:
+      // out^T [16 outputs (zero-padded)][64 rows] = W2_k^T [16][256] U^T [256][64] with
+      // v_mfma_f32_16x16x32_bf16 (lane l: output / row l % 16, k = 8 (l / 16) .. + 7 of each
+      // 32-wide k-step). W2 is FP32: it enters as hi + lo, hi = bf16(w), lo = bf16(w - hi), two
+      // products into the same FP32 sums (|w - hi - lo| <= 2^-18 |w|). Wave w owns rows 16 w ..
+      // 16 w + 15.
+      const int k = p.head0 + n0 / 256;
+      const int c0 = k == 0 ? 0 : k + 5 + (k == 4), wid = k == 0 ? 6 : k == 3 ? 2 : 1;
+      char* w2s = smem + kHeadsHid;  // [2 (hi, lo)][16][kHeadsRS]
+      {
+        const int j = tid;  // hidden unit (NT == 256)
+#pragma unroll
+        for (int o = 0; o < 16; ++o) {
+          const float w = o < wid ? p.w2[j * 11 + c0 + o] : 0.f;
+          const __bf16 hi = (__bf16)w;
+          const __bf16 lo = (__bf16)(w - (float)hi);
+          *(__bf16*)(w2s + o * kHeadsRS + 2 * j) = hi;
+          *(__bf16*)(w2s + (16 + o) * kHeadsRS + 2 * j) = lo;
+        }
+      }
+      __syncthreads();
+      const int r16 = lane & 15, kq = lane >> 4;
+      const char* ub = smem + (16 * wave + r16) * kHeadsRS + 16 * kq;
+      const char* wh = w2s + r16 * kHeadsRS + 16 * kq;
+      const char* wl = wh + 16 * kHeadsRS;
+      f32x4 o4 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < 8; ++st) {
+        const bf16x8 u = __builtin_bit_cast(bf16x8, *(const u32x4*)(ub + 64 * st));
+        const bf16x8 a_hi = __builtin_bit_cast(bf16x8, *(const u32x4*)(wh + 64 * st));
+        const bf16x8 a_lo = __builtin_bit_cast(bf16x8, *(const u32x4*)(wl + 64 * st));
+        o4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, u, o4, 0, 0, 0);
+        o4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, u, o4, 0, 0, 0);
+      }
+      // Lane holds row 16 w + l % 16 and outputs 4 (l / 16) + e.
+      const int row = m0 + 16 * wave + r16;
+      if (row < M) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int o = 4 * kq + e;
+          if (o < wid) p.hout[(int64_t)row * 11 + c0 + o] = o4[e];
+        }
+      }
+      continue;
     }
     __syncthreads();
     constexpr int CPR = BN / EO;                         // chunks per staged row
@@ -230,6 +289,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
       const int row = m0 + pass * PROWS + lrow, col = n0 + lc;
       const bool live = row < M && col < p.N;
       [[maybe_unused]] float ss = 0.f;  // E_QKV with knorm: sum of squares of this K chunk
+      [[maybe_unused]] u32x4 hn = u32x4{0, 0, 0, 0};  // E_RESID_B: the chunk's new bf16 values
       if (live) {
       const float* src = (const float*)(smem + lrow * SRS + lc * 4);
       if constexpr (kResF32) {
@@ -249,7 +309,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
         }
         const u32x2 lo = pack_bf16x4(v0[0], v0[1], v0[2], v0[3]);
         const u32x2 hi = pack_bf16x4(v1[0], v1[1], v1[2], v1[3]);
-        *dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        hn = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        *dst = hn;
       } else {
         float qs = 1.f;
         S* dst;
@@ -291,6 +352,16 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
           *(u32x4*)dst = o;
         }
       }
+      }
+      if constexpr (EPI == E_RESID_B) {
+        // Next LayerNorm of the updated rows (the host passes y_next only when BN == N): the CPR
+        // threads of a row are consecutive lanes of one wave.
+        if (p.y_next) {
+          float x[8];
+          unpack_bf16x8(hn, x);
+          const u32x4 yn = ln_row_chunk8<CPR>(x, col, p.ln_g, p.ln_b, p.ln_eps);
+          if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)row * p.N + col) = yn;
+        }
       }
       if constexpr (EPI == E_QKV && sizeof(S) == 2) {
         // Squared norm of each (row, head) of K from its bf16 values: the dh/8 chunks of one head
@@ -338,6 +409,8 @@ constexpr GemmTile kTiles[] = {
     {128, 64, 2, 2, 64, 1},
     {64, 128, 2, 2, 64, 1},
     {128, 128, 2, 2, 128, 1},
+    // 64 rows x 256 columns, 1 x 4 waves: whole 256-wide rows per workgroup (fused output heads)
+    {64, 256, 1, 4, 64, 0},
 };
 
 // Workgroups of one kernel that fit on the device at once (the grid of a persistent launch). The
@@ -389,6 +462,7 @@ hipError_t launch_tile(int tile, const GemmArgs& p, hipStream_t s) {
     case 10: return launch_t<T, ALD, EPI, 128, 64, 2, 2, 64, true>(p, s);
     case 11: return launch_t<T, ALD, EPI, 64, 128, 2, 2, 64, true>(p, s);
     case 12: return launch_t<T, ALD, EPI, 128, 128, 2, 2, 128, true>(p, s);
+    case 13: return launch_t<T, ALD, EPI, 64, 256, 1, 4, 64>(p, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -402,8 +476,16 @@ hipError_t launch_prec(ALoad aload, Epi epi, int tile, const GemmArgs& p, hipStr
   if (aload == A_PLAIN && epi == E_RESID) return launch_tile<T, A_PLAIN, E_RESID>(tile, p, s);
   if (aload == A_PLAIN && epi == E_GELU) return launch_tile<T, A_PLAIN, E_GELU>(tile, p, s);
   if constexpr (!std::is_same_v<T, F32>) {
+    if (aload == A_PLAIN && epi == E_HEADS) {
+      if (tile != 13 || p.N % 256 != 0 || !p.w2 || !p.hout) return hipErrorInvalidValue;
+      return launch_t<T, A_PLAIN, E_HEADS, 64, 256, 1, 4, 64>(p, s);
+    }
     if (aload == A_PLAIN && epi == E_BIAS_B) return launch_tile<T, A_PLAIN, E_BIAS_B>(tile, p, s);
-    if (aload == A_PLAIN && epi == E_RESID_B) return launch_tile<T, A_PLAIN, E_RESID_B>(tile, p, s);
+    if (aload == A_PLAIN && epi == E_RESID_B) {
+      if (p.y_next && (tile < 0 || tile >= gemm_num_tiles() || kTiles[tile].bn != p.N))
+        return hipErrorInvalidValue;
+      return launch_tile<T, A_PLAIN, E_RESID_B>(tile, p, s);
+    }
   }
   if (aload == A_F32 && epi == E_GELU) return launch_tile<T, A_F32, E_GELU>(tile, p, s);
   return hipErrorInvalidValue;

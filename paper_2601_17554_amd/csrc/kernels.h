@@ -23,6 +23,8 @@ enum Epi {
   E_QKV = 3,     // Q (scaled), K, V written head-major [head][row][d_head] in the operand type
   E_BIAS_B = 4,  // out_bf16[row][col] = acc + bias            (bf16 residual stream)
   E_RESID_B = 5, // out_bf16[row][col] = bf16(out + acc + bias), the sum taken in FP32
+  E_HEADS = 6,   // first head layer (GELU, bf16) and, per 256-wide head tile, its second-layer
+                 // outputs: hout[row][cols of head] = hidden . W2[:, cols] (biases added later)
 };
 
 struct GemmArgs {
@@ -46,6 +48,16 @@ struct GemmArgs {
   int d = 0, dh = 0;
   float q_scale = 1.f;
   float* knorm = nullptr;  // bf16 E_QKV: also write |k|^2 per (head, row), [H][hstride / dh]
+  // E_RESID_B with one column tile per row (BN == N): also y_next = LayerNorm(updated row) in bf16,
+  // bitwise equal to the LayerNorm kernel's output (the next LayerNorm fused into the epilogue).
+  void* y_next = nullptr;
+  const float* ln_g = nullptr;
+  const float* ln_b = nullptr;
+  float ln_eps = 1e-5f;
+  // E_HEADS
+  const float* w2 = nullptr;  // [256][11]
+  float* hout = nullptr;      // [M][11]
+  int head0 = 0;              // head index of the first 256 columns
 };
 
 // Tile shapes available to the GEMM (index = tile id). Each entry: BM, BN, BK(bytes-agnostic
@@ -143,6 +155,9 @@ struct Heads2Args {
   float* decoded = nullptr;
 };
 hipError_t launch_heads2(Prec prec, const Heads2Args& args, hipStream_t stream);
+// From the E_HEADS partial outputs (uh = hout [rows][11] FP32): adds b2, writes logits, reg,
+// cls (argmax) and the optional decode.
+hipError_t launch_heads_finish(const Heads2Args& args, hipStream_t stream);
 
 // LayerNorm of FP32 or bf16 rows [rows][d] into y [rows][d] of the operand type.
 struct LayerNormArgs {

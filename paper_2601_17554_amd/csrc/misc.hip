@@ -148,6 +148,44 @@ hipError_t launch_heads2(Prec prec, const Heads2Args& p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Output stage after the fused head GEMM: one thread per row adds b2 to the 11 second-layer sums
+// that the GEMM epilogue wrote, then argmax and decode as above.
+__global__ __launch_bounds__(256) void heads_finish_kernel(const Heads2Args p) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  int M = p.rows;
+  if (p.m_dev) M = min(M, max(*p.m_dev, 0));
+  if (row >= M) return;
+  const float* u = (const float*)p.uh + (int64_t)row * 11;
+  float acc[11];
+#pragma unroll
+  for (int c = 0; c < 11; ++c) acc[c] = u[c] + p.b2[c];
+  int best = 0;
+#pragma unroll
+  for (int c = 1; c < 6; ++c)
+    if (acc[c] > acc[best]) best = c;
+  float* lg = p.logits + (int64_t)row * 6;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) lg[c] = acc[c];
+  float* rg = p.reg + (int64_t)row * 5;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) rg[c] = acc[6 + c];
+  p.cls[row] = best;
+  if (p.prim && p.decoded) {
+    float* dd = p.decoded + (int64_t)row * 4;
+    dd[0] = p.prim[2 * row] * expf(acc[6]);
+    dd[1] = acc[7];
+    dd[2] = atan2f(acc[8], acc[9]);
+    dd[3] = p.prim[2 * row + 1] * expf(acc[10]);
+  }
+}
+
+hipError_t launch_heads_finish(const Heads2Args& p, hipStream_t s) {
+  const int grid = (p.rows + 255) / 256;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(heads_finish_kernel, dim3(grid), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------------
 // LayerNorm of FP32 rows into the operand type of the next product (pre-LN transformer block):
 // FP32, BF16, or FP8 E4M3 after multiplying by out_scale (the inverse per-tensor scale).

@@ -229,6 +229,7 @@ def test_every_gemm_tile(B, prec):
     evs = [synth.make_event(2000 + i, n) for i, n in enumerate([70, 1, 517, 200, 33])]
     pk = synth.pack(evs)
     m.tune_set("ffn", 0)  # the FFN as two products, so that their tiles apply
+    m.tune_set("heads", 0)  # likewise the heads' first product
     for tile in range(B.Model.tune_count("qkv")):
         for op in GEMM_OPS:
             m.tune_set(op, tile)
@@ -244,6 +245,7 @@ def test_persistent_gemm_bitwise(B, prec):
     pk = synth.pack(synth.event_set(400, 12, lo=1500))
     tiles = [B.Model.tune_shape("qkv", t) for t in range(B.Model.tune_count("qkv"))]
     m.tune_set("ffn", 0)
+    m.tune_set("heads", 0)
     results = {}
     for t, spec in enumerate(tiles):
         for op in GEMM_OPS:
@@ -283,3 +285,57 @@ def test_fused_ffn_bitwise(B, cfg):
                 np.testing.assert_array_equal(fused[k][r], two[k][r], err_msg=f"tile {tile} {k}")
     with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
         B.Model(cfg, w, "fp32").tune_set("ffn", 1)
+
+
+@pytest.mark.parametrize("cfg", [synth.FULL, synth.PAPER], ids=["d256", "paper_parallel2"])
+def test_fused_heads(B, cfg):
+    """The head GEMM with the second head layer in its epilogue (BF16, d_model 256) against the
+    oracle, and against the unfused heads (same hidden layer bits, sums in another order), on
+    ragged events with garbage padding; the paper's two-stack layout sends the classification head
+    and the regression heads to separate launches."""
+    w, m = _model(B, cfg, 16, "bf16", sharpen=2.0)
+    evs = [synth.make_event(5100 + i, n) for i, n in enumerate([300, 1, 65, 64, 700])]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=10)
+    assert B.Model.tune_shape("heads", 1) == {"fused": 1, "bm": 64, "bn": 256}
+    fused = run_gpu(m, pk)
+    _check_all(fused, pk, w, cfg, TOL["bf16"], f"fused heads {cfg.topology}")
+    m.tune_set("heads", 0)
+    plain = run_gpu(m, pk)
+    live = np.concatenate([np.arange(pk.event_rows(e).start, pk.event_rows(e).stop)
+                           for e in range(pk.n_events)])
+    for k in ("logits", "reg"):
+        a, b = fused[k][live], plain[k][live]
+        err = float(np.abs(a - b).max()) / max(float(np.abs(b).max()), 1e-6)
+        print(f"fused vs plain heads {k}: rel max err {err:.3e}", flush=True)
+        assert err <= 1e-4, k
+    agree = float((fused["cls"][live] == plain["cls"][live]).mean())
+    assert agree >= 0.999, agree
+    with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
+        B.Model(cfg, w, "fp32").tune_set("heads", 1)
+    with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
+        B.Model(synth.SMALL, synth.make_weights(synth.SMALL, 1), "bf16").tune_set("heads", 1)
+
+
+@pytest.mark.parametrize("cfg,fused_tiles,plain_tile", [
+    (synth.FULL, (13, 5), 6),
+    (synth.Config(d_model=128, n_heads=4, d_ff=192, n_layers=2), (6, 9), 7),
+    (synth.SMALL, (7, 0), 6)], ids=["d256", "d128", "d64"])
+def test_fused_ln2_bitwise(B, cfg, fused_tiles, plain_tile):
+    """With the fused FFN, an output-projection tile as wide as d_model also writes LN2 from its
+    epilogue; the outputs are bitwise those of the separate LayerNorm kernel (other tiles), on
+    ragged events with garbage padding."""
+    w, m = _model(B, cfg, 17, "bf16", sharpen=2.0)
+    evs = [synth.make_event(5200 + i, n) for i, n in enumerate([257, 1, 64, 130])]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=11)
+    m.tune_set("outproj", plain_tile)
+    assert B.Model.tune_shape("outproj", plain_tile)["bn"] != cfg.d_model
+    ref = run_gpu(m, pk)
+    for t in fused_tiles:
+        assert B.Model.tune_shape("outproj", t)["bn"] == cfg.d_model
+        m.tune_set("outproj", t)
+        got = run_gpu(m, pk)
+        for e in range(pk.n_events):
+            r = pk.event_rows(e)
+            for k in ("logits", "reg", "cls"):
+                np.testing.assert_array_equal(got[k][r], ref[k][r], err_msg=f"tile {t} event {e} {k}")
+    _check_all(got, pk, w, cfg, TOL["bf16"], f"fused ln2 d{cfg.d_model}")
