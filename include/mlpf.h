@@ -178,8 +178,8 @@ typedef enum {
   MLPF_PROF_EMBED = 0,     /* both products of the embedding FFN */
   MLPF_PROF_QKV = 1,       /* LN1 + Q/K/V projection */
   MLPF_PROF_ATTENTION = 2, /* fused masked varlen attention */
-  MLPF_PROF_OUTPROJ = 3,   /* attention output projection + residual + LN2 */
-  MLPF_PROF_FFN1 = 4,      /* FFN1 + GELU (the whole fused FFN when it runs) */
+  MLPF_PROF_OUTPROJ = 3,   /* attention output projection + residual (+ LN2 unless fused FFN) */
+  MLPF_PROF_FFN1 = 4,      /* FFN1 + GELU (the whole fused FFN, LN2 included, when it runs) */
   MLPF_PROF_FFN2 = 5,      /* FFN2 + residual */
   MLPF_PROF_HEADS = 6,     /* both head layers, argmax, decode */
   MLPF_PROF_WORKLIST = 7,  /* batch sanitising and attention work list */

@@ -303,16 +303,10 @@ int attn_tile_of(const mlpf_model_s* m) {
   return m->kprec == P_BF16 ? kDefaultAttnTileBf16 : 0;
 }
 
-// The GEMM tile op runs with: the pinned one, else the size-based rule.
-int gemm_tile_of(const Ctx& cx, int op, int M, int N, int prec = -1) {
-  const int pr = prec >= 0 ? prec : (int)cx.m->kprec;
-  return cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(M, N, (Prec)pr);
-}
-
 mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a, int prec = -1) {
   a.m_dev = cx.n_rows;
   const int pr = prec >= 0 ? prec : (int)cx.m->kprec;
-  const int tile = gemm_tile_of(cx, op, a.M, a.N, pr);
+  const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N, (Prec)pr);
   HIP_TRY(launch_gemm((Prec)pr, al, ep, tile, a, cx.s), "gemm launch");
   return MLPF_OK;
 }
@@ -483,25 +477,16 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
   o.bias = m->atf(L.bo);
   o.out = h;
   o.ldo = d;
-  // LN2 follows the residual update (timed with it). With the fused FFN and a projection tile one
-  // row wide, the projection's epilogue writes LN2(h) itself (bitwise equal to the LayerNorm).
+  // LN2 follows the residual update (timed with it); the fused FFN computes it itself from h.
   const bool fp8 = m->prec == MLPF_BF16_FP8FFN;
   const bool ffn_one = ffn_fused_on(m) && !cx.calib;
-  const bool ln2_fused = ffn_one && gemm_tile(gemm_tile_of(cx, MLPF_OP_OUTPROJ, T, d)).bn == d;
-  if (ln2_fused) {
-    o.y_next = cx.p(cx.w.y);
-    o.ln_g = m->atf(L.ln2g);
-    o.ln_b = m->atf(L.ln2b);
-    o.ln_eps = c.ln_eps;
-  }
   float* am1 = cx.calib ? cx.calib + 2 * layer : nullptr;
   float* am2 = cx.calib ? cx.calib + 2 * layer + 1 : nullptr;
   {
     ProfScope prof(cx.m, MLPF_PROF_OUTPROJ, cx.s);
     if ((st = run_gemm(cx, MLPF_OP_OUTPROJ, A_PLAIN, m->hbytes == 2 ? E_RESID_B : E_RESID, o))) return st;
-    if (!ln2_fused &&
-        (st = run_layernorm(cx, h, L.ln2g, L.ln2b, fp8 && !ffn_one ? P_FP8 : -1,
-                            fp8 && !ffn_one ? 1.f / L.s_a1 : 1.f, am1)))
+    if (!ffn_one && (st = run_layernorm(cx, h, L.ln2g, L.ln2b, fp8 ? P_FP8 : -1,
+                                        fp8 ? 1.f / L.s_a1 : 1.f, am1)))
       return st;
   }
   // LN2 + FFN1 + GELU, FFN2 + residual. FP8 mode: LN2 writes E4M3 (scaled by 1/s_a1), FFN1
@@ -527,7 +512,10 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
     // One kernel: the d_ff-wide intermediate stays on chip (timed in the FFN1 class).
     ProfScope prof(cx.m, MLPF_PROF_FFN1, cx.s);
     FfnArgs a;
-    a.y = cx.p(cx.w.y);
+    a.y = h;  // LN2 in the kernel
+    a.ln_in_g = m->atf(L.ln2g);
+    a.ln_in_b = m->atf(L.ln2b);
+    a.ln_in_eps = c.ln_eps;
     a.M = T;
     a.m_dev = cx.n_rows;
     a.d_model = d;

@@ -1,5 +1,7 @@
 // Fused position-wise feed-forward block of one encoder layer, BF16 (paper Sec. 5.3):
 //   h[M][D] += GELU(y W1 + b1) W2 + b2,   y = LN2(h), h and y in bf16, W1 [D][d_ff], W2 [d_ff][D].
+// y is read as given, or computed from h in registers (LN2 fused, bitwise equal to the LayerNorm
+// kernel).
 // The d_ff-wide intermediate never leaves the workgroup: it is produced and consumed in chunks of
 // kFfnHC hidden units. A workgroup owns kFfnBM rows; per chunk
 //   phase 1: U^T = W1_c^T y^T (32x32 MFMA blocks; y's fragments stay in registers for the whole
@@ -53,6 +55,66 @@ __device__ __forceinline__ void copy_to_lds(const char* src, char* dst, int byte
   }
 }
 
+// LayerNorm of the rows held as y fragments (in place): lane (i, h) holds columns 16 g + 8 h + 0..7
+// of its row for g < KG, the lane 32 apart the other half. The sums reproduce the LayerNorm
+// kernel's exactly: there lane L = 4 g + 2 h + e holds columns 4L .. 4L+3 (e = the two halves of a
+// fragment) and a butterfly over lane offsets 32 .. 1 adds partners; offsets above the row's lanes
+// add zeros (no change), the next ones pair g with g ^ (KG/2) .. g ^ 1, then h (the lane 32 apart),
+// then e. Every lane of the wave must call it (shuffles).
+template <int KG>
+__device__ __forceinline__ void ln_fragments(u32x4* yf, int h, const float* gam, const float* bet,
+                                             float eps) {
+  constexpr int D = 16 * KG;
+  float t0[KG], t1[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) {
+    float x[8];
+    unpack_bf16x8(yf[g], x);
+    t0[g] = add_nc(0.f, ln_sum4(x[0], x[1], x[2], x[3]));
+    t1[g] = add_nc(0.f, ln_sum4(x[4], x[5], x[6], x[7]));
+  }
+#pragma unroll
+  for (int w = KG / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int g = 0; g < w; ++g) {
+      t0[g] = add_nc(t0[g], t0[g + w]);
+      t1[g] = add_nc(t1[g], t1[g + w]);
+    }
+  const float s0 = add_nc(t0[0], __shfl_xor(t0[0], 32, 64));
+  const float s1 = add_nc(t1[0], __shfl_xor(t1[0], 32, 64));
+  const float mu = ln_mean(add_nc(s0, s1), D);
+#pragma unroll
+  for (int g = 0; g < KG; ++g) {
+    float x[8];
+    unpack_bf16x8(yf[g], x);
+    t0[g] = add_nc(0.f, ln_sq4(x[0], x[1], x[2], x[3], mu));
+    t1[g] = add_nc(0.f, ln_sq4(x[4], x[5], x[6], x[7], mu));
+  }
+#pragma unroll
+  for (int w = KG / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int g = 0; g < w; ++g) {
+      t0[g] = add_nc(t0[g], t0[g + w]);
+      t1[g] = add_nc(t1[g], t1[g + w]);
+    }
+  const float q0 = add_nc(t0[0], __shfl_xor(t0[0], 32, 64));
+  const float q1 = add_nc(t1[0], __shfl_xor(t1[0], 32, 64));
+  const float rs = ln_rstd(add_nc(q0, q1), D, eps);
+#pragma unroll
+  for (int g = 0; g < KG; ++g) {
+    float x[8];
+    unpack_bf16x8(yf[g], x);
+    const int c = 16 * g + 8 * h;
+    const f32x4 g0 = *(const f32x4*)(gam + c), g1 = *(const f32x4*)(gam + c + 4);
+    const f32x4 b0 = *(const f32x4*)(bet + c), b1 = *(const f32x4*)(bet + c + 4);
+    const u32x2 lo = pack_bf16x4(ln_out(x[0], mu, rs, g0[0], b0[0]), ln_out(x[1], mu, rs, g0[1], b0[1]),
+                                 ln_out(x[2], mu, rs, g0[2], b0[2]), ln_out(x[3], mu, rs, g0[3], b0[3]));
+    const u32x2 hi = pack_bf16x4(ln_out(x[4], mu, rs, g1[0], b1[0]), ln_out(x[5], mu, rs, g1[1], b1[1]),
+                                 ln_out(x[6], mu, rs, g1[2], b1[2]), ln_out(x[7], mu, rs, g1[3], b1[3]));
+    yf[g] = u32x4{lo[0], lo[1], hi[0], hi[1]};
+  }
+}
+
 // BM rows per workgroup of NW waves. DBUF: the next chunk's W1 and W2 travel during the current
 // chunk (one workgroup per CU at d_model 256). Single buffered: W1 of chunk c+1 is fetched during
 // phase 2 of chunk c, W2 after it, and the LDS image is small enough for two workgroups per CU,
@@ -99,6 +161,7 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
     for (int g = 0; g < KG1; ++g)
       yf[g] = row < M ? *(const u32x4*)(yr + 16 * g + 8 * h) : u32x4{0, 0, 0, 0};
   }
+  if (p.ln_in_g) ln_fragments<KG1>(yf, h, p.ln_in_g, p.ln_in_b, p.ln_in_eps);
   // Phase-2 role: FM2 x FN2 blocks of 32x32 outputs.
   const int wm2 = wave / WN2, wn2 = wave % WN2;
   f32x16 acc[FM2][FN2];

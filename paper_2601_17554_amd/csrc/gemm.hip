@@ -289,7 +289,6 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
       const int row = m0 + pass * PROWS + lrow, col = n0 + lc;
       const bool live = row < M && col < p.N;
       [[maybe_unused]] float ss = 0.f;  // E_QKV with knorm: sum of squares of this K chunk
-      [[maybe_unused]] u32x4 hn = u32x4{0, 0, 0, 0};  // E_RESID_B: the chunk's new bf16 values
       if (live) {
       const float* src = (const float*)(smem + lrow * SRS + lc * 4);
       if constexpr (kResF32) {
@@ -309,8 +308,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
         }
         const u32x2 lo = pack_bf16x4(v0[0], v0[1], v0[2], v0[3]);
         const u32x2 hi = pack_bf16x4(v1[0], v1[1], v1[2], v1[3]);
-        hn = u32x4{lo[0], lo[1], hi[0], hi[1]};
-        *dst = hn;
+        *dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
       } else {
         float qs = 1.f;
         S* dst;
@@ -352,16 +350,6 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
           *(u32x4*)dst = o;
         }
       }
-      }
-      if constexpr (EPI == E_RESID_B) {
-        // Next LayerNorm of the updated rows (the host passes y_next only when BN == N): the CPR
-        // threads of a row are consecutive lanes of one wave.
-        if (p.y_next) {
-          float x[8];
-          unpack_bf16x8(hn, x);
-          const u32x4 yn = ln_row_chunk8<CPR>(x, col, p.ln_g, p.ln_b, p.ln_eps);
-          if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)row * p.N + col) = yn;
-        }
       }
       if constexpr (EPI == E_QKV && sizeof(S) == 2) {
         // Squared norm of each (row, head) of K from its bf16 values: the dh/8 chunks of one head
@@ -481,11 +469,7 @@ hipError_t launch_prec(ALoad aload, Epi epi, int tile, const GemmArgs& p, hipStr
       return launch_t<T, A_PLAIN, E_HEADS, 64, 256, 1, 4, 64>(p, s);
     }
     if (aload == A_PLAIN && epi == E_BIAS_B) return launch_tile<T, A_PLAIN, E_BIAS_B>(tile, p, s);
-    if (aload == A_PLAIN && epi == E_RESID_B) {
-      if (p.y_next && (tile < 0 || tile >= gemm_num_tiles() || kTiles[tile].bn != p.N))
-        return hipErrorInvalidValue;
-      return launch_tile<T, A_PLAIN, E_RESID_B>(tile, p, s);
-    }
+    if (aload == A_PLAIN && epi == E_RESID_B) return launch_tile<T, A_PLAIN, E_RESID_B>(tile, p, s);
   }
   if (aload == A_F32 && epi == E_GELU) return launch_tile<T, A_F32, E_GELU>(tile, p, s);
   return hipErrorInvalidValue;

@@ -48,12 +48,6 @@ struct GemmArgs {
   int d = 0, dh = 0;
   float q_scale = 1.f;
   float* knorm = nullptr;  // bf16 E_QKV: also write |k|^2 per (head, row), [H][hstride / dh]
-  // E_RESID_B with one column tile per row (BN == N): also y_next = LayerNorm(updated row) in bf16,
-  // bitwise equal to the LayerNorm kernel's output (the next LayerNorm fused into the epilogue).
-  void* y_next = nullptr;
-  const float* ln_g = nullptr;
-  const float* ln_b = nullptr;
-  float ln_eps = 1e-5f;
   // E_HEADS
   const float* w2 = nullptr;  // [256][11]
   float* hout = nullptr;      // [M][11]
@@ -75,7 +69,10 @@ hipError_t launch_gemm(Prec prec, ALoad aload, Epi epi, int tile, const GemmArgs
 // Fused BF16 FFN block: h[M][d_model] += GELU(y W1 + b1) W2 + b2 with the weights pre-tiled by
 // ffn_pack (W1 and W2 chunks of 64 hidden units as their LDS images).
 struct FfnArgs {
-  const void* y = nullptr;      // bf16 [M][d_model]
+  const void* y = nullptr;      // bf16 [M][d_model]: LN2(h), or h itself when ln_in_g is set
+  const float* ln_in_g = nullptr;  // optional: y = LayerNorm(rows of y) computed in the kernel
+  const float* ln_in_b = nullptr;
+  float ln_in_eps = 1e-5f;
   int M = 0;
   const int32_t* m_dev = nullptr;
   int d_model = 0, d_ff = 0;

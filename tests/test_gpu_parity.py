@@ -315,27 +315,3 @@ def test_fused_heads(B, cfg):
     with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
         B.Model(synth.SMALL, synth.make_weights(synth.SMALL, 1), "bf16").tune_set("heads", 1)
 
-
-@pytest.mark.parametrize("cfg,fused_tiles,plain_tile", [
-    (synth.FULL, (13, 5), 6),
-    (synth.Config(d_model=128, n_heads=4, d_ff=192, n_layers=2), (6, 9), 7),
-    (synth.SMALL, (7, 0), 6)], ids=["d256", "d128", "d64"])
-def test_fused_ln2_bitwise(B, cfg, fused_tiles, plain_tile):
-    """With the fused FFN, an output-projection tile as wide as d_model also writes LN2 from its
-    epilogue; the outputs are bitwise those of the separate LayerNorm kernel (other tiles), on
-    ragged events with garbage padding."""
-    w, m = _model(B, cfg, 17, "bf16", sharpen=2.0)
-    evs = [synth.make_event(5200 + i, n) for i, n in enumerate([257, 1, 64, 130])]
-    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=11)
-    m.tune_set("outproj", plain_tile)
-    assert B.Model.tune_shape("outproj", plain_tile)["bn"] != cfg.d_model
-    ref = run_gpu(m, pk)
-    for t in fused_tiles:
-        assert B.Model.tune_shape("outproj", t)["bn"] == cfg.d_model
-        m.tune_set("outproj", t)
-        got = run_gpu(m, pk)
-        for e in range(pk.n_events):
-            r = pk.event_rows(e)
-            for k in ("logits", "reg", "cls"):
-                np.testing.assert_array_equal(got[k][r], ref[k][r], err_msg=f"tile {t} event {e} {k}")
-    _check_all(got, pk, w, cfg, TOL["bf16"], f"fused ln2 d{cfg.d_model}")
