@@ -319,7 +319,8 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
 // keys and runs the key loop again with them.
 //
 // Key loop: 32-key blocks, software pipelined (the QK^T product of block b+1 is issued before the
-// exponentials of block b, with the two score sets in alternating registers). K and V stages of
+// exponentials of block b, with the two score sets in alternating registers, and its K fragments
+// were read from LDS a step earlier). K and V stages of
 // 32*G keys rotate through three LDS slots: while stage s is consumed, stage s+1 is resident (the
 // look-ahead product reads it) and stage s+2 travels from global memory in registers; one barrier
 // per stage. Each wave owns QB blocks of 32 queries. V stays row-major in LDS (one 16-byte store
@@ -423,12 +424,14 @@ void attn_bf16_kernel(const AttnArgs p) {
   float l_run[QB], m_ex[QB];
   f32x16 oacc[QB];
 
-  // Scores plus C of key block bb of the stage in LDS slot `slot`.
-  auto scores = [&](int slot, int bb, f32x16 (&s)[QB], const f32x16 (&c0)[QB]) {
-    const char* Ks = smem + slot * SLOT;
-    u32x4 ka[QKG];
+  // K fragments of key block b (its stage b / G sits in LDS slot (b / G) % 3).
+  auto kread = [&](int b, u32x4 (&ka)[QKG]) {
+    const char* Ks = smem + ((b / G) % 3) * SLOT;
 #pragma unroll
-    for (int c = 0; c < QKG; ++c) ka[c] = *(const u32x4*)(Ks + (32 * bb + i) * KRS + (2 * c + h) * 16);
+    for (int c = 0; c < QKG; ++c) ka[c] = *(const u32x4*)(Ks + (32 * (b % G) + i) * KRS + (2 * c + h) * 16);
+  };
+  // Scores plus C from K fragments.
+  auto scores = [&](const u32x4 (&ka)[QKG], f32x16 (&s)[QB], const f32x16 (&c0)[QB]) {
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
       s[j] = c0[j];
@@ -510,18 +513,25 @@ void attn_bf16_kernel(const AttnArgs p) {
     if (nst > 2) load(2, rk, rv);
 
     f32x16 sa[QB], sb[QB];
+    u32x4 kn[QKG];  // K fragments of the block after the one in `cur`, read a step ahead
     if (nblk > 0) {
-      scores(0, 0, sa, c0);
+      kread(0, kn);
+      scores(kn, sa, c0);
       if (nblk == 1 && (n & 31)) mask(0, sa);
     }
-    // Block b of stage st (position bb) is in `cur`; the look-ahead product fills `nxt`.
+    if (nblk > 1) kread(1, kn);
+    // Block b of stage st (position bb) is in `cur`; the look-ahead product fills `nxt` from the
+    // K fragments read during the previous step, and the fragments of block b + 2 (in stage st or
+    // st + 1, both resident) are read for the next one. Past the last block both repeat the last
+    // block (unused results; no branch, so the fragment registers rotate without copies).
     auto step = [&](int st, int slot, int bb, f32x16 (&cur)[QB], f32x16 (&nxt)[QB]) {
       const int b = st * G + bb;
-      if (b + 1 < nblk) {
-        if (bb + 1 < G)
-          scores(slot, bb + 1, nxt, c0);
-        else
-          scores(slot == 2 ? 0 : slot + 1, 0, nxt, c0);
+      {
+        u32x4 ka[QKG];
+#pragma unroll
+        for (int c = 0; c < QKG; ++c) ka[c] = kn[c];
+        kread(min(b + 2, nblk - 1), kn);
+        scores(ka, nxt, c0);
         if (b + 2 == nblk && (n & 31)) mask(b + 1, nxt);
       }
       if constexpr (MAXPASS)
