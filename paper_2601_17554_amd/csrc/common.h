@@ -51,9 +51,30 @@ constexpr float kLog2e = 1.4426950408889634f;
 // bounds-checked against num_records (loads past it return zero).
 constexpr int kBufferWord3 = 0x00020000;
 
+// The value of lane (this lane ^ o) for a constant o in 1..32: offsets below 16 move through DPP
+// lane permutations on the VALU (quad_perm xor 1 and xor 2; xor 4 = half-row mirror then xor 3;
+// xor 8 = row mirror then half-row mirror), the others through ds_bpermute. Same values as
+// __shfl_xor, without its LDS round trip for the short offsets.
+__device__ __forceinline__ float xor_lane(float v, int o) {
+  const int x = __float_as_int(v);
+  switch (o) {
+    case 1: return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true));
+    case 2: return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true));
+    case 4: {
+      const int m = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true);
+      return __int_as_float(__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, true));
+    }
+    case 8: {
+      const int m = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true);
+      return __int_as_float(__builtin_amdgcn_mov_dpp(m, 0x141, 0xF, 0xF, true));
+    }
+    default: return __shfl_xor(v, o, 64);
+  }
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int o = 32; o >= 1; o >>= 1) v += xor_lane(v, o);
   return v;
 }
 
@@ -184,15 +205,15 @@ __device__ __forceinline__ u32x4 ln_row_chunk8(const float* x, int col, const fl
   float se = add_nc(0.f, ln_sum4(x[0], x[1], x[2], x[3])), so = add_nc(0.f, ln_sum4(x[4], x[5], x[6], x[7]));
 #pragma unroll
   for (int off = CPR / 2; off >= 1; off >>= 1) {
-    se = add_nc(se, __shfl_xor(se, off, 64));
-    so = add_nc(so, __shfl_xor(so, off, 64));
+    se = add_nc(se, xor_lane(se, off));
+    so = add_nc(so, xor_lane(so, off));
   }
   const float mu = ln_mean(add_nc(se, so), D);
   float qe = add_nc(0.f, ln_sq4(x[0], x[1], x[2], x[3], mu)), qo = add_nc(0.f, ln_sq4(x[4], x[5], x[6], x[7], mu));
 #pragma unroll
   for (int off = CPR / 2; off >= 1; off >>= 1) {
-    qe = add_nc(qe, __shfl_xor(qe, off, 64));
-    qo = add_nc(qo, __shfl_xor(qo, off, 64));
+    qe = add_nc(qe, xor_lane(qe, off));
+    qo = add_nc(qo, xor_lane(qo, off));
   }
   const float rs = ln_rstd(add_nc(qe, qo), D, eps);
   const f32x4 g0 = *(const f32x4*)(g + col), g1 = *(const f32x4*)(g + col + 4);
@@ -215,7 +236,7 @@ __device__ __forceinline__ void unpack_bf16x8(const u32x4& w, float* x) {
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, xor_lane(v, o));
   return v;
 }
 

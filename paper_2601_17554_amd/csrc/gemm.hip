@@ -355,8 +355,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
         // Squared norm of each (row, head) of K from its bf16 values: the dh/8 chunks of one head
         // are consecutive threads (the tile's columns start on a head boundary).
         if (p.knorm) {
-          ss += __shfl_xor(ss, 1, 64);
-          if (p.dh == 32) ss += __shfl_xor(ss, 2, 64);
+          ss += xor_lane(ss, 1);
+          if (p.dh == 32) ss += xor_lane(ss, 2);
           const int rem = col - p.d;
           if (live && rem >= 0 && rem < p.d && rem % p.dh == 0)
             p.knorm[(int64_t)(rem / p.dh) * (p.hstride / p.dh) + row] = ss;
