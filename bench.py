@@ -31,8 +31,8 @@ EVENTS_PER_BATCH = 64
 # (FETCH_SIZE, WRITE_SIZE) of paper_2601_17554_amd/profile_run.py scaled by a 256 MiB copy
 # (profiles/attention_bf16_varlen64_hbm_traffic.md). Valid only for the kernel source it was
 # measured on: reported as null once attention.hip, common.h or kernels.h change.
-ATTN_TRAFFIC = {"sha256": "e3582b704d452b163062cd022738067d51df5d1978f7957bbd8b3a564f7570be",
-                "bytes_per_launch": 453141111.7}
+ATTN_TRAFFIC = {"sha256": "d36b82dd81d48c4c19484757f9eeecdba2f8182f3883f47c52d7e6028819a2b3",
+                "bytes_per_launch": 455789976.5}
 
 
 def attention_traffic():
