@@ -227,7 +227,18 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
 
   // Epilogue: out + b2 staged through LDS as FP32 rows, then h = bf16(h + out) in 16-byte row
   // chunks (8 values; the sum in FP32). Lane l of a 32x32 block holds column l%32 of rows
-  // 8*(r/4) + 4*(l/32) + r%4.
+  // 8*(r/4) + 4*(l/32) + r%4. The h chunks this thread updates are loaded first, so that their
+  // latency passes during the staging.
+  constexpr int CPR = D / 8;
+  constexpr int ROUNDS = BM * CPR / NT;
+  static_assert(BM * CPR % NT == 0, "epilogue rounds");
+  u32x4 hv[ROUNDS];
+#pragma unroll
+  for (int q = 0; q < ROUNDS; ++q) {
+    const int t = tid + q * NT, row = t / CPR, col = (t % CPR) * 8;
+    hv[q] = m0 + row < M ? *(const u32x4*)((const __bf16*)p.h + (int64_t)(m0 + row) * D + col)
+                         : u32x4{0, 0, 0, 0};
+  }
 #pragma unroll
   for (int a = 0; a < FM2; ++a)
 #pragma unroll
@@ -245,12 +256,12 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
   // statistics when the next block's LN1 is fused here (y_next), with the reduction tree of the
   // LayerNorm kernel (its lane l holds values 4l..4l+3: thread j = its lanes 2j, 2j+1), so the
   // output matches that kernel bit for bit.
-  constexpr int CPR = D / 8;
-  for (int t = tid; t < BM * CPR; t += NT) {
-    const int row = t / CPR, col = (t % CPR) * 8;
+#pragma unroll
+  for (int q = 0; q < ROUNDS; ++q) {
+    const int t = tid + q * NT, row = t / CPR, col = (t % CPR) * 8;
     const bool live = m0 + row < M;
     u32x4* dst = (u32x4*)((__bf16*)p.h + (int64_t)(m0 + row) * D + col);
-    const u32x4 o = live ? *dst : u32x4{0, 0, 0, 0};
+    const u32x4 o = hv[q];
     const f32x4 v0 = *(const f32x4*)(smem + row * L::SRS + col * 4);
     const f32x4 v1 = *(const f32x4*)(smem + row * L::SRS + col * 4 + 16);
     const u32x2 lo = pack_bf16x4(v0[0] + __uint_as_float(o[0] << 16), v0[1] + __uint_as_float(o[0] & 0xffff0000u),
