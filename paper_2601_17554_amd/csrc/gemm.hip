@@ -210,6 +210,23 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   constexpr bool kResB16 = (EPI == E_BIAS_B || EPI == E_RESID_B);
   constexpr int OSZ = kResF32 ? 4 : kResB16 ? 2 : (int)sizeof(S);
   constexpr int EO = 16 / OSZ;                           // output elements per 16-byte chunk
+  constexpr int CPR = BN / EO;                           // chunks per staged row
+  // bf16 residual update: the h chunks of a pass are loaded before its staging, so that their
+  // latency passes meanwhile (the next pass's right after this pass's last use).
+  constexpr bool kPrefH = (EPI == E_RESID_B);
+  constexpr int RPP = (PROWS * CPR + NT - 1) / NT;       // chunks per thread and pass
+  [[maybe_unused]] u32x4 hv[kPrefH ? RPP : 1];
+  [[maybe_unused]] auto hload = [&](int pass) {
+#pragma unroll
+    for (int q = 0; q < RPP; ++q) {
+      const int c = tid + q * NT;
+      const int row = m0 + pass * PROWS + c / CPR, col = n0 + (c % CPR) * EO;
+      hv[q] = (c < PROWS * CPR && row < M && col < p.N)
+                  ? *(const u32x4*)((const __bf16*)p.out + (int64_t)row * p.ldo + col)
+                  : u32x4{0, 0, 0, 0};
+    }
+  };
+  if constexpr (kPrefH) hload(0);
 #pragma unroll
   for (int pass = 0; pass < PASSES; ++pass) {
     if (PASSES == 1 || wm == pass) {
@@ -283,7 +300,29 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
       continue;
     }
     __syncthreads();
-    constexpr int CPR = BN / EO;                         // chunks per staged row
+    if constexpr (kPrefH) {
+#pragma unroll
+      for (int q = 0; q < RPP; ++q) {
+        const int c = tid + q * NT;
+        if (PROWS * CPR % NT != 0 && c >= PROWS * CPR) break;
+        const int lrow = c / CPR, lc = (c % CPR) * EO;
+        const int row = m0 + pass * PROWS + lrow, col = n0 + lc;
+        if (row < M && col < p.N) {
+          const float* src = (const float*)(smem + lrow * SRS + lc * 4);
+          const u32x4 o = hv[q];
+          const f32x4 v0 = *(const f32x4*)src + f32x4{__uint_as_float(o[0] << 16), __uint_as_float(o[0] & 0xffff0000u),
+                                                      __uint_as_float(o[1] << 16), __uint_as_float(o[1] & 0xffff0000u)};
+          const f32x4 v1 = *(const f32x4*)(src + 4) + f32x4{__uint_as_float(o[2] << 16), __uint_as_float(o[2] & 0xffff0000u),
+                                                            __uint_as_float(o[3] << 16), __uint_as_float(o[3] & 0xffff0000u)};
+          const u32x2 lo = pack_bf16x4(v0[0], v0[1], v0[2], v0[3]);
+          const u32x2 hi = pack_bf16x4(v1[0], v1[1], v1[2], v1[3]);
+          *(u32x4*)((__bf16*)p.out + (int64_t)row * p.ldo + col) = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        }
+      }
+      if (pass + 1 < PASSES) hload(pass + 1);
+      if (PASSES > 1 && pass + 1 < PASSES) __syncthreads();
+      continue;
+    }
     for (int c = tid; c < PROWS * CPR; c += NT) {
       const int lrow = c / CPR, lc = (c % CPR) * EO;
       const int row = m0 + pass * PROWS + lrow, col = n0 + lc;
@@ -297,15 +336,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
         if constexpr (EPI == E_RESID) v += *dst;
         *dst = v;
       } else if constexpr (kResB16) {
-        f32x4 v0 = *(const f32x4*)src, v1 = *(const f32x4*)(src + 4);
+        const f32x4 v0 = *(const f32x4*)src, v1 = *(const f32x4*)(src + 4);
         u32x4* dst = (u32x4*)((__bf16*)p.out + (int64_t)row * p.ldo + col);
-        if constexpr (EPI == E_RESID_B) {
-          const u32x4 o = *dst;
-          v0 += f32x4{__uint_as_float(o[0] << 16), __uint_as_float(o[0] & 0xffff0000u),
-                      __uint_as_float(o[1] << 16), __uint_as_float(o[1] & 0xffff0000u)};
-          v1 += f32x4{__uint_as_float(o[2] << 16), __uint_as_float(o[2] & 0xffff0000u),
-                      __uint_as_float(o[3] << 16), __uint_as_float(o[3] & 0xffff0000u)};
-        }
         const u32x2 lo = pack_bf16x4(v0[0], v0[1], v0[2], v0[3]);
         const u32x2 hi = pack_bf16x4(v1[0], v1[1], v1[2], v1[3]);
         *dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
