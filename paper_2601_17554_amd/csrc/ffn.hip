@@ -170,11 +170,25 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
 #pragma unroll
     for (int b = 0; b < FN2; ++b) acc[a][b] = f32x16{};
 
+  // b1 values of a chunk are loaded one chunk ahead: the wait at the end of each chunk covers them,
+  // so GELU never waits on the weight copies in flight (outstanding loads complete in issue order,
+  // and the copies' count is not known to the compiler).
+  f32x4 bq_next[4];
+  auto load_b1 = [&](int c) {
+    const float* b1 = p.b1 + c * kFfnHC + 32 * hb + 4 * h;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bq_next[q] = *(const f32x4*)(b1 + 8 * q);
+  };
+  load_b1(0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
   for (int c = 0; c < nch; ++c) {
     const int buf = DBUF ? (c & 1) : 0;
+    f32x4 bq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bq[q] = bq_next[q];
+    if (c + 1 < nch) load_b1(c + 1);
     if (DBUF && c + 1 < nch) {
       copy_to_lds<NT>(w1p + (size_t)(c + 1) * L::W1CH, w1buf + (buf ^ 1) * L::W1CH, L::W1CH, wave, lane);
       copy_to_lds<NT>(w2p + (size_t)(c + 1) * L::W2CH, w2buf + (buf ^ 1) * L::W2CH, L::W2CH, wave, lane);
@@ -182,18 +196,25 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
     // Phase 1: this wave's 32x32 block of U^T, summed over k = 0 .. D-1 in order.
     {
       const char* w1 = w1buf + buf * L::W1CH + (32 * hb + i) * L::W1RS + 16 * h;
+      // The W1 fragments are read in two halves, each issued before its MFMAs (one LDS wait per
+      // half rather than one per fragment pair).
       f32x16 u = f32x16{};
 #pragma unroll
-      for (int g = 0; g < KG1; ++g) mma_kg<BF16>(*(const u32x4*)(w1 + 32 * g), yf[g], u);
+      for (int half = 0; half < 2; ++half) {
+        u32x4 wf[KG1 / 2];
+#pragma unroll
+        for (int g = 0; g < KG1 / 2; ++g) wf[g] = *(const u32x4*)(w1 + 32 * (half * KG1 / 2 + g));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < KG1 / 2; ++g) mma_kg<BF16>(wf[g], yf[half * KG1 / 2 + g], u);
+      }
       // Lane holds row 32 tb + i and hidden units 32 hb + 8 q + 4 h + (0..3) in registers 4q..4q+3.
-      const float* b1 = p.b1 + c * kFfnHC + 32 * hb + 4 * h;
       char* urow = ubuf + (32 * tb + i) * L::URS + (32 * hb + 4 * h) * 2;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const f32x4 bq = *(const f32x4*)(b1 + 8 * q);
         *(u32x2*)(urow + 16 * q) =
-            pack_bf16x4(gelu_erf(u[4 * q] + bq[0]), gelu_erf(u[4 * q + 1] + bq[1]),
-                        gelu_erf(u[4 * q + 2] + bq[2]), gelu_erf(u[4 * q + 3] + bq[3]));
+            pack_bf16x4(gelu_erf(u[4 * q] + bq[q][0]), gelu_erf(u[4 * q + 1] + bq[q][1]),
+                        gelu_erf(u[4 * q + 2] + bq[q][2]), gelu_erf(u[4 * q + 3] + bq[q][3]));
       }
     }
     __syncthreads();
