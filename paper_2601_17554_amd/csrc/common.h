@@ -194,13 +194,14 @@ __device__ __forceinline__ float add_nc(float a, float b) {
 }
 
 // LayerNorm of a row of D = 8 CPR bf16 values held by CPR consecutive lanes (lane-aligned groups),
-// each with 8 consecutive values x[0..7] starting at column col; returns the 8 outputs as bf16.
+// each with 8 consecutive values x[0..7] (gamma g0, g1 and beta b0, b1 of those 8 columns); returns
+// the 8 outputs as bf16.
 // The sums follow the LayerNorm kernel's tree (its lane l holds values 4l .. 4l+3, so this lane's
 // halves are its lanes 2j and 2j+1; zero lanes beyond D add exactly nothing), so the result is that
 // kernel's bit for bit. Every lane of the group must call it (shuffles).
 template <int CPR>
-__device__ __forceinline__ u32x4 ln_row_chunk8(const float* x, int col, const float* g, const float* b,
-                                               float eps) {
+__device__ __forceinline__ u32x4 ln_row_chunk8(const float* x, const f32x4& g0, const f32x4& g1,
+                                               const f32x4& b0, const f32x4& b1, float eps) {
   constexpr int D = 8 * CPR;
   float se = add_nc(0.f, ln_sum4(x[0], x[1], x[2], x[3])), so = add_nc(0.f, ln_sum4(x[4], x[5], x[6], x[7]));
 #pragma unroll
@@ -216,8 +217,6 @@ __device__ __forceinline__ u32x4 ln_row_chunk8(const float* x, int col, const fl
     qo = add_nc(qo, xor_lane(qo, off));
   }
   const float rs = ln_rstd(add_nc(qe, qo), D, eps);
-  const f32x4 g0 = *(const f32x4*)(g + col), g1 = *(const f32x4*)(g + col + 4);
-  const f32x4 b0 = *(const f32x4*)(b + col), b1 = *(const f32x4*)(b + col + 4);
   const u32x2 lo = pack_bf16x4(ln_out(x[0], mu, rs, g0[0], b0[0]), ln_out(x[1], mu, rs, g0[1], b0[1]),
                                ln_out(x[2], mu, rs, g0[2], b0[2]), ln_out(x[3], mu, rs, g0[3], b0[3]));
   const u32x2 hi = pack_bf16x4(ln_out(x[4], mu, rs, g1[0], b1[0]), ln_out(x[5], mu, rs, g1[1], b1[1]),

@@ -35,7 +35,8 @@ struct FfnLayout {
   static constexpr int NBUF = DBUF ? 2 : 1;
   static constexpr int URS = 2 * kFfnHC + 16;   // U row: one token row, kFfnHC hidden units
   static constexpr int U_BYTES = BM * URS;
-  static constexpr int LDS = NBUF * (W1CH + W2CH) + U_BYTES;
+  static constexpr int LN_OFF = NBUF * (W1CH + W2CH) + U_BYTES;  // LN2 gamma, beta (FP32)
+  static constexpr int LDS = LN_OFF + 2 * D * 4;
   static constexpr int SRS = 4 * D + 16;        // epilogue staging row (FP32)
   static_assert(BM * SRS <= LDS, "epilogue staging does not fit");
 };
@@ -161,7 +162,15 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
     for (int g = 0; g < KG1; ++g)
       yf[g] = row < M ? *(const u32x4*)(yr + 16 * g + 8 * h) : u32x4{0, 0, 0, 0};
   }
-  if (p.ln_in_g) ln_fragments<KG1>(yf, h, p.ln_in_g, p.ln_in_b, p.ln_in_eps);
+  if (p.ln_in_g) {
+    // gamma and beta through LDS (one copy, short latency) rather than per fragment from memory.
+    const float* lg = (const float*)(smem + L::LN_OFF);
+    copy_to_lds<NT>((const char*)p.ln_in_g, smem + L::LN_OFF, D * 4, wave, lane);
+    copy_to_lds<NT>((const char*)p.ln_in_b, smem + L::LN_OFF + D * 4, D * 4, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    ln_fragments<KG1>(yf, h, lg, lg + D, p.ln_in_eps);
+  }
   // Phase-2 role: FM2 x FN2 blocks of 32x32 outputs.
   const int wm2 = wave / WN2, wn2 = wave % WN2;
   f32x16 acc[FM2][FN2];
@@ -252,7 +261,16 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
   // latency passes during the staging.
   constexpr int CPR = D / 8;
   constexpr int ROUNDS = BM * CPR / NT;
-  static_assert(BM * CPR % NT == 0, "epilogue rounds");
+  static_assert(BM * CPR % NT == 0 && NT % CPR == 0, "epilogue rounds");
+  // Every round of this thread covers the same 8 columns: their LN gamma and beta load once.
+  f32x4 lng[2], lnb[2];
+  if (p.y_next) {
+    const int col = (tid % CPR) * 8;
+    lng[0] = *(const f32x4*)(p.ln_g + col);
+    lng[1] = *(const f32x4*)(p.ln_g + col + 4);
+    lnb[0] = *(const f32x4*)(p.ln_b + col);
+    lnb[1] = *(const f32x4*)(p.ln_b + col + 4);
+  }
   u32x4 hv[ROUNDS];
 #pragma unroll
   for (int q = 0; q < ROUNDS; ++q) {
@@ -294,7 +312,7 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
     if (p.y_next) {
       float x[8];
       unpack_bf16x8(hn, x);
-      const u32x4 yn = ln_row_chunk8<CPR>(x, col, p.ln_g, p.ln_b, p.ln_eps);
+      const u32x4 yn = ln_row_chunk8<CPR>(x, lng[0], lng[1], lnb[0], lnb[1], p.ln_eps);
       if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)(m0 + row) * D + col) = yn;
     }
   }
