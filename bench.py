@@ -25,6 +25,9 @@ import synth  # noqa: E402
 
 METRIC = "events/sec + p50/p99 ms/event, BF16 varlen vs FP32 plain, 1 MI355X"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+# exp2 ceiling of the BF16 attention: transcendentals issue at a quarter of the FP32 vector rate
+# (157.3 TFLOP/s = 32 FMA lanes per SIMD x 1024 SIMDs x 2.4 GHz), i.e. 8 lanes per cycle per SIMD.
+PEAK_EXP_T_PER_S = 1024 * 8 * 2.4e9 / 1e12
 EVENTS_PER_BATCH = 64
 
 # HBM bytes per launch of the BF16 attention kernel on these batches, from two rocprofv3 --pmc runs
@@ -231,6 +234,7 @@ def main():
     attn_avg_ms = vr["attn_ms"] / max(vr["attn_launches"], 1)
     attn_flops_per_launch = vr["attn_flops"] / max(vr["attn_launches"], 1)
     achieved = attn_flops_per_launch / (attn_avg_ms * 1e-3) / 1e12
+    exp_rate = attn_flops_per_launch * cfg.n_heads / (4.0 * cfg.d_model) / (attn_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     pl_attn_ms, pl_attn_n = pl["prof"]["attention"]
     pl_achieved = (pl["attn_flops"] / max(pl_attn_n, 1)) / (pl_attn_ms / max(pl_attn_n, 1) * 1e-3) / 1e12
@@ -265,7 +269,10 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "attention", "achieved": round(achieved, 1),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": attention_traffic() if args.precision == "bf16" else None,
-                     "traffic_unit": "bytes per launch (HBM)", "avg_launch_ms": round(attn_avg_ms, 4)},
+                     "traffic_unit": "bytes per launch (HBM)", "avg_launch_ms": round(attn_avg_ms, 4),
+                     # One exp2 per score: h * sum N^2 per launch, against the transcendental rate.
+                     "exp_ceiling": {"achieved": round(exp_rate, 2), "peak": round(PEAK_EXP_T_PER_S, 2),
+                                     "unit": "Texp/s", "frac": round(exp_rate / PEAK_EXP_T_PER_S, 4)}},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in vr["prof"].items()},
     }
     if args.serve_rates:

@@ -90,14 +90,19 @@ def test_full_event_from_workload(B, prec):
         check_event(got, ref, pk.event_rows(0), TOL[prec], f"full-{prec} event {i}")
 
 
-def test_fp32_max_seqlen_8192(B):
-    """The largest event (8192 elements) through a one-block full-width model."""
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_max_seqlen_8192(B, prec):
+    """The largest event (8192 elements) through a one-block full-width model, alone and beside a
+    one-element event in the same launch (BF16: the bound-offset attention, fused FFN and heads)."""
     cfg = synth.Config(d_model=256, n_heads=8, d_ff=1024, n_layers=1)
-    w, m = _model(B, cfg, 4, "fp32", sharpen=4.0)
+    w, m = _model(B, cfg, 4, prec, sharpen=4.0)
     ev = synth.make_event(77, 8192)
-    pk = synth.pack([ev])
+    one = synth.make_event(78, 1)
+    pk = synth.pack([ev, one])
     got = run_gpu(m, pk)
-    check_event(got, O.forward(ev.x, w, cfg), pk.event_rows(0), TOL["fp32"], "8192")
+    ref = oracle(ev.x, w, cfg, ("max8192", 4))
+    check_event(got, ref, pk.event_rows(0), TOL[prec], f"8192 {prec}")
+    check_event(got, O.forward(one.x, w, cfg), pk.event_rows(1), TOL[prec], f"8192 + 1 {prec}")
 
 
 @pytest.mark.parametrize("cfg", [
