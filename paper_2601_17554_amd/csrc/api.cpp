@@ -296,8 +296,9 @@ struct Ctx {
   void* p(size_t off) const { return ws + off; }
 };
 
-// Default attention tile: BF16 takes the score-bound kernel with 8 waves per workgroup.
-constexpr int kDefaultAttnTileBf16 = 10;
+// Default attention tile: BF16 takes the score-bound kernel, 4 waves x 2 query blocks, no look-ahead
+// product, three waves per SIMD.
+constexpr int kDefaultAttnTileBf16 = 14;
 int attn_tile_of(const mlpf_model_s* m) {
   if (m->tune[MLPF_OP_ATTENTION] >= 0) return m->tune[MLPF_OP_ATTENTION];
   return m->kprec == P_BF16 ? kDefaultAttnTileBf16 : 0;
@@ -407,7 +408,7 @@ mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const v
   at.ev_n = (const int32_t*)cx.p(cx.w.ev_n);
   at.cap_items = cx.w.cap_items;
   const int tile = attn_tile_of(m);
-  if (m->kprec == P_BF16 && attn_tile(tile).kind == 1) {
+  if (m->kprec == P_BF16 && attn_tile(tile).kind >= 1) {
     // Squared key norms for the score bound: written by the QKV projection in the forward pass,
     // computed here for mlpf_attention_forward (timed with the QKV class).
     float* kn = (float*)cx.p(cx.w.knorm);
@@ -455,7 +456,7 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
   q.dh = dh;
   q.q_scale = (float)(1.4426950408889634 / std::sqrt((double)dh));
   // The BF16 score-bound attention reads squared key norms: the projection's epilogue writes them.
-  const bool kn_fused = m->kprec == P_BF16 && attn_tile(attn_tile_of(m)).kind == 1;
+  const bool kn_fused = m->kprec == P_BF16 && attn_tile(attn_tile_of(m)).kind >= 1;
   if (kn_fused) q.knorm = (float*)cx.p(cx.w.knorm);
   {
     ProfScope prof(cx.m, MLPF_PROF_QKV, cx.s);

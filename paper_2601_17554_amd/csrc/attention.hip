@@ -320,7 +320,9 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
 //
 // Key loop: 32-key blocks, software pipelined (the QK^T product of block b+1 is issued before the
 // exponentials of block b, with the two score sets in alternating registers, and its K fragments
-// were read from LDS a step earlier). K and V stages of
+// were read from LDS a step earlier). PIPE false drops the look-ahead: each block is scored
+// and consumed in one step, and the score set fewer in registers lets three waves share a SIMD,
+// whose interleaving then hides the MFMA latency (the faster form at d_head 32). K and V stages of
 // 32*G keys rotate through three LDS slots: while stage s is consumed, stage s+1 is resident (the
 // look-ahead product reads it) and stage s+2 travels from global memory in registers; one barrier
 // per stage. Each wave owns QB blocks of 32 queries. V stays row-major in LDS (one 16-byte store
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
 // each 16-lane group, lane j receives element j%4 of the 8-byte chunks addressed by lanes j/4,
 // j/4+4, j/4+8 and j/4+12 of the group, so lane s addresses row (key) s/4 and dh columns
 // 4(s%4)..4(s%4)+3 and every lane gets one dh column of four consecutive keys.
-template <int DH, int NW, int G, int QB, int OCC>
+template <int DH, int NW, int G, int QB, int OCC, bool PIPE>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(OCC)))
 void attn_bf16_kernel(const AttnArgs p) {
   constexpr int NT = NW * 64;
@@ -513,13 +515,13 @@ void attn_bf16_kernel(const AttnArgs p) {
     if (nst > 2) load(2, rk, rv);
 
     f32x16 sa[QB], sb[QB];
-    u32x4 kn[QKG];  // K fragments of the block after the one in `cur`, read a step ahead
-    if (nblk > 0) {
+    u32x4 kn[QKG];  // K fragments of the next block to score, read a step ahead
+    if (PIPE && nblk > 0) {
       kread(0, kn);
       scores(kn, sa, c0);
       if (nblk == 1 && (n & 31)) mask(0, sa);
     }
-    if (nblk > 1) kread(1, kn);
+    if (PIPE && nblk > 1) kread(1, kn);
     // Block b of stage st (position bb) is in `cur`; the look-ahead product fills `nxt` from the
     // K fragments read during the previous step, and the fragments of block b + 2 (in stage st or
     // st + 1, both resident) are read for the next one. Past the last block both repeat the last
@@ -539,13 +541,31 @@ void attn_bf16_kernel(const AttnArgs p) {
       else
         consume(slot, bb, cur);
     };
+    // Without the look-ahead (PIPE false): block b is scored and consumed in the same step, with one
+    // score set fewer in registers (more waves per SIMD hide the MFMA latency instead).
+    auto step_np = [&](int st, int slot, int bb) {
+      const int b = st * G + bb;
+      u32x4 ka[QKG];
+      kread(b, ka);
+      scores(ka, sa, c0);
+      if (b + 1 == nblk && (n & 31)) mask(b, sa);
+      if constexpr (MAXPASS)
+        take_max(sa);
+      else
+        consume(slot, bb, sa);
+    };
     int slot = 0;
     for (int st = 0; st < nst; ++st) {
 #pragma unroll
       for (int bb = 0; bb < G; bb += 2) {
         const int b = st * G + bb;
-        if (b < nblk) step(st, slot, bb, sa, sb);
-        if (b + 1 < nblk) step(st, slot, bb + 1, sb, sa);
+        if constexpr (PIPE) {
+          if (b < nblk) step(st, slot, bb, sa, sb);
+          if (b + 1 < nblk) step(st, slot, bb + 1, sb, sa);
+        } else {
+          if (b < nblk) step_np(st, slot, bb);
+          if (b + 1 < nblk) step_np(st, slot, bb + 1);
+        }
       }
       if (st + 2 < nst) store(slot == 0 ? 2 : slot - 1, rk, rv);
       __syncthreads();
@@ -642,6 +662,10 @@ constexpr AttnTile kTiles[] = {
     {4, 64, 1, 1},  // as 6, registers capped for 4 waves per SIMD
     {2, 64, 2, 1},
     {4, 128, 2, 1},
+    // the same without the look-ahead product (kind 2), registers capped for 3 or 4 waves per SIMD
+    {4, 64, 2, 2},
+    {4, 128, 2, 2},
+    {4, 64, 1, 2},
 };
 
 template <class T, int DH, int NW, int KT, int QB>
@@ -651,14 +675,14 @@ hipError_t launch_t(const AttnArgs& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <class T, int DH, int NW, int KT, int QB, int OCC = 1>
+template <class T, int DH, int NW, int KT, int QB, int OCC = 1, bool PIPE = true>
 hipError_t launch_b(const AttnArgs& p, hipStream_t s) {
   if constexpr (!std::is_same_v<T, BF16>) {
     return launch_t<T, DH, NW, KT, QB>(p, s);
   } else {
     if (p.cap_items <= 0) return hipSuccess;
     if (p.knorm == nullptr) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((attn_bf16_kernel<DH, NW, KT / 32, QB, OCC>), dim3(p.cap_items), dim3(NW * 64),
+    hipLaunchKernelGGL((attn_bf16_kernel<DH, NW, KT / 32, QB, OCC, PIPE>), dim3(p.cap_items), dim3(NW * 64),
                        0, s, p);
     return hipGetLastError();
   }
@@ -681,6 +705,9 @@ hipError_t launch_dh(int tile, const AttnArgs& p, hipStream_t s) {
     case 11: return launch_b<T, DH, 4, 64, 1, 4>(p, s);
     case 12: return launch_b<T, DH, 2, 64, 2>(p, s);
     case 13: return launch_b<T, DH, 4, 128, 2>(p, s);
+    case 14: return launch_b<T, DH, 4, 64, 2, 3, false>(p, s);
+    case 15: return launch_b<T, DH, 4, 128, 2, 3, false>(p, s);
+    case 16: return launch_b<T, DH, 4, 64, 1, 4, false>(p, s);
     default: return hipErrorInvalidValue;
   }
 }

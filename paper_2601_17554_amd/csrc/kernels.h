@@ -116,7 +116,8 @@ struct AttnTile {
   int waves;  // waves per workgroup
   int kt;     // keys per LDS tile
   int qb;     // 32-query blocks per wave; queries per work item = 32 * waves * qb
-  int kind;   // 0: two-buffer online-softmax kernel; 1: BF16 bound-offset kernel (needs knorm)
+  int kind;   // 0: two-buffer online-softmax kernel; 1: BF16 bound-offset kernel (needs knorm);
+              // 2: the bound-offset kernel without the look-ahead product
 };
 int attn_num_tiles();
 AttnTile attn_tile(int id);
