@@ -375,7 +375,11 @@ void attn_bf16_kernel(const AttnArgs p) {
 
   int qi[QB];
   u32x4 qr[QB][QKG];
-  f32x16 cneg[QB];
+  // PIPE: the offset -m_q as the QK^T MFMA's C operand (16 registers per query block). Otherwise no
+  // offset while every bound m_q <= 64 (scores, P and the sums stay far inside the FP32 and bf16
+  // ranges), else exp2(s - m_q) with the offset kept once per query.
+  f32x16 cneg[PIPE ? QB : 1];
+  float mq_[QB];
 #pragma unroll
   for (int j = 0; j < QB; ++j) {
     qi[j] = (qtile * NW + wave) * (32 * QB) + 32 * j + i;
@@ -393,8 +397,11 @@ void attn_bf16_kernel(const AttnArgs p) {
     qn2 += other_half(qn2);
     // Scores are sums of DH exact products in FP32: |s - q.k| <= DH * 2^-24 |q| |k|.
     const float mq = sqrtf(qn2 * kn2) * (1.f + 0x1p-12f);
+    mq_[j] = mq;
+    if constexpr (PIPE) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) cneg[j][r] = -mq;
+      for (int r = 0; r < 16; ++r) cneg[j][r] = -mq;
+    }
   }
 
   // Bounded buffer loads: zeros past the event's last key.
@@ -455,7 +462,9 @@ void attn_bf16_kernel(const AttnArgs p) {
   typedef __attribute__((address_space(3))) tr4 lds_tr4;
   const int j16 = i & 15;
   const int vcol = ((DH == 32 ? (i & 16) : 0) + 4 * (j16 & 3)) * 2;  // byte column this lane addresses
-  auto consume = [&](int slot, int bb, const f32x16 (&s)[QB]) {
+  float msh[QB];  // the per-query shift of the exponents when SHIFT (PIPE false)
+  auto consume = [&](int slot, int bb, const f32x16 (&s)[QB], auto shift_tag) {
+    constexpr bool SHIFT = decltype(shift_tag)::value;
     const char* Vs = smem + slot * SLOT + K_BYTES;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -471,10 +480,10 @@ void attn_bf16_kernel(const AttnArgs p) {
         u32x4 pb;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const float e0 = __builtin_amdgcn_exp2f(s[j][8 * c + 4 * q + 0]);
-          const float e1 = __builtin_amdgcn_exp2f(s[j][8 * c + 4 * q + 1]);
-          const float e2 = __builtin_amdgcn_exp2f(s[j][8 * c + 4 * q + 2]);
-          const float e3 = __builtin_amdgcn_exp2f(s[j][8 * c + 4 * q + 3]);
+          const float e0 = __builtin_amdgcn_exp2f(SHIFT ? s[j][8 * c + 4 * q + 0] - msh[j] : s[j][8 * c + 4 * q + 0]);
+          const float e1 = __builtin_amdgcn_exp2f(SHIFT ? s[j][8 * c + 4 * q + 1] - msh[j] : s[j][8 * c + 4 * q + 1]);
+          const float e2 = __builtin_amdgcn_exp2f(SHIFT ? s[j][8 * c + 4 * q + 2] - msh[j] : s[j][8 * c + 4 * q + 2]);
+          const float e3 = __builtin_amdgcn_exp2f(SHIFT ? s[j][8 * c + 4 * q + 3] - msh[j] : s[j][8 * c + 4 * q + 3]);
           const u32x2 pk = pack_bf16x4(e0, e1, e2, e3);
           l_run[j] = add_bf16x4(e0, e1, e2, e3, l_run[j]);
           pb[2 * q] = pk[0];
@@ -501,7 +510,7 @@ void attn_bf16_kernel(const AttnArgs p) {
   const int nblk = (n + 31) >> 5;
   const int nst = (nblk + G - 1) / G;
   // One sweep over the keys through the LDS stages; MAXPASS: maxima only.
-  auto sweep = [&](auto maxpass_tag, const f32x16 (&c0)[QB]) {
+  auto sweep = [&](auto maxpass_tag, const f32x16 (&c0)[QB], auto shift_tag) {
     constexpr bool MAXPASS = decltype(maxpass_tag)::value;
     {
       u32x4 rk0[PT], rv0[PT], rk1[PT], rv1[PT];
@@ -539,7 +548,7 @@ void attn_bf16_kernel(const AttnArgs p) {
       if constexpr (MAXPASS)
         take_max(cur);
       else
-        consume(slot, bb, cur);
+        consume(slot, bb, cur, shift_tag);
     };
     // Without the look-ahead (PIPE false): block b is scored and consumed in the same step, with one
     // score set fewer in registers (more waves per SIMD hide the MFMA latency instead).
@@ -552,7 +561,7 @@ void attn_bf16_kernel(const AttnArgs p) {
       if constexpr (MAXPASS)
         take_max(sa);
       else
-        consume(slot, bb, sa);
+        consume(slot, bb, sa, shift_tag);
     };
     int slot = 0;
     for (int st = 0; st < nst; ++st) {
@@ -579,7 +588,23 @@ void attn_bf16_kernel(const AttnArgs p) {
     l_run[j] = 0.f;
     oacc[j] = f32x16{};
   }
-  sweep(std::false_type{}, cneg);
+  f32x16 zero[QB];
+#pragma unroll
+  for (int j = 0; j < QB; ++j) zero[j] = f32x16{};
+  if constexpr (PIPE) {
+    sweep(std::false_type{}, cneg, std::false_type{});
+  } else {
+    bool big = false;
+#pragma unroll
+    for (int j = 0; j < QB; ++j) big = big || (qi[j] < n && !(mq_[j] <= 64.f));
+    if (__syncthreads_or(big)) {
+#pragma unroll
+      for (int j = 0; j < QB; ++j) msh[j] = mq_[j];
+      sweep(std::false_type{}, zero, std::true_type{});
+    } else {
+      sweep(std::false_type{}, zero, std::false_type{});
+    }
+  }
 
   // Fallback when a bound was too loose: l >= 2^-(bound - max) and that fell below 2^-96.
   bool loose = false;
@@ -589,22 +614,25 @@ void attn_bf16_kernel(const AttnArgs p) {
     loose = loose || (qi[j] < n && !(l_tot >= 0x1p-96f) && l_tot == l_tot);
   }
   if (__syncthreads_or(loose)) {
-    f32x16 zero[QB];
 #pragma unroll
-    for (int j = 0; j < QB; ++j) {
-      zero[j] = f32x16{};
-      m_ex[j] = -INFINITY;
-    }
-    sweep(std::true_type{}, zero);
+    for (int j = 0; j < QB; ++j) m_ex[j] = -INFINITY;
+    sweep(std::true_type{}, zero, std::false_type{});
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
       const float mx = fmaxf(m_ex[j], other_half(m_ex[j]));
+      if constexpr (PIPE) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) cneg[j][r] = -mx;
+        for (int r = 0; r < 16; ++r) cneg[j][r] = -mx;
+      } else {
+        msh[j] = mx;
+      }
       l_run[j] = 0.f;
       oacc[j] = f32x16{};
     }
-    sweep(std::false_type{}, cneg);
+    if constexpr (PIPE)
+      sweep(std::false_type{}, cneg, std::false_type{});
+    else
+      sweep(std::false_type{}, zero, std::true_type{});
   }
 
   // O = O^T / l. Lane l holds dh = 8c + 4*(l/32) + (0..3) of query l%32 in registers 4c..4c+3.
@@ -666,6 +694,7 @@ constexpr AttnTile kTiles[] = {
     {4, 64, 2, 2},
     {4, 128, 2, 2},
     {4, 64, 1, 2},
+    {4, 64, 2, 2},  // as 14, registers capped for 4 waves per SIMD
 };
 
 template <class T, int DH, int NW, int KT, int QB>
@@ -708,6 +737,7 @@ hipError_t launch_dh(int tile, const AttnArgs& p, hipStream_t s) {
     case 14: return launch_b<T, DH, 4, 64, 2, 3, false>(p, s);
     case 15: return launch_b<T, DH, 4, 128, 2, 3, false>(p, s);
     case 16: return launch_b<T, DH, 4, 64, 1, 4, false>(p, s);
+    case 17: return launch_b<T, DH, 4, 64, 2, 4, false>(p, s);
     default: return hipErrorInvalidValue;
   }
 }
