@@ -39,9 +39,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   constexpr bool kSplit = (T::kBytes == 4);
   static_assert(C % 2 == 0 && FM >= 1 && FN >= 1, "bad tile");
 
-  // Epilogue staging (FP32 rows of the tile): one pass, or one pass per wave row when the full tile
-  // does not fit the main loop's LDS. E_HEADS stages bf16 rows and the head's slice of W2 instead.
-  constexpr int SRS = BN * 4 + 16;                       // staging row stride (bytes)
+  // Epilogue staging: rows of the tile, FP32, or bf16 where the output is exactly the bf16 rounding
+  // of the staged value (so the rounding happens once, on the way into LDS); one pass, or one pass
+  // per wave row when the full tile does not fit the main loop's LDS. E_HEADS stages bf16 rows and
+  // the head's slice of W2 instead.
+  constexpr bool kStageB16 = (EPI == E_QKV || EPI == E_GELU) ? sizeof(S) == 2 : EPI == E_BIAS_B;
+  constexpr int SRS = BN * (kStageB16 ? 2 : 4) + 16;    // staging row stride (bytes)
   constexpr int MAIN = 2 * (A_BYTES + B_BYTES);
   constexpr int PASSES = (BM * SRS <= MAIN || WM == 1) ? 1 : WM;
   constexpr int PROWS = BM / PASSES;                     // rows staged per pass
@@ -245,10 +248,14 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
               v = gelu_erf(v);
               if (m0 + pass * PROWS + lrow < M && col < p.N) amax = fmaxf(amax, fabsf(v));
             }
-            if constexpr (EPI == E_HEADS)  // the hidden layer, bf16 rows of kHeadsRS bytes
+            if constexpr (EPI == E_HEADS) {  // the hidden layer, bf16 rows of kHeadsRS bytes
               *(__bf16*)(smem + lrow * kHeadsRS + lcol * 2) = (__bf16)gelu_erf(v);
-            else
+            } else if constexpr (kStageB16) {
+              if constexpr (EPI == E_QKV) v *= col < p.d ? p.q_scale : 1.f;  // Q pre-scaled
+              *(__bf16*)(smem + lrow * SRS + lcol * 2) = (__bf16)v;
+            } else {
               *(float*)(smem + lrow * SRS + lcol * 4) = v;
+            }
           }
         }
       }
@@ -329,20 +336,16 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
       const bool live = row < M && col < p.N;
       [[maybe_unused]] float ss = 0.f;  // E_QKV with knorm: sum of squares of this K chunk
       if (live) {
-      const float* src = (const float*)(smem + lrow * SRS + lc * 4);
+      const float* src = (const float*)(smem + lrow * SRS + lc * (kStageB16 ? 2 : 4));
       if constexpr (kResF32) {
         f32x4 v = *(const f32x4*)src;
         f32x4* dst = (f32x4*)((float*)p.out + (int64_t)row * p.ldo + col);
         if constexpr (EPI == E_RESID) v += *dst;
         *dst = v;
-      } else if constexpr (kResB16) {
-        const f32x4 v0 = *(const f32x4*)src, v1 = *(const f32x4*)(src + 4);
-        u32x4* dst = (u32x4*)((__bf16*)p.out + (int64_t)row * p.ldo + col);
-        const u32x2 lo = pack_bf16x4(v0[0], v0[1], v0[2], v0[3]);
-        const u32x2 hi = pack_bf16x4(v1[0], v1[1], v1[2], v1[3]);
-        *dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
+      } else if constexpr (kResB16) {  // E_BIAS_B (E_RESID_B takes the loop above): staged as bf16
+        *(u32x4*)((__bf16*)p.out + (int64_t)row * p.ldo + col) = *(const u32x4*)src;
       } else {
-        float qs = 1.f;
+        [[maybe_unused]] float qs = 1.f;
         S* dst;
         if constexpr (EPI == E_QKV) {
           const int which = col / p.d, rem = col % p.d;
@@ -356,14 +359,11 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
         if constexpr (sizeof(S) == 4) {
           const f32x4 v = *(const f32x4*)src;
           *(f32x4*)dst = v * qs;
-        } else if constexpr (sizeof(S) == 2) {
-          const f32x4 v0 = *(const f32x4*)src, v1 = *(const f32x4*)(src + 4);
-          const u32x2 lo = pack_bf16x4(v0[0] * qs, v0[1] * qs, v0[2] * qs, v0[3] * qs);
-          const u32x2 hi = pack_bf16x4(v1[0] * qs, v1[1] * qs, v1[2] * qs, v1[3] * qs);
-          *(u32x4*)dst = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        } else if constexpr (sizeof(S) == 2) {  // staged as bf16 (Q already scaled)
+          const u32x4 w = *(const u32x4*)src;
+          *(u32x4*)dst = w;
           if constexpr (EPI == E_QKV) {
             if (p.knorm && col >= p.d && col < 2 * p.d) {
-              const u32x4 w = {lo[0], lo[1], hi[0], hi[1]};
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
                 const float a = __uint_as_float(w[e] << 16), b = __uint_as_float(w[e] & 0xffff0000u);
