@@ -34,8 +34,8 @@ EVENTS_PER_BATCH = 64
 # (FETCH_SIZE, WRITE_SIZE) of paper_2601_17554_amd/profile_run.py scaled by a 256 MiB copy
 # (profiles/attention_bf16_varlen64_hbm_traffic.md). Valid only for the kernel source it was
 # measured on: reported as null once attention.hip, common.h or kernels.h change.
-ATTN_TRAFFIC = {"sha256": "d36b82dd81d48c4c19484757f9eeecdba2f8182f3883f47c52d7e6028819a2b3",
-                "bytes_per_launch": 455789976.5}
+ATTN_TRAFFIC = {"sha256": "3528ad0b50c001057b56d90b28aab254a017575145a18cb6a7d529cb214cc545",
+                "bytes_per_launch": 457956322.2}
 
 
 def attention_traffic():
@@ -98,6 +98,7 @@ def bench_varlen(args, cfg, w):
         outs = [model.outputs(pk.total_rows) for pk in batches]
         stream.synchronize()
         res["tiles"] = autotune.tune(model, dev[0][0], dev[0][1], ws=wss[0], use_cache=False)
+        print(f"bench: tiles {res['tiles']}", file=sys.stderr, flush=True)
         graphs = [B.Graph(model, x, b, o, ws, stream) for (x, b), o, ws in zip(dev, outs, wss)]
         for i in range(args.warmup):
             graphs[i % len(graphs)].launch()
@@ -226,7 +227,9 @@ def main():
     cfg = synth.FULL
     w = synth.make_weights(cfg, 1)
     vr = bench_varlen(args, cfg, w)
+    print(f"bench: varlen {vr['events'] / vr['wall_s']:.1f} events/s", file=sys.stderr, flush=True)
     pl = bench_plain_fp32(args, cfg, w)
+    print("bench: fp32 plain done", file=sys.stderr, flush=True)
 
     ms_per_step = vr["wall_s"] * 1e3 / args.steps
     value = vr["events"] / vr["wall_s"]

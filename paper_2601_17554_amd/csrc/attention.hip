@@ -694,7 +694,6 @@ constexpr AttnTile kTiles[] = {
     {4, 64, 2, 2},
     {4, 128, 2, 2},
     {4, 64, 1, 2},
-    {4, 64, 2, 2},  // as 14, registers capped for 4 waves per SIMD
 };
 
 template <class T, int DH, int NW, int KT, int QB>
@@ -737,7 +736,6 @@ hipError_t launch_dh(int tile, const AttnArgs& p, hipStream_t s) {
     case 14: return launch_b<T, DH, 4, 64, 2, 3, false>(p, s);
     case 15: return launch_b<T, DH, 4, 128, 2, 3, false>(p, s);
     case 16: return launch_b<T, DH, 4, 64, 1, 4, false>(p, s);
-    case 17: return launch_b<T, DH, 4, 64, 2, 4, false>(p, s);
     default: return hipErrorInvalidValue;
   }
 }
