@@ -2,9 +2,10 @@
 
 A step is one mlpf_reconstruct_events call (embedding, all encoder blocks, heads) over one batch of
 64 synthetic events packed varlen (element counts log-normal, median 3000, 200..8192) in BF16,
-inputs already resident in HBM. Beside it, the plain FP32 path runs one full-size event per launch
-(the same log-normal counts, 500..8192, padded to a multiple of 64), and the FP64 oracle is timed on
-the host's cores on a bounded sample of the same events.
+inputs already resident in HBM. Beside it: the plain path runs one full-size event per launch in FP32
+and in BF16 (the same log-normal counts, 500..8192, padded to a multiple of 64); the small model runs
+one 256-element event per launch in FP32 (latency over many reps, kernels only and with the PCIe
+copies); and the FP64 oracle is timed on the host's cores on a bounded sample of the varlen events.
 
 Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -123,14 +124,15 @@ def bench_varlen(args, cfg, w):
     return res
 
 
-def bench_plain_fp32(args, cfg, w):
-    """One full-size event per launch in FP32: eager (profiled) and graph-replayed latency."""
+def bench_plain(args, cfg, w, precision):
+    """One full-size event per launch (the same events for FP32 and BF16): eager (profiled) and
+    graph-replayed latency."""
     import torch
     from paper_2601_17554_amd import autotune
     from paper_2601_17554_amd import binding as B
 
-    model = B.Model(cfg, w, "fp32")
-    evs = synth.event_set(200, args.fp32_events, lo=500)
+    model = B.Model(cfg, w, precision)
+    evs = synth.event_set(200, args.plain_events, lo=500)
     pks = [synth.pack([e], pad_to=64) for e in evs]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -153,8 +155,72 @@ def bench_plain_fp32(args, cfg, w):
         del graphs
     n = np.array([e.n for e in evs])
     attn_flops = sum(attention_flops(np.array([k]), cfg) * cfg.n_layers for k in n)
-    return {"wall_s": wall, "lat_ms": lat, "graph_wall_s": gwall, "graph_lat_ms": glat, "n": n,
-            "prof": prof, "attn_flops": attn_flops, "tiles": tiles}
+    pl_attn_ms, pl_attn_n = prof["attention"]
+    achieved = (attn_flops / max(pl_attn_n, 1)) / (pl_attn_ms / max(pl_attn_n, 1) * 1e-3) / 1e12
+    return {
+        "value": round(len(n) / gwall, 2), "unit": "events/s",
+        "p50_ms_per_event": round(float(np.percentile(glat, 50)), 3),
+        "p99_ms_per_event": round(float(np.percentile(glat, 99)), 3),
+        "eager_value": round(len(n) / wall, 2),
+        "eager_p50_ms_per_event": round(float(np.percentile(lat, 50)), 3),
+        "eager_p99_ms_per_event": round(float(np.percentile(lat, 99)), 3),
+        "events": int(len(n)), "median_elements": int(np.median(n)),
+        "attention_tflops": round(achieved, 1),
+        f"attention_frac_{precision}_peak": round(achieved / PEAK_TFLOPS[precision], 4),
+        "tiles": tiles,
+    }
+
+
+def bench_small(args):
+    """The small model (d64 h4 ffn256 L3, weights seed 0) on one event of exactly 256 elements
+    (seed 100) in FP32, one event per launch. Latency per rep: kernels only (eager launches, then
+    the captured graph, input resident), and end to end (pinned H2D of the features, the graph,
+    D2H of the outputs, host wait)."""
+    import torch
+    from paper_2601_17554_amd import binding as B
+
+    cfg = synth.SMALL
+    model = B.Model(cfg, synth.make_weights(cfg, 0), "fp32")
+    pk = synth.pack([synth.make_event(100, 256)])
+    reps, warm = args.small_reps, 50
+    stream = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(stream):
+        x_host = torch.from_numpy(pk.x).pin_memory()
+        x = x_host.cuda()
+        batch = B.Batch.from_host(pk.row_start, pk.n_valid)
+        ws = model.workspace(pk.total_rows, 1)
+        out = model.outputs(pk.total_rows)
+        host_out = {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True) for k, v in out.items()}
+        stream.synchronize()
+        for _ in range(warm):
+            model.reconstruct(x, batch, ws=ws, out=out, stream=stream)
+        _, res["eager"] = _timed_steps(stream, reps, lambda i: model.reconstruct(
+            x, batch, ws=ws, out=out, stream=stream))
+        graph = B.Graph(model, x, batch, out, ws, stream)
+        for _ in range(warm):
+            graph.launch()
+        _, res["graph"] = _timed_steps(stream, reps, lambda i: graph.launch())
+        e2e = np.empty(reps)
+        for i in range(warm + reps):
+            t0 = time.perf_counter()
+            x.copy_(x_host, non_blocking=True)
+            graph.launch()
+            for k, v in out.items():
+                host_out[k].copy_(v, non_blocking=True)
+            stream.synchronize()
+            if i >= warm:
+                e2e[i - warm] = (time.perf_counter() - t0) * 1e3
+        res["e2e"] = e2e
+        del graph
+
+    def summary(ms):
+        return {"p50_ms": round(float(np.percentile(ms, 50)), 4),
+                "p99_ms": round(float(np.percentile(ms, 99)), 4),
+                "events_per_s": round(1e3 / float(ms.mean()), 1)}
+    return {"model": "d64 h4 ffn256 L3", "elements": 256, "reps": reps, "warmup": warm,
+            "eager_kernels": summary(res["eager"]), "graph_kernels": summary(res["graph"]),
+            "graph_with_h2d_d2h": summary(res["e2e"])}
 
 
 def bench_serving(args, cfg, w):
@@ -210,7 +276,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batches", type=int, default=4)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
-    ap.add_argument("--fp32-events", type=int, default=40)
+    ap.add_argument("--plain-events", type=int, default=40)
+    ap.add_argument("--small-reps", type=int, default=2000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rates", type=int, nargs="*", default=[200, 500, 1000, 2000])
@@ -226,10 +293,16 @@ def main():
 
     cfg = synth.FULL
     w = synth.make_weights(cfg, 1)
+    # The one-event legs first: the varlen leg's eager pass is then the last run of the BF16
+    # attention kernel before the serving leg (a kernel trace reads its dispatches there).
+    sm = bench_small(args)
+    print("bench: small fp32 done", file=sys.stderr, flush=True)
+    pl = bench_plain(args, cfg, w, "fp32")
+    print("bench: fp32 plain done", file=sys.stderr, flush=True)
+    pb = bench_plain(args, cfg, w, "bf16")
+    print("bench: bf16 plain done", file=sys.stderr, flush=True)
     vr = bench_varlen(args, cfg, w)
     print(f"bench: varlen {vr['events'] / vr['wall_s']:.1f} events/s", file=sys.stderr, flush=True)
-    pl = bench_plain_fp32(args, cfg, w)
-    print("bench: fp32 plain done", file=sys.stderr, flush=True)
 
     ms_per_step = vr["wall_s"] * 1e3 / args.steps
     value = vr["events"] / vr["wall_s"]
@@ -239,8 +312,7 @@ def main():
     achieved = attn_flops_per_launch / (attn_avg_ms * 1e-3) / 1e12
     exp_rate = attn_flops_per_launch * cfg.n_heads / (4.0 * cfg.d_model) / (attn_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    pl_attn_ms, pl_attn_n = pl["prof"]["attention"]
-    pl_achieved = (pl["attn_flops"] / max(pl_attn_n, 1)) / (pl_attn_ms / max(pl_attn_n, 1) * 1e-3) / 1e12
+    traffic = attention_traffic() if args.precision == "bf16" else None
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "events/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -257,22 +329,15 @@ def main():
         "p99_ms_per_event_amortised": round(float(np.percentile(per_event, 99)), 4),
         "eager_ms_per_step": round(vr["eager_ms_per_step"], 3),
         "forward_tflops": round(vr["flops"] / vr["wall_s"] / 1e12, 1),
-        "fp32_plain": {
-            "value": round(len(pl["n"]) / pl["graph_wall_s"], 2), "unit": "events/s",
-            "p50_ms_per_event": round(float(np.percentile(pl["graph_lat_ms"], 50)), 3),
-            "p99_ms_per_event": round(float(np.percentile(pl["graph_lat_ms"], 99)), 3),
-            "eager_value": round(len(pl["n"]) / pl["wall_s"], 2),
-            "eager_p50_ms_per_event": round(float(np.percentile(pl["lat_ms"], 50)), 3),
-            "eager_p99_ms_per_event": round(float(np.percentile(pl["lat_ms"], 99)), 3),
-            "events": int(len(pl["n"])), "median_elements": int(np.median(pl["n"])),
-            "attention_tflops": round(pl_achieved, 1),
-            "attention_frac_fp32_peak": round(pl_achieved / PEAK_TFLOPS["fp32"], 4),
-            "tiles": pl["tiles"],
-        },
+        "fp32_plain": pl,
+        "bf16_plain": pb,
+        "small_fp32_one_event": sm,
         "roofline": {"bound": "mfma", "kernel": "attention", "achieved": round(achieved, 1),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": attention_traffic() if args.precision == "bf16" else None,
-                     "traffic_unit": "bytes per launch (HBM)", "avg_launch_ms": round(attn_avg_ms, 4),
+                     "traffic": traffic, "traffic_unit": "bytes per launch (HBM)",
+                     "traffic_gb_per_s": (round(traffic / (attn_avg_ms * 1e-3) / 1e9, 1)
+                                          if traffic is not None else None),
+                     "avg_launch_ms": round(attn_avg_ms, 4),
                      # One exp2 per score: h * sum N^2 per launch, against the transcendental rate.
                      "exp_ceiling": {"achieved": round(exp_rate, 2), "peak": round(PEAK_EXP_T_PER_S, 2),
                                      "unit": "Texp/s", "frac": round(exp_rate / PEAK_EXP_T_PER_S, 4)}},
