@@ -534,7 +534,7 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
       a.ln_eps = c.ln_eps;
       if (y_next_out) *y_next_out = true;
     }
-    HIP_TRY(launch_ffn_fused(a, m->tune[MLPF_OP_FFN] > 0 ? m->tune[MLPF_OP_FFN] : 1, cx.s),
+    HIP_TRY(launch_ffn_fused(a, m->tune[MLPF_OP_FFN] > 0 ? m->tune[MLPF_OP_FFN] : 3, cx.s),
             "fused FFN launch");
     return MLPF_OK;
   }
@@ -938,7 +938,7 @@ mlpf_status_t mlpf_graph_destroy(mlpf_graph_t graph) {
 
 int32_t mlpf_tune_count(int32_t op) {
   if (op < 0 || op >= MLPF_OP_COUNT) return 0;
-  if (op == MLPF_OP_FFN) return 3;
+  if (op == MLPF_OP_FFN) return 4;
   if (op == MLPF_OP_HEADS) return 2;
   return op == MLPF_OP_ATTENTION ? attn_num_tiles() : gemm_num_tiles();
 }
@@ -975,8 +975,8 @@ mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape) {
     const int32_t v[6] = {tile, tile ? t.bm : 0, tile ? t.bn : 0, 0, 0, 0};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else if (op == MLPF_OP_FFN) {
-    const int32_t v[6] = {tile > 0, tile == 1 ? 128 : tile == 2 ? 64 : 0, tile == 1 ? 8 : tile == 2 ? 4 : 0,
-                          tile == 1, 0, 0};
+    const int rows = tile == 2 ? 64 : tile > 0 ? 128 : 0, waves = tile == 2 ? 4 : tile > 0 ? 8 : 0;
+    const int32_t v[6] = {tile > 0, rows, waves, tile == 1 || tile == 3, tile == 3, 0};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else {
     const GemmTile t = gemm_tile(tile);

@@ -318,6 +318,246 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
   }
 }
 
+// Persistent form of the 128-row, 8-wave shape: one workgroup per CU loops over row tiles, so that
+// what the one-tile-per-workgroup form pays at the start and end of every tile overlaps work:
+// the next tile's first weight chunk (with its b1 values) travels during this tile's last chunk,
+// into the buffer that chunk does not use; this tile's residual rows are loaded right after the
+// last chunk's products; the stores drain while the next tile computes; LN2's gamma and beta are
+// loaded once. The epilogue stages half a tile at a time in the weight buffer the last chunk used.
+// Chunk buffers alternate across tiles (par = buffer of a tile's first chunk), so any chunk count
+// works. Arithmetic and summation order are those of ffn_fused_kernel (same bits).
+template <int D>
+__global__ __launch_bounds__(512) void ffn_persistent_kernel(const FfnArgs p) {
+  constexpr int BM = 128, NW = 8, NT = NW * 64, HALF = BM / 2;
+  constexpr int W1RS = 2 * D + 16, W1CH = kFfnHC * W1RS;
+  constexpr int W2RS = 2 * kFfnHC + 16, W2CH = D * W2RS;
+  constexpr int B1_OFF = W1CH + W2CH;
+  constexpr int BUF = B1_OFF + kFfnHC * 4;  // one chunk: W1 image, W2^T image, b1 values
+  constexpr int URS = 2 * kFfnHC + 16;
+  constexpr int U_OFF = 2 * BUF;
+  constexpr int LN_OFF = U_OFF + BM * URS;
+  constexpr int LDS = LN_OFF + 2 * D * 4;
+  constexpr int SRS = 4 * D + 16;
+  static_assert(HALF * SRS <= BUF, "half-tile staging does not fit a chunk buffer");
+  constexpr int KG1 = D / 16, KG2 = kFfnHC / 16;
+  constexpr int WN2 = D / 32 < 4 ? D / 32 : 4;
+  constexpr int WM2 = NW / WN2;
+  constexpr int FM2 = (BM / 32) / WM2, FN2 = (D / 32) / WN2;
+  static_assert(FM2 >= 1 && FN2 >= 1 && WM2 * FM2 * 32 == BM && FM2 * 32 <= HALF, "bad FFN shape");
+  constexpr int CPR = D / 8;                  // epilogue threads per row (8 values each)
+  constexpr int RH = HALF * CPR / NT;         // epilogue rounds per half tile
+  static_assert(HALF * CPR % NT == 0 && NT % CPR == 0, "epilogue rounds");
+
+  __shared__ __attribute__((aligned(16))) char smem[LDS];
+  char* const ubuf = smem + U_OFF;
+  const float* lg = (const float*)(smem + LN_OFF);
+
+  int M = p.M;
+  if (p.m_dev) M = min(M, max(*p.m_dev, 0));
+  const int ntiles = (M + BM - 1) / BM;
+  int tile = blockIdx.x;
+  if (tile >= ntiles) return;  // uniform over the workgroup
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, h = lane >> 5;
+  const int nch = p.d_ff / kFfnHC;
+  const char* w1p = (const char*)p.w1p;
+  const char* w2p = (const char*)p.w2p;
+  const int hb = wave / (BM / 32), tb = wave % (BM / 32);  // phase-1 role
+  const int wm2 = wave / WN2, wn2 = wave % WN2;            // phase-2 role
+  const int whalf = 32 * wm2 * FM2 / HALF;                 // the half tile holding this wave's rows
+
+  auto copy_chunk = [&](int c, int b) {
+    copy_to_lds<NT>(w1p + (size_t)c * W1CH, smem + b * BUF, W1CH, wave, lane);
+    copy_to_lds<NT>(w2p + (size_t)c * W2CH, smem + b * BUF + W1CH, W2CH, wave, lane);
+    copy_to_lds<NT>((const char*)(p.b1 + c * kFfnHC), smem + b * BUF + B1_OFF, kFfnHC * 4, wave, lane);
+  };
+  // Rows beyond M read row M-1 instead (no branches around the loads); rows are independent
+  // through both products and the LayerNorm, and those rows are never stored.
+  u32x4 yf[KG1];
+  auto load_y = [&](int m0) {
+    const int row = min(m0 + 32 * tb + i, M - 1);
+    const __bf16* yr = (const __bf16*)p.y + (int64_t)row * D;
+#pragma unroll
+    for (int g = 0; g < KG1; ++g) yf[g] = *(const u32x4*)(yr + 16 * g + 8 * h);
+  };
+
+  if (p.ln_in_g) {  // LN2 gamma and beta stay in LDS for every tile
+    copy_to_lds<NT>((const char*)p.ln_in_g, smem + LN_OFF, D * 4, wave, lane);
+    copy_to_lds<NT>((const char*)p.ln_in_b, smem + LN_OFF + D * 4, D * 4, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  copy_chunk(0, 0);
+  int par = 0;
+
+  for (;;) {
+    const int m0 = tile * BM;
+    const int next = tile + (int)gridDim.x;
+    const bool has_next = next < ntiles;
+    load_y(m0);
+    if (p.ln_in_g) ln_fragments<KG1>(yf, h, lg, lg + D, p.ln_in_eps);
+    f32x16 acc[FM2][FN2];
+#pragma unroll
+    for (int a = 0; a < FM2; ++a)
+#pragma unroll
+      for (int b = 0; b < FN2; ++b) acc[a][b] = f32x16{};
+    // The tile's first chunk has landed (and the previous epilogue is done with the staging
+    // buffer, which the copies below reuse).
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    for (int c = 0; c < nch; ++c) {
+      const int buf = par ^ (c & 1);
+      const bool more = c + 1 < nch;
+      if (more || has_next) copy_chunk(more ? c + 1 : 0, buf ^ 1);  // next chunk, or next tile's first
+      // Phase 1: this wave's 32x32 block of U^T, summed over k = 0 .. D-1 in order.
+      {
+        const char* w1 = smem + buf * BUF + (32 * hb + i) * W1RS + 16 * h;
+        f32x16 u = f32x16{};
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          u32x4 wf[KG1 / 2];
+#pragma unroll
+          for (int g = 0; g < KG1 / 2; ++g) wf[g] = *(const u32x4*)(w1 + 32 * (half * KG1 / 2 + g));
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int g = 0; g < KG1 / 2; ++g) mma_kg<BF16>(wf[g], yf[half * KG1 / 2 + g], u);
+        }
+        // Lane holds row 32 tb + i and hidden units 32 hb + 8 q + 4 h + (0..3) in registers 4q..4q+3.
+        const float* b1 = (const float*)(smem + buf * BUF + B1_OFF) + 32 * hb + 4 * h;
+        f32x4 bq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bq[q] = *(const f32x4*)(b1 + 8 * q);
+        char* urow = ubuf + (32 * tb + i) * URS + (32 * hb + 4 * h) * 2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          *(u32x2*)(urow + 16 * q) =
+              pack_bf16x4(gelu_erf(u[4 * q] + bq[q][0]), gelu_erf(u[4 * q + 1] + bq[q][1]),
+                          gelu_erf(u[4 * q + 2] + bq[q][2]), gelu_erf(u[4 * q + 3] + bq[q][3]));
+        }
+      }
+      __syncthreads();
+      // Phase 2: O += U W2_c over the chunk's k-groups in order.
+      {
+        const char* w2 = smem + buf * BUF + W1CH;
+#pragma unroll
+        for (int g = 0; g < KG2; ++g) {
+          u32x4 af[FM2], bf[FN2];
+#pragma unroll
+          for (int a = 0; a < FM2; ++a)
+            af[a] = *(const u32x4*)(ubuf + (32 * (wm2 * FM2 + a) + i) * URS + 32 * g + 16 * h);
+#pragma unroll
+          for (int b = 0; b < FN2; ++b)
+            bf[b] = *(const u32x4*)(w2 + (32 * (wn2 * FN2 + b) + i) * W2RS + 32 * g + 16 * h);
+#pragma unroll
+          for (int a = 0; a < FM2; ++a)
+#pragma unroll
+            for (int b = 0; b < FN2; ++b) mma_kg<BF16>(af[a], bf[b], acc[a][b]);
+        }
+      }
+      if (more) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies for chunk c+1 have landed
+        __syncthreads();
+      }
+    }
+    const int bl = par ^ ((nch - 1) & 1);  // buffer of the last chunk: the staging area now
+
+    // Residual rows of this tile. The epilogue's thread index goes through an empty asm statement so that its addresses are formed
+    // here rather than hoisted out of the tile loop (where they would stay live across the chunks).
+    int etid = tid;
+    __asm__ volatile("" : "+v"(etid));
+    u32x4 hv[2 * RH];
+#pragma unroll
+    for (int q = 0; q < 2 * RH; ++q) {
+      const int t = etid + q * NT, row = min(m0 + t / CPR, M - 1), col = (t % CPR) * 8;
+      hv[q] = *(const u32x4*)((const __bf16*)p.h + (int64_t)row * D + col);
+    }
+    // The next block's LN1 gamma and beta of the 8 columns this thread updates in every round.
+    f32x4 lng[2], lnb[2];
+    if (p.y_next) {
+      const int col = (etid % CPR) * 8;
+      lng[0] = *(const f32x4*)(p.ln_g + col);
+      lng[1] = *(const f32x4*)(p.ln_g + col + 4);
+      lnb[0] = *(const f32x4*)(p.ln_b + col);
+      lnb[1] = *(const f32x4*)(p.ln_b + col + 4);
+    }
+    __syncthreads();  // every wave is done reading the last chunk's buffer and U
+
+    char* const stage = smem + bl * BUF;
+    // This wave's rows within its half tile: row 32 a + 8 (r/4) + (r%4) from srow (constant
+    // offsets from one base address).
+    int soff = (32 * wm2 * FM2 - HALF * whalf + 4 * h) * SRS + (32 * wn2 * FN2 + i) * 4;
+    __asm__ volatile("" : "+v"(soff));
+    float bias[FN2];
+#pragma unroll
+    for (int b = 0; b < FN2; ++b) bias[b] = p.b2[32 * (wn2 * FN2 + b) + i];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (whalf == half) {
+#pragma unroll
+        for (int a = 0; a < FM2; ++a)
+#pragma unroll
+          for (int b = 0; b < FN2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              *(float*)(stage + soff + (32 * a + 8 * (r >> 2) + (r & 3)) * SRS + 128 * b) =
+                  acc[a][b][r] + bias[b];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < RH; ++q) {
+        const int t = etid + q * NT, row = t / CPR, col = (t % CPR) * 8;
+        const int grow = m0 + HALF * half + row;
+        const bool live = grow < M;
+        const u32x4 o = hv[half * RH + q];
+        const f32x4 v0 = *(const f32x4*)(stage + row * SRS + col * 4);
+        const f32x4 v1 = *(const f32x4*)(stage + row * SRS + col * 4 + 16);
+        const u32x2 lo = pack_bf16x4(v0[0] + __uint_as_float(o[0] << 16), v0[1] + __uint_as_float(o[0] & 0xffff0000u),
+                                     v0[2] + __uint_as_float(o[1] << 16), v0[3] + __uint_as_float(o[1] & 0xffff0000u));
+        const u32x2 hi = pack_bf16x4(v1[0] + __uint_as_float(o[2] << 16), v1[1] + __uint_as_float(o[2] & 0xffff0000u),
+                                     v1[2] + __uint_as_float(o[3] << 16), v1[3] + __uint_as_float(o[3] & 0xffff0000u));
+        const u32x4 hn = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        if (live) *(u32x4*)((__bf16*)p.h + (int64_t)grow * D + col) = hn;
+        if (p.y_next) {
+          float x[8];
+          unpack_bf16x8(hn, x);
+          const u32x4 yn = ln_row_chunk8<CPR>(x, lng[0], lng[1], lnb[0], lnb[1], p.ln_eps);
+          if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)grow * D + col) = yn;
+        }
+      }
+      if (half == 0) __syncthreads();  // the second half reuses the staging rows
+    }
+    if (!has_next) break;
+    tile = next;
+    par = bl ^ 1;
+  }
+}
+
+template <int D>
+hipError_t launch_persistent(const FfnArgs& p, hipStream_t s) {
+  const int64_t tiles = ((int64_t)p.M + 127) / 128;
+  if (tiles == 0) return hipSuccess;
+  // As many workgroups as fit on the device at once (one per CU at d_model 256, where the LDS
+  // image takes the CU's whole LDS).
+  static int slots[64] = {0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (slots[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ffn_persistent_kernel<D>, 512, 0);
+    if (e != hipSuccess) return e;
+    slots[dev] = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  }
+  const unsigned grid = (unsigned)(tiles < slots[dev] ? tiles : slots[dev]);
+  hipLaunchKernelGGL((ffn_persistent_kernel<D>), dim3(grid), dim3(512), 0, s, p);
+  return hipGetLastError();
+}
+
 template <int BM, int NW, bool DBUF>
 hipError_t launch_v(const FfnArgs& p, hipStream_t s) {
   const int64_t grid = ((int64_t)p.M + BM - 1) / BM;
@@ -361,6 +601,13 @@ hipError_t launch_ffn_fused(const FfnArgs& p, int variant, hipStream_t s) {
   if (!ffn_fused_supported(p.d_model, p.d_ff)) return hipErrorInvalidValue;
   if (variant == 1) return launch_v<128, 8, true>(p, s);
   if (variant == 2) return launch_v<64, 4, false>(p, s);
+  if (variant == 3) {
+    switch (p.d_model) {
+      case 64: return launch_persistent<64>(p, s);
+      case 128: return launch_persistent<128>(p, s);
+      default: return launch_persistent<256>(p, s);
+    }
+  }
   return hipErrorInvalidValue;
 }
 

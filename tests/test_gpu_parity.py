@@ -275,10 +275,11 @@ def test_fused_ffn_bitwise(B, cfg):
     evs = [synth.make_event(5000 + i, n) for i, n in enumerate([300, 1, 129, 64, 1000])]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=9)
     fused = run_gpu(m, pk)
-    m.tune_set("ffn", 2)
-    fused2 = run_gpu(m, pk)
-    for k in ("logits", "reg", "cls"):
-        np.testing.assert_array_equal(fused[k], fused2[k], err_msg=f"fused shapes {k}")
+    for variant in (2, 3):
+        m.tune_set("ffn", variant)
+        other = run_gpu(m, pk)
+        for k in ("logits", "reg", "cls"):
+            np.testing.assert_array_equal(fused[k], other[k], err_msg=f"fused shape {variant} {k}")
     m.tune_set("ffn", 0)
     for tile in (-1, 6, 9):
         for op in ("ffn1", "ffn2"):
@@ -290,6 +291,32 @@ def test_fused_ffn_bitwise(B, cfg):
                 np.testing.assert_array_equal(fused[k][r], two[k][r], err_msg=f"tile {tile} {k}")
     with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
         B.Model(cfg, w, "fp32").tune_set("ffn", 1)
+
+
+def test_persistent_ffn_many_tiles(B):
+    """The persistent fused FFN when every workgroup loops over several row tiles (256 workgroups,
+    ~600 tiles of 128 rows, a ragged last tile, garbage padding): bitwise equal to the
+    one-tile-per-workgroup kernel and to the two-product FFN, and consistent with the oracle on
+    sampled events."""
+    cfg = synth.FULL
+    w, m = _model(B, cfg, 16, "bf16", sharpen=2.0)
+    sizes = [8192, 8192, 8192, 8192, 8192, 8192, 8192, 8192, 4000, 3000, 2500, 2100, 1500, 777, 1, 65]
+    evs = [synth.make_event(5100 + i, n) for i, n in enumerate(sizes)]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=10)
+    assert pk.total_rows // 128 > 2 * 256
+    m.tune_set("ffn", 3)
+    pers = run_gpu(m, pk)
+    m.tune_set("ffn", 1)
+    one = run_gpu(m, pk)
+    m.tune_set("ffn", 0)
+    two = run_gpu(m, pk)
+    live = np.concatenate([np.arange(r.start, r.stop) for r in map(pk.event_rows, range(pk.n_events))])
+    for k in ("logits", "reg", "cls"):
+        np.testing.assert_array_equal(pers[k][live], one[k][live], err_msg=f"persistent vs one tile {k}")
+        np.testing.assert_array_equal(pers[k][live], two[k][live], err_msg=f"persistent vs two products {k}")
+    for e in (13, 14, 15):  # small events the oracle finishes quickly
+        rows = pk.event_rows(e)
+        check_event(pers, oracle(pk.x[rows], w, cfg), rows, TOL["bf16"], f"persistent FFN event {e}")
 
 
 @pytest.mark.parametrize("cfg", [synth.FULL, synth.PAPER], ids=["d256", "paper_parallel2"])
