@@ -597,6 +597,7 @@ void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, u
   }
 }
 
+// Variants 1 and 2 as declared; 3 = variant 1 as a persistent kernel (ffn_persistent_kernel).
 hipError_t launch_ffn_fused(const FfnArgs& p, int variant, hipStream_t s) {
   if (!ffn_fused_supported(p.d_model, p.d_ff)) return hipErrorInvalidValue;
   if (variant == 1) return launch_v<128, 8, true>(p, s);

@@ -94,8 +94,7 @@ size_t ffn_pack_bytes(int d_model, int d_ff, int which);
 // Packs W1^T [d_ff][d_model] and W2^T [d_model][d_ff] (bf16 bits) into the chunked images.
 void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, uint16_t* w1p,
               uint16_t* w2p);
-// variant 1: 128 rows x 8 waves, double-buffered weights; 2: 64 rows x 4 waves, single-buffered;
-// 3: variant 1 as a persistent kernel (workgroups loop over row tiles).
+// variant 1: 128 rows x 8 waves, double-buffered weights; 2: 64 rows x 4 waves, single-buffered.
 hipError_t launch_ffn_fused(const FfnArgs& args, int variant, hipStream_t stream);
 
 // Attention over a device work list (see worklist).
