@@ -204,10 +204,12 @@ typedef enum {
    * update, tiles of MLPF_OP_FFN1/FFN2 apply); tiles 1 to 3 = one fused kernel that keeps the
    * d_ff-wide intermediate on chip (1: 128 rows per workgroup, double-buffered weights; 2: 64
    * rows, single-buffered, two workgroups per CU; 3: as 1, with persistent workgroups that loop
-   * over the row tiles and overlap one tile's end with the next one's start, the default),
-   * for MLPF_BF16 models with d_model 64, 128 or 256, bitwise equal to tile 0 with any GEMM tiles.
-   * Setting 1 to 3 on another model returns MLPF_ERR_UNSUPPORTED. FP8 calibration always runs the
-   * two products. */
+   * over the row tiles and overlap one tile's end with the next one's start, the default when d_ff
+   * is not a multiple of 128; 4: as 3, software-pipelined: the GELU of one 64-unit chunk runs
+   * beside the first product of the next, d_ff a multiple of 128 only, the default there), for
+   * MLPF_BF16 models with d_model 64, 128 or 256, bitwise equal
+   * to tile 0 with any GEMM tiles. Setting 1 to 4 on another model returns MLPF_ERR_UNSUPPORTED.
+   * FP8 calibration always runs the two products. */
   MLPF_OP_FFN = 8,
   /* How the output heads run: tile 0 = the first-layer product (tiles of MLPF_OP_HEADS1 apply)
    * writing the five GELU hidden layers, then a kernel for the second layer, argmax and decode;
@@ -227,7 +229,7 @@ int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule *
  * kind (0: online softmax with running maxima, 1: BF16 score-bound offset, 2: the same without the
  * look-ahead QK^T product; FP32 runs kind 0),
  * 0, 0}; MLPF_OP_FFN {fused (1) or two products (0), rows per workgroup, waves, double buffered,
- * persistent, 0}; MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
+ * persistent, pipelined}; MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
 mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);
 
 /* FP8 activation calibration for MLPF_BF16_FP8FFN. Runs the embedding and encoder of `model` (an

@@ -309,7 +309,7 @@ class Model:
         v = (ctypes.c_int32 * 6)()
         _check(load().mlpf_tune_shape(OPS.index(op), tile, v))
         keys = (("waves", "kt", "qb", "kind") if op == "attention" else
-                ("fused", "rows", "waves", "double_buffered", "persistent") if op == "ffn" else
+                ("fused", "rows", "waves", "double_buffered", "persistent", "pipelined") if op == "ffn" else
                 ("fused", "bm", "bn") if op == "heads"
                 else ("bm", "bn", "wm", "wn", "bkb", "persist"))
         return {k: int(v[i]) for i, k in enumerate(keys)}

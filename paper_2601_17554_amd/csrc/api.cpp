@@ -534,7 +534,8 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
       a.ln_eps = c.ln_eps;
       if (y_next_out) *y_next_out = true;
     }
-    HIP_TRY(launch_ffn_fused(a, m->tune[MLPF_OP_FFN] > 0 ? m->tune[MLPF_OP_FFN] : 3, cx.s),
+    const int ffn_default = (c.d_ff / 64) % 2 == 0 ? 4 : 3;  // pipelined when the chunk count is even
+    HIP_TRY(launch_ffn_fused(a, m->tune[MLPF_OP_FFN] > 0 ? m->tune[MLPF_OP_FFN] : ffn_default, cx.s),
             "fused FFN launch");
     return MLPF_OK;
   }
@@ -938,7 +939,7 @@ mlpf_status_t mlpf_graph_destroy(mlpf_graph_t graph) {
 
 int32_t mlpf_tune_count(int32_t op) {
   if (op < 0 || op >= MLPF_OP_COUNT) return 0;
-  if (op == MLPF_OP_FFN) return 4;
+  if (op == MLPF_OP_FFN) return 5;
   if (op == MLPF_OP_HEADS) return 2;
   return op == MLPF_OP_ATTENTION ? attn_num_tiles() : gemm_num_tiles();
 }
@@ -950,6 +951,8 @@ mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile) {
     return fail(MLPF_ERR_INVALID_ARG, "tile=%d out of range for op %d", tile, op);
   if (op == MLPF_OP_FFN && tile >= 1 && !model->plan.ffn_fused)
     return fail(MLPF_ERR_UNSUPPORTED, "the fused FFN needs an MLPF_BF16 model with d_model 64, 128 or 256");
+  if (op == MLPF_OP_FFN && tile == 4 && (model->cfg.d_ff / 64) % 2 != 0)
+    return fail(MLPF_ERR_UNSUPPORTED, "the pipelined fused FFN needs d_ff a multiple of 128");
   if (op == MLPF_OP_HEADS && tile == 1 && !model->plan.heads_fused)
     return fail(MLPF_ERR_UNSUPPORTED, "the fused heads need a bf16 model with d_model 256");
   model->tune[op] = tile;
@@ -976,7 +979,7 @@ mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape) {
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else if (op == MLPF_OP_FFN) {
     const int rows = tile == 2 ? 64 : tile > 0 ? 128 : 0, waves = tile == 2 ? 4 : tile > 0 ? 8 : 0;
-    const int32_t v[6] = {tile > 0, rows, waves, tile == 1 || tile == 3, tile == 3, 0};
+    const int32_t v[6] = {tile > 0, rows, waves, tile != 0 && tile != 2, tile >= 3, tile == 4};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else {
     const GemmTile t = gemm_tile(tile);

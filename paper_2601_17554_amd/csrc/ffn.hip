@@ -101,13 +101,18 @@ __device__ __forceinline__ void ln_fragments(u32x4* yf, int h, const float* gam,
   const float q0 = add_nc(t0[0], __shfl_xor(t0[0], 32, 64));
   const float q1 = add_nc(t1[0], __shfl_xor(t1[0], 32, 64));
   const float rs = ln_rstd(add_nc(q0, q1), D, eps);
+  // One base address per array (the empty asm keeps the compiler from forming one per fragment):
+  // the fragments' offsets 64 g are immediates.
+  int hoff = 8 * h;
+  __asm__ volatile("" : "+v"(hoff));
+  const float* gh = gam + hoff;
+  const float* bh = bet + hoff;
 #pragma unroll
   for (int g = 0; g < KG; ++g) {
     float x[8];
     unpack_bf16x8(yf[g], x);
-    const int c = 16 * g + 8 * h;
-    const f32x4 g0 = *(const f32x4*)(gam + c), g1 = *(const f32x4*)(gam + c + 4);
-    const f32x4 b0 = *(const f32x4*)(bet + c), b1 = *(const f32x4*)(bet + c + 4);
+    const f32x4 g0 = *(const f32x4*)(gh + 16 * g), g1 = *(const f32x4*)(gh + 16 * g + 4);
+    const f32x4 b0 = *(const f32x4*)(bh + 16 * g), b1 = *(const f32x4*)(bh + 16 * g + 4);
     const u32x2 lo = pack_bf16x4(ln_out(x[0], mu, rs, g0[0], b0[0]), ln_out(x[1], mu, rs, g0[1], b0[1]),
                                  ln_out(x[2], mu, rs, g0[2], b0[2]), ln_out(x[3], mu, rs, g0[3], b0[3]));
     const u32x2 hi = pack_bf16x4(ln_out(x[4], mu, rs, g1[0], b1[0]), ln_out(x[5], mu, rs, g1[1], b1[1]),
@@ -534,6 +539,261 @@ __global__ __launch_bounds__(512) void ffn_persistent_kernel(const FfnArgs p) {
   }
 }
 
+// Software-pipelined persistent form (chunk counts even): the GELU of chunk c runs while the
+// first product of chunk c+1 accumulates, in the same wave, so that the VALU and transcendental
+// work of one chunk overlaps the MFMAs of the next instead of following them. W1 therefore
+// travels two chunks ahead and W2 (with b1) one chunk ahead: in chunk c, W1 of c+2 goes to buffer
+// c%2 and W2, b1 of c+1 to buffer (c+1)%2. The epilogue stages in buffer 1 (the last chunk's);
+// the next tile's W1 and W2 of chunk 0 arrive in buffer 0 during the last two chunks, its W1 of
+// chunk 1 at the tile's start. Arithmetic and summation order are those of ffn_fused_kernel.
+template <int D>
+__global__ __launch_bounds__(512) void ffn_pipelined_kernel(const FfnArgs p) {
+  constexpr int BM = 128, NW = 8, NT = NW * 64, HALF = BM / 2;
+  constexpr int W1RS = 2 * D + 16, W1CH = kFfnHC * W1RS;
+  constexpr int W2RS = 2 * kFfnHC + 16, W2CH = D * W2RS;
+  constexpr int B1_OFF = W1CH + W2CH;
+  constexpr int BUF = B1_OFF + kFfnHC * 4;
+  constexpr int URS = 2 * kFfnHC + 16;
+  constexpr int U_OFF = 2 * BUF;
+  constexpr int LN_OFF = U_OFF + BM * URS;
+  constexpr int LDS = LN_OFF + 2 * D * 4;
+  constexpr int SRS = 4 * D + 16;
+  static_assert(HALF * SRS <= BUF, "half-tile staging does not fit a chunk buffer");
+  constexpr int KG1 = D / 16, KG2 = kFfnHC / 16;
+  constexpr int WN2 = D / 32 < 4 ? D / 32 : 4;
+  constexpr int WM2 = NW / WN2;
+  constexpr int FM2 = (BM / 32) / WM2, FN2 = (D / 32) / WN2;
+  static_assert(FM2 >= 1 && FN2 >= 1 && WM2 * FM2 * 32 == BM && FM2 * 32 <= HALF, "bad FFN shape");
+  static_assert(KG1 % 4 == 0, "first product in four parts");
+  constexpr int CPR = D / 8;
+  constexpr int RH = HALF * CPR / NT;
+  static_assert(HALF * CPR % NT == 0 && NT % CPR == 0, "epilogue rounds");
+
+  __shared__ __attribute__((aligned(16))) char smem[LDS];
+  char* const ubuf = smem + U_OFF;
+  const float* lg = (const float*)(smem + LN_OFF);
+
+  int M = p.M;
+  if (p.m_dev) M = min(M, max(*p.m_dev, 0));
+  const int ntiles = (M + BM - 1) / BM;
+  int tile = blockIdx.x;
+  const int nch = p.d_ff / kFfnHC;
+  if (tile >= ntiles || (nch & 1)) return;  // uniform over the workgroup
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, h = lane >> 5;
+  const char* w1p = (const char*)p.w1p;
+  const char* w2p = (const char*)p.w2p;
+  const int hb = wave / (BM / 32), tb = wave % (BM / 32);
+  const int wm2 = wave / WN2, wn2 = wave % WN2;
+  const int whalf = 32 * wm2 * FM2 / HALF;
+
+  // The copies are issued by waves 0-3 only: the waves of the second hidden block (4-7, the
+  // younger wave on each SIMD) finish the first product later, and the first four would otherwise
+  // wait for them at the barrier after it.
+  const bool copier = wave < NW / 2;
+  auto copy_w1 = [&](int c, int b) {
+    if (copier) copy_to_lds<NT / 2>(w1p + (size_t)c * W1CH, smem + b * BUF, W1CH, wave, lane);
+  };
+  auto copy_w2 = [&](int c, int b) {
+    if (copier) {
+      copy_to_lds<NT / 2>(w2p + (size_t)c * W2CH, smem + b * BUF + W1CH, W2CH, wave, lane);
+      copy_to_lds<NT / 2>((const char*)(p.b1 + c * kFfnHC), smem + b * BUF + B1_OFF, kFfnHC * 4, wave,
+                          lane);
+    }
+  };
+  u32x4 yf[KG1];
+  auto load_y = [&](int m0) {
+    const int row = min(m0 + 32 * tb + i, M - 1);
+    const __bf16* yr = (const __bf16*)p.y + (int64_t)row * D;
+#pragma unroll
+    for (int g = 0; g < KG1; ++g) yf[g] = *(const u32x4*)(yr + 16 * g + 8 * h);
+  };
+  // Values 4q..4q+3 of this wave's U^T block (row 32 tb + i, hidden units 32 hb + 8q + 4h + 0..3):
+  // + b1, GELU, bf16, to U.
+  char* const urow = ubuf + (32 * tb + i) * URS + (32 * hb + 4 * h) * 2;
+  auto gelu_part = [&](const f32x16& u, int q, const float* b1s) {
+    const f32x4 bq = *(const f32x4*)(b1s + 8 * q);
+    *(u32x2*)(urow + 16 * q) =
+        pack_bf16x4(gelu_erf(u[4 * q] + bq[0]), gelu_erf(u[4 * q + 1] + bq[1]),
+                    gelu_erf(u[4 * q + 2] + bq[2]), gelu_erf(u[4 * q + 3] + bq[3]));
+  };
+
+  if (p.ln_in_g) {
+    copy_to_lds<NT>((const char*)p.ln_in_g, smem + LN_OFF, D * 4, wave, lane);
+    copy_to_lds<NT>((const char*)p.ln_in_b, smem + LN_OFF + D * 4, D * 4, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  copy_w1(0, 0);
+  copy_w2(0, 0);
+
+  for (;;) {
+    const int m0 = tile * BM;
+    const int next = tile + (int)gridDim.x;
+    const bool has_next = next < ntiles;
+    copy_w1(1, 1);  // buffer 1 is free: the previous epilogue is done with it
+    load_y(m0);
+    if (p.ln_in_g) ln_fragments<KG1>(yf, h, lg, lg + D, p.ln_in_eps);
+    f32x16 acc[FM2][FN2];
+#pragma unroll
+    for (int a = 0; a < FM2; ++a)
+#pragma unroll
+      for (int b = 0; b < FN2; ++b) acc[a][b] = f32x16{};
+    __builtin_amdgcn_s_waitcnt(0);  // chunk 0 and W1 of chunk 1 have landed
+    __syncthreads();
+    // First product of chunk 0 on its own.
+    f32x16 u = f32x16{};
+    {
+      const char* w1 = smem + (32 * hb + i) * W1RS + 16 * h;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        u32x4 wf[KG1 / 2];
+#pragma unroll
+        for (int g = 0; g < KG1 / 2; ++g) wf[g] = *(const u32x4*)(w1 + 32 * (half * KG1 / 2 + g));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < KG1 / 2; ++g) mma_kg<BF16>(wf[g], yf[half * KG1 / 2 + g], u);
+      }
+    }
+
+    for (int c = 0; c < nch; ++c) {
+      const int b = c & 1;
+      if (c + 2 < nch) copy_w1(c + 2, b);
+      else if (c + 2 == nch && has_next) copy_w1(0, b);
+      if (c + 1 < nch) copy_w2(c + 1, b ^ 1);
+      else if (has_next) copy_w2(0, b ^ 1);
+      const float* b1s = (const float*)(smem + b * BUF + B1_OFF) + 32 * hb + 4 * h;
+      f32x16 un = f32x16{};
+      if (c + 1 < nch) {
+        // GELU of chunk c in four parts, each beside a quarter of chunk c+1's first product.
+        const char* w1 = smem + (b ^ 1) * BUF + (32 * hb + i) * W1RS + 16 * h;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          u32x4 wf[KG1 / 4];
+#pragma unroll
+          for (int g = 0; g < KG1 / 4; ++g) wf[g] = *(const u32x4*)(w1 + 32 * (q * KG1 / 4 + g));
+          gelu_part(u, q, b1s);
+#pragma unroll
+          for (int g = 0; g < KG1 / 4; ++g) mma_kg<BF16>(wf[g], yf[q * KG1 / 4 + g], un);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gelu_part(u, q, b1s);
+      }
+      __syncthreads();
+      {
+        const char* w2 = smem + b * BUF + W1CH;
+#pragma unroll
+        for (int g = 0; g < KG2; ++g) {
+          u32x4 af[FM2], bf[FN2];
+#pragma unroll
+          for (int a = 0; a < FM2; ++a)
+            af[a] = *(const u32x4*)(ubuf + (32 * (wm2 * FM2 + a) + i) * URS + 32 * g + 16 * h);
+#pragma unroll
+          for (int bb = 0; bb < FN2; ++bb)
+            bf[bb] = *(const u32x4*)(w2 + (32 * (wn2 * FN2 + bb) + i) * W2RS + 32 * g + 16 * h);
+#pragma unroll
+          for (int a = 0; a < FM2; ++a)
+#pragma unroll
+            for (int bb = 0; bb < FN2; ++bb) mma_kg<BF16>(af[a], bf[bb], acc[a][bb]);
+        }
+      }
+      if (c + 1 < nch) {
+        __builtin_amdgcn_s_waitcnt(0);  // W1 of c+2, W2 and b1 of c+1 have landed
+        __syncthreads();                // and U is free again
+        u = un;
+      }
+    }
+
+    int etid = tid;
+    __asm__ volatile("" : "+v"(etid));
+    u32x4 hv[2 * RH];
+#pragma unroll
+    for (int q = 0; q < 2 * RH; ++q) {
+      const int t = etid + q * NT, row = min(m0 + t / CPR, M - 1), col = (t % CPR) * 8;
+      hv[q] = *(const u32x4*)((const __bf16*)p.h + (int64_t)row * D + col);
+    }
+    f32x4 lng[2], lnb[2];
+    if (p.y_next) {
+      const int col = (etid % CPR) * 8;
+      lng[0] = *(const f32x4*)(p.ln_g + col);
+      lng[1] = *(const f32x4*)(p.ln_g + col + 4);
+      lnb[0] = *(const f32x4*)(p.ln_b + col);
+      lnb[1] = *(const f32x4*)(p.ln_b + col + 4);
+    }
+    __syncthreads();  // every wave is done reading buffer 1 and U
+
+    char* const stage = smem + BUF;
+    int soff = (32 * wm2 * FM2 - HALF * whalf + 4 * h) * SRS + (32 * wn2 * FN2 + i) * 4;
+    __asm__ volatile("" : "+v"(soff));
+    float bias[FN2];
+#pragma unroll
+    for (int bb = 0; bb < FN2; ++bb) bias[bb] = p.b2[32 * (wn2 * FN2 + bb) + i];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (whalf == half) {
+#pragma unroll
+        for (int a = 0; a < FM2; ++a)
+#pragma unroll
+          for (int bb = 0; bb < FN2; ++bb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              *(float*)(stage + soff + (32 * a + 8 * (r >> 2) + (r & 3)) * SRS + 128 * bb) =
+                  acc[a][bb][r] + bias[bb];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < RH; ++q) {
+        const int t = etid + q * NT, row = t / CPR, col = (t % CPR) * 8;
+        const int grow = m0 + HALF * half + row;
+        const bool live = grow < M;
+        const u32x4 o = hv[half * RH + q];
+        const f32x4 v0 = *(const f32x4*)(stage + row * SRS + col * 4);
+        const f32x4 v1 = *(const f32x4*)(stage + row * SRS + col * 4 + 16);
+        const u32x2 lo = pack_bf16x4(v0[0] + __uint_as_float(o[0] << 16), v0[1] + __uint_as_float(o[0] & 0xffff0000u),
+                                     v0[2] + __uint_as_float(o[1] << 16), v0[3] + __uint_as_float(o[1] & 0xffff0000u));
+        const u32x2 hi = pack_bf16x4(v1[0] + __uint_as_float(o[2] << 16), v1[1] + __uint_as_float(o[2] & 0xffff0000u),
+                                     v1[2] + __uint_as_float(o[3] << 16), v1[3] + __uint_as_float(o[3] & 0xffff0000u));
+        const u32x4 hn = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        if (live) *(u32x4*)((__bf16*)p.h + (int64_t)grow * D + col) = hn;
+        if (p.y_next) {
+          float x[8];
+          unpack_bf16x8(hn, x);
+          const u32x4 yn = ln_row_chunk8<CPR>(x, lng[0], lng[1], lnb[0], lnb[1], p.ln_eps);
+          if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)grow * D + col) = yn;
+        }
+      }
+      __syncthreads();  // the staging rows (buffer 1) are reused next
+    }
+    if (!has_next) break;
+    tile = next;
+  }
+}
+
+template <int D>
+hipError_t launch_pipelined(const FfnArgs& p, hipStream_t s) {
+  if ((p.d_ff / kFfnHC) & 1) return hipErrorInvalidValue;
+  const int64_t tiles = ((int64_t)p.M + 127) / 128;
+  if (tiles == 0) return hipSuccess;
+  static int slots[64] = {0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (slots[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ffn_pipelined_kernel<D>, 512, 0);
+    if (e != hipSuccess) return e;
+    slots[dev] = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  }
+  const unsigned grid = (unsigned)(tiles < slots[dev] ? tiles : slots[dev]);
+  hipLaunchKernelGGL((ffn_pipelined_kernel<D>), dim3(grid), dim3(512), 0, s, p);
+  return hipGetLastError();
+}
+
 template <int D>
 hipError_t launch_persistent(const FfnArgs& p, hipStream_t s) {
   const int64_t tiles = ((int64_t)p.M + 127) / 128;
@@ -597,7 +857,8 @@ void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, u
   }
 }
 
-// Variants 1 and 2 as declared; 3 = variant 1 as a persistent kernel (ffn_persistent_kernel).
+// Variants 1 and 2 as declared; 3 = variant 1 as a persistent kernel (ffn_persistent_kernel);
+// 4 = the software-pipelined persistent kernel (even chunk counts).
 hipError_t launch_ffn_fused(const FfnArgs& p, int variant, hipStream_t s) {
   if (!ffn_fused_supported(p.d_model, p.d_ff)) return hipErrorInvalidValue;
   if (variant == 1) return launch_v<128, 8, true>(p, s);
@@ -607,6 +868,13 @@ hipError_t launch_ffn_fused(const FfnArgs& p, int variant, hipStream_t s) {
       case 64: return launch_persistent<64>(p, s);
       case 128: return launch_persistent<128>(p, s);
       default: return launch_persistent<256>(p, s);
+    }
+  }
+  if (variant == 4) {
+    switch (p.d_model) {
+      case 64: return launch_pipelined<64>(p, s);
+      case 128: return launch_pipelined<128>(p, s);
+      default: return launch_pipelined<256>(p, s);
     }
   }
   return hipErrorInvalidValue;

@@ -275,7 +275,11 @@ def test_fused_ffn_bitwise(B, cfg):
     evs = [synth.make_event(5000 + i, n) for i, n in enumerate([300, 1, 129, 64, 1000])]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=9)
     fused = run_gpu(m, pk)
-    for variant in (2, 3):
+    for variant in (2, 3, 4):
+        if variant == 4 and (cfg.d_ff // 64) % 2:
+            with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
+                m.tune_set("ffn", variant)
+            continue
         m.tune_set("ffn", variant)
         other = run_gpu(m, pk)
         for k in ("logits", "reg", "cls"):
@@ -294,10 +298,10 @@ def test_fused_ffn_bitwise(B, cfg):
 
 
 def test_persistent_ffn_many_tiles(B):
-    """The persistent fused FFN when every workgroup loops over several row tiles (256 workgroups,
-    ~600 tiles of 128 rows, a ragged last tile, garbage padding): bitwise equal to the
-    one-tile-per-workgroup kernel and to the two-product FFN, and consistent with the oracle on
-    sampled events."""
+    """The persistent fused FFN kernels (plain and software-pipelined) when every workgroup loops
+    over several row tiles (256 workgroups, ~600 tiles of 128 rows, a ragged last tile, garbage
+    padding): bitwise equal to the one-tile-per-workgroup kernel and to the two-product FFN, and
+    consistent with the oracle on sampled events."""
     cfg = synth.FULL
     w, m = _model(B, cfg, 16, "bf16", sharpen=2.0)
     sizes = [8192, 8192, 8192, 8192, 8192, 8192, 8192, 8192, 4000, 3000, 2500, 2100, 1500, 777, 1, 65]
@@ -306,6 +310,8 @@ def test_persistent_ffn_many_tiles(B):
     assert pk.total_rows // 128 > 2 * 256
     m.tune_set("ffn", 3)
     pers = run_gpu(m, pk)
+    m.tune_set("ffn", 4)
+    pipe = run_gpu(m, pk)
     m.tune_set("ffn", 1)
     one = run_gpu(m, pk)
     m.tune_set("ffn", 0)
@@ -313,6 +319,7 @@ def test_persistent_ffn_many_tiles(B):
     live = np.concatenate([np.arange(r.start, r.stop) for r in map(pk.event_rows, range(pk.n_events))])
     for k in ("logits", "reg", "cls"):
         np.testing.assert_array_equal(pers[k][live], one[k][live], err_msg=f"persistent vs one tile {k}")
+        np.testing.assert_array_equal(pipe[k][live], one[k][live], err_msg=f"pipelined vs one tile {k}")
         np.testing.assert_array_equal(pers[k][live], two[k][live], err_msg=f"persistent vs two products {k}")
     for e in (13, 14, 15):  # small events the oracle finishes quickly
         rows = pk.event_rows(e)
