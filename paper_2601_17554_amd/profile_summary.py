@@ -3,10 +3,14 @@
     python paper_2601_17554_amd/profile_summary.py stats <prefix>_kernel_stats.csv [--top 20]
     python paper_2601_17554_amd/profile_summary.py trace <prefix>_kernel_trace.csv
         --kernel <name substring> --last N
+    python paper_2601_17554_amd/profile_summary.py step <prefix>_kernel_trace.csv
+        --marker <name substring of a step's last kernel>
     python paper_2601_17554_amd/profile_summary.py traffic --fetch <fetch counter csv>
         --write <write counter csv> --kernel <name substring> --last N [--copy-mib 256]
 
 `trace` prints the average duration of the last N dispatches of one kernel in a kernel trace.
+`step` prints the kernels of one step: the dispatches after the second-to-last dispatch of the
+marker kernel (the step's last kernel) up to and including the last one, grouped by name.
 `stats` prints the kernel table (calls, average and total duration, share) of a
 `rocprofv3 --kernel-trace --stats --output-format csv` run. `traffic` reads two
 `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of profile_run.py (KiB per dispatch), takes
@@ -51,6 +55,25 @@ def trace(path: str, kernel: str, last: int) -> None:
     dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in ds]
     print(f"Kernel `{ds[-1]['Kernel_Name']}`: last {last} dispatches, average "
           f"{sum(dur) / len(dur) / 1e6:.4f} ms (min {min(dur) / 1e6:.4f}, max {max(dur) / 1e6:.4f}).")
+
+
+def step(path: str, marker: str) -> None:
+    ds = sorted(_rows(path), key=lambda r: int(r["Dispatch_Id"]))
+    ends = [k for k, r in enumerate(ds) if marker in r["Kernel_Name"]]
+    if len(ends) < 2:
+        sys.exit(f"fewer than two dispatches of {marker!r}")
+    one = ds[ends[-2] + 1:ends[-1] + 1]
+    groups: Dict[str, List[int]] = {}
+    for r in one:
+        groups.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    total = sum(sum(v) for v in groups.values())
+    print("| Kernel | Launches | Total (us) | % |")
+    print("|---|---:|---:|---:|")
+    for name, v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| `{name.replace('|', '/')}` | {len(v)} | {sum(v) / 1e3:.1f} | {100 * sum(v) / total:.1f} |")
+    print(f"| all | | {total / 1e3:.1f} | 100 |")
+    span = int(one[-1]["End_Timestamp"]) - int(one[0]["Start_Timestamp"])
+    print(f"\nSum of kernel durations {total / 1e3:.1f} us; first start to last end {span / 1e3:.1f} us.")
 
 
 def _dispatches(path: str, counter: str) -> List[Dict[str, object]]:
@@ -105,6 +128,9 @@ def main() -> None:
     r.add_argument("csv")
     r.add_argument("--kernel", required=True)
     r.add_argument("--last", type=int, required=True)
+    st = sub.add_parser("step")
+    st.add_argument("csv")
+    st.add_argument("--marker", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -116,6 +142,8 @@ def main() -> None:
         stats(a.csv, a.top)
     elif a.cmd == "trace":
         trace(a.csv, a.kernel, a.last)
+    elif a.cmd == "step":
+        step(a.csv, a.marker)
     else:
         traffic(a.fetch, a.write, a.kernel, a.last, a.copy_mib)
 
