@@ -15,6 +15,10 @@ What it follows (arxiv 2601.17554):
     materialised form (the fallback the paper names for hardware without a fused kernel).
   * Eq. 2: the regression targets for p_T and E are log-ratios to the primary element; ``decode``
     inverts them.
+  * Sec. 5.3 (inference rule) and Sec. 8 (the reconstruction module turns the model outputs into a
+    list of particle candidates per event): ``candidates`` keeps, event by event and in element
+    order, the elements whose predicted class is a particle, with their class and decoded
+    four-momentum.
 
 Readings where the paper is silent (each is listed with its reason in the design notes):
   * serial topology by default (one stack of L blocks read by all heads); 'parallel2' is the
@@ -167,6 +171,33 @@ def decode(reg: np.ndarray, prim: np.ndarray) -> Dict[str, np.ndarray]:
     prim = np.asarray(prim, dtype=np.float64)
     return {"pt": prim[:, 0] * np.exp(reg[:, 0]), "eta": reg[:, 1],
             "phi": np.arctan2(reg[:, 2], reg[:, 3]), "e": prim[:, 1] * np.exp(reg[:, 4])}
+
+
+def candidates(cls, kin, row_start, n_valid=None):
+    """Particle candidates per event (Sec. 5.3 inference rule, Sec. 8 module output).
+
+    cls: [T] predicted class per row (0 = no particle); kin: [T][k] per-row kinematics (the decoded
+    p_T, eta, phi, E) or None; row_start: [n_events + 1]; n_valid: [n_events] or None (every row of
+    an event is an element). Event e's elements are rows row_start[e] .. row_start[e] + n_valid[e] - 1.
+    Returns (offsets [n_events + 1], rows [C], classes [C], kin [C][k] or None): event e's
+    candidates are entries offsets[e] .. offsets[e+1] - 1, in element order; each entry names its
+    row, its class and that row's kinematics.
+    """
+    cls = np.asarray(cls)
+    row_start = np.asarray(row_start, dtype=np.int64)
+    n_events = len(row_start) - 1
+    offsets = [0]
+    rows = []
+    for e in range(n_events):
+        n = row_start[e + 1] - row_start[e] if n_valid is None else n_valid[e]
+        for i in range(int(n)):
+            r = int(row_start[e]) + i
+            if cls[r] != 0:
+                rows.append(r)
+        offsets.append(len(rows))
+    rows = np.asarray(rows, dtype=np.int64)
+    out_kin = None if kin is None else np.asarray(kin)[rows]
+    return np.asarray(offsets, dtype=np.int64), rows, cls[rows], out_kin
 
 
 def encode(pt_target, e_target, prim) -> np.ndarray:

@@ -318,6 +318,50 @@ def test_decode_inverts_eq2():
     np.testing.assert_allclose(dec["phi"], phi, rtol=0, atol=1e-12)
 
 
+# ---------------------------------------------------------------- candidates (inference rule)
+
+
+def test_candidates_hand_example():
+    """Sec. 5.3 inference rule on a hand-worked batch: three events (rows 0-4 with 4 valid, rows
+    5-5 with 1 valid, rows 6-9 with 0 valid) and a padding row that claims a particle."""
+    cls = np.array([0, 3, 1, 0, 5,   2,   4, 4, 4, 4])
+    kin = np.arange(40, dtype=np.float64).reshape(10, 4)
+    offsets, rows, classes, k = O.candidates(cls, kin, [0, 5, 6, 10], [4, 1, 0])
+    # event 0: elements 0..3 -> rows 1 (class 3) and 2 (class 1); row 4 is padding
+    # event 1: row 5 (class 2); event 2: no elements
+    np.testing.assert_array_equal(offsets, [0, 2, 3, 3])
+    np.testing.assert_array_equal(rows, [1, 2, 5])
+    np.testing.assert_array_equal(classes, [3, 1, 2])
+    np.testing.assert_array_equal(k, kin[[1, 2, 5]])
+    offsets, rows, classes, _ = O.candidates(cls, None, [0, 5, 6, 10])
+    np.testing.assert_array_equal(offsets, [0, 3, 4, 8])
+    np.testing.assert_array_equal(rows, [1, 2, 4, 5, 6, 7, 8, 9])
+
+
+def test_candidates_mask_formulation():
+    """The same selection written as one mask over all rows (valid element and class != 0), on
+    random ragged batches with empty events."""
+    rng = np.random.default_rng(21)
+    for _ in range(20):
+        n_ev = int(rng.integers(0, 12))
+        lens = rng.integers(0, 40, n_ev)
+        nval = np.array([rng.integers(0, l + 1) for l in lens], dtype=np.int64)
+        rs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        cls = rng.integers(0, 6, int(rs[-1]))
+        kin = rng.standard_normal((int(rs[-1]), 4))
+        offsets, rows, classes, k = O.candidates(cls, kin, rs, nval)
+        valid = np.zeros(int(rs[-1]), dtype=bool)
+        for e in range(n_ev):
+            valid[rs[e]:rs[e] + nval[e]] = True
+        want = np.nonzero(valid & (cls != 0))[0]
+        np.testing.assert_array_equal(rows, want)
+        np.testing.assert_array_equal(classes, cls[want])
+        np.testing.assert_array_equal(k, kin[want])
+        ev_of = np.searchsorted(rs, want, side="right") - 1
+        np.testing.assert_array_equal(offsets, np.searchsorted(ev_of, np.arange(n_ev + 1), side="left"))
+        assert np.all(classes != 0) and offsets[-1] == len(rows)
+
+
 def test_parameter_count_matches_paper():
     """The paper's model has about 5.1 M parameters (Sec. 5.3); the full configuration read here
     (d 256, FFN 4d, 6 blocks, 5 two-layer heads) has 5,140,747."""
