@@ -100,6 +100,8 @@ def bench_varlen(args, cfg, w):
         stream.synchronize()
         res["tiles"] = autotune.tune(model, dev[0][0], dev[0][1], ws=wss[0], use_cache=False)
         print(f"bench: tiles {res['tiles']}", file=sys.stderr, flush=True)
+        # Before the timed passes: the eager pass stays the last run of the attention kernel.
+        res["candidates"] = bench_candidates(model, batches[0], dev[0], wss[0], stream)
         graphs = [B.Graph(model, x, b, o, ws, stream) for (x, b), o, ws in zip(dev, outs, wss)]
         for i in range(args.warmup):
             graphs[i % len(graphs)].launch()
@@ -122,6 +124,31 @@ def bench_varlen(args, cfg, w):
     res["mean_n"] = float(n_timed.mean())
     del graphs
     return res
+
+
+def bench_candidates(model, pk, dev, ws, stream, reps: int = 50):
+    """Candidate construction (mlpf_candidates: per-event counts, scan, ordered writes) on the
+    outputs of one 64-event batch with the Eq. 2 decode; HIP events on the launch stream."""
+    import torch
+    from paper_2601_17554_amd import binding as B
+    x, batch = dev
+    prim = torch.from_numpy(pk.prim).cuda()
+    out = model.outputs(pk.total_rows, decode=True)
+    model.reconstruct(x, batch, prim=prim, ws=ws, out=out, stream=stream)
+    cands = B.candidates(batch, out["cls"], out["decoded"], stream=stream)
+    _, ms = _timed_steps(stream, reps, lambda i: B.mlpf_candidates(
+        batch, out["cls"], out["decoded"], cands["offsets"], cands["rows"], cands["cls"],
+        cands["kin"], pk.total_rows, stream))
+    total = int(cands["offsets"][-1].item())
+    valid = int(pk.n_valid.sum())
+    # Algorithmic bytes: the classes of the valid rows read twice (count, write), 16 B of decoded
+    # kinematics read and 24 B written per candidate, the offsets written twice and read once.
+    nbytes = 8 * valid + 40 * total + 12 * (pk.n_events + 1)
+    avg = float(ms.mean())
+    return {"ms_per_batch": round(avg, 4), "p99_ms": round(float(np.percentile(ms, 99)), 4),
+            "candidates_per_batch": total, "elements_per_batch": valid,
+            "algorithmic_bytes": nbytes, "gb_per_s": round(nbytes / (avg * 1e-3) / 1e9, 1),
+            "launches": 3}
 
 
 def bench_plain(args, cfg, w, precision):
@@ -342,6 +369,7 @@ def main():
                      "exp_ceiling": {"achieved": round(exp_rate, 2), "peak": round(PEAK_EXP_T_PER_S, 2),
                                      "unit": "Texp/s", "frac": round(exp_rate / PEAK_EXP_T_PER_S, 4)}},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in vr["prof"].items()},
+        "candidates": vr["candidates"],
     }
     if args.serve_rates:
         line["serving"] = bench_serving(args, cfg, w)

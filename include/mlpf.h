@@ -150,6 +150,23 @@ mlpf_status_t mlpf_reconstruct_events(mlpf_model_t model, const float* x,
                                       int32_t* cls, const float* prim, float* decoded, void* ws,
                                       size_t ws_bytes, void* stream);
 
+/* Particle candidates per event (Sec. 5.3: at inference an element yields a particle when its
+ * predicted class is a particle, with that class and the four-momentum of its heads; Sec. 8: the
+ * reconstruction module turns the outputs into a list of candidates per event). From cls[T] (as
+ * written by mlpf_heads; 0 = no particle) and optionally decoded[T][4] (pT, eta, phi, E), keeps
+ * every valid element of every event with cls != 0, in element order within its event, events in
+ * order. Writes event_offsets[n_events + 1] (device int32): event e's candidates are entries
+ * event_offsets[e] .. event_offsets[e+1]-1, and event_offsets[n_events] is their total; for each
+ * entry k < cap: cand_row[k] (device int32, the row of the element), cand_cls[k] (its class), and,
+ * when cand_kin is non-NULL, cand_kin[k][4] = decoded[row] (cand_kin and decoded 16-byte aligned).
+ * Entries k >= cap are not written: a total above cap means the list was cut (the caller sizes cap,
+ * e.g. to total_rows, or reads the total and calls again). The batch description is clamped as
+ * in the forward calls. Allocates nothing; three kernel launches on `stream`; graph-capturable.
+ * MLPF_ERR_INVALID_ARG for NULL required pointers, negative sizes or misaligned kinematics. */
+mlpf_status_t mlpf_candidates(const mlpf_batch_t* batch, const int32_t* cls, const float* decoded,
+                              int32_t* event_offsets, int32_t* cand_row, int32_t* cand_cls,
+                              float* cand_kin, int32_t cap, void* stream);
+
 /* Captured forward passes (HIP graphs). mlpf_graph_create captures one mlpf_reconstruct_events
  * call with exactly these arguments on `stream` (which must not be the NULL stream; nothing is
  * executed during capture) and instantiates it. Every kernel reads the batch description

@@ -79,6 +79,7 @@ def load() -> ctypes.CDLL:
         "mlpf_tune_set": (st, [vp, i32, i32]),
         "mlpf_tune_get": (i32, [vp, i32]),
         "mlpf_tune_shape": (st, [i32, i32, ctypes.POINTER(ctypes.c_int32)]),
+        "mlpf_candidates": (st, [bp, vp, vp, vp, vp, vp, vp, i32, vp]),
         "mlpf_status_string": (ctypes.c_char_p, [st]),
         "mlpf_last_error": (ctypes.c_char_p, []),
     }
@@ -95,7 +96,7 @@ def exported_symbols() -> Sequence[str]:
             "mlpf_reconstruct_events", "mlpf_profiler_enable", "mlpf_profiler_read",
             "mlpf_attention_forward", "mlpf_calibrate_fp8", "mlpf_graph_create", "mlpf_graph_launch",
             "mlpf_graph_destroy", "mlpf_tune_count", "mlpf_tune_set", "mlpf_tune_get",
-            "mlpf_tune_shape", "mlpf_status_string", "mlpf_last_error")
+            "mlpf_tune_shape", "mlpf_candidates", "mlpf_status_string", "mlpf_last_error")
 
 
 PROF_CLASSES = ("embed", "qkv", "attention", "outproj", "ffn1", "ffn2", "heads", "worklist")
@@ -202,6 +203,42 @@ def mlpf_reconstruct_events(model: "Model", x, batch: Batch, logits, reg, cls, p
 def mlpf_attention_forward(model: "Model", q, k, v, o, batch: Batch, ws, stream=None) -> None:
     _check(load().mlpf_attention_forward(model.handle, _ptr(q), _ptr(k), _ptr(v), _ptr(o), batch.c,
                                          _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mlpf_candidates(batch: Batch, cls, decoded, event_offsets, cand_row, cand_cls, cand_kin,
+                    cap: int, stream=None) -> None:
+    _check(load().mlpf_candidates(batch.c, _ptr(cls), _ptr(decoded), _ptr(event_offsets),
+                                  _ptr(cand_row), _ptr(cand_cls), _ptr(cand_kin), int(cap),
+                                  _stream(stream)))
+
+
+def candidates(batch: Batch, cls: torch.Tensor, decoded: Optional[torch.Tensor] = None,
+               cap: Optional[int] = None, stream=None) -> Dict[str, torch.Tensor]:
+    """Device candidate lists (mlpf_candidates) with cap = total_rows by default (nothing can be
+    cut): {"offsets" [n_events + 1], "rows" [cap], "cls" [cap], "kin" [cap][4] if decoded}."""
+    dev = cls.device
+    cap = batch.total_rows if cap is None else cap
+    out = {"offsets": torch.empty(batch.n_events + 1, dtype=torch.int32, device=dev),
+           "rows": torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+           "cls": torch.empty(max(cap, 1), dtype=torch.int32, device=dev)}
+    if decoded is not None:
+        out["kin"] = torch.empty(max(cap, 1), 4, dtype=torch.float32, device=dev)
+    mlpf_candidates(batch, cls, decoded, out["offsets"], out["rows"], out["cls"], out.get("kin"),
+                    cap, stream)
+    return out
+
+
+def candidates_to_host(cands: Dict[str, torch.Tensor], stream=None) -> Dict[str, np.ndarray]:
+    """Variable-length download: the offsets first, then only the first total entries."""
+    s = stream if stream is not None else torch.cuda.current_stream()
+    s.synchronize()
+    offsets = cands["offsets"].cpu().numpy()
+    total = min(int(offsets[-1]), cands["rows"].numel())
+    out = {"offsets": offsets, "total": int(offsets[-1])}
+    for k in ("rows", "cls", "kin"):
+        if k in cands:
+            out[k] = cands[k][:total].cpu().numpy()
+    return out
 
 
 def build_fp8_model(cfg, weights: Mapping[str, np.ndarray], calib: Sequence, device: str = "cuda",

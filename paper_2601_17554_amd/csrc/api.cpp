@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/mlpf.h"
+#include "candidates.h"
 #include "kernels.h"
 
 using namespace mlpf;
@@ -873,6 +874,36 @@ mlpf_status_t mlpf_reconstruct_events(mlpf_model_t model, const float* x,
   if ((st = do_embed(cx, x, h))) return st;
   if ((st = do_encoder(cx, h))) return st;
   return do_heads(cx, h, logits, reg, cls, prim, decoded);
+}
+
+mlpf_status_t mlpf_candidates(const mlpf_batch_t* batch, const int32_t* cls, const float* decoded,
+                              int32_t* event_offsets, int32_t* cand_row, int32_t* cand_cls,
+                              float* cand_kin, int32_t cap, void* stream) {
+  mlpf_status_t st = check_batch(nullptr, batch);
+  if (st) return st;
+  if (!event_offsets) return fail(MLPF_ERR_INVALID_ARG, "event_offsets is NULL");
+  if (batch->total_rows > 0 && !cls) return fail(MLPF_ERR_INVALID_ARG, "cls is NULL");
+  if (cap < 0) return fail(MLPF_ERR_INVALID_ARG, "negative cap");
+  if (cap > 0 && (!cand_row || !cand_cls))
+    return fail(MLPF_ERR_INVALID_ARG, "cand_row or cand_cls is NULL");
+  if (cand_kin && !decoded) return fail(MLPF_ERR_INVALID_ARG, "cand_kin needs decoded");
+  if ((cand_kin && ((uintptr_t)cand_kin % 16 != 0)) || (decoded && ((uintptr_t)decoded % 16 != 0)))
+    return fail(MLPF_ERR_INVALID_ARG, "cand_kin and decoded must be 16-byte aligned");
+  CandArgs a;
+  a.row_start = batch->row_start;
+  a.n_valid = batch->n_valid;
+  a.n_events = batch->n_events;
+  a.total_rows = batch->total_rows;
+  a.max_seqlen = batch->max_seqlen;
+  a.cls = cls;
+  a.decoded = decoded;
+  a.offsets = event_offsets;
+  a.cand_row = cand_row;
+  a.cand_cls = cand_cls;
+  a.cand_kin = cand_kin;
+  a.cap = cap;
+  HIP_TRY(launch_candidates(a, (hipStream_t)stream), "candidate launch");
+  return MLPF_OK;
 }
 
 struct mlpf_graph_s {

@@ -47,6 +47,32 @@ def test_sizes_and_validation_without_gpu():
     assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG"  # host_weights NULL
 
 
+def test_candidates_validation_without_gpu():
+    """mlpf_candidates rejects bad arguments before anything is enqueued (fake non-NULL device
+    addresses are never dereferenced on these paths)."""
+    B, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    odd = ctypes.c_void_p(0x1008)
+
+    def status(batch, cls, dec, offs, rows, clss, kin, cap):
+        return lib.mlpf_status_string(lib.mlpf_candidates(batch, cls, dec, offs, rows, clss, kin, cap, None))
+
+    good = B._Batch(fake, None, 2, 10, 10)
+    neg = B._Batch(fake, None, -1, 10, 10)
+    big = B._Batch(fake, None, 2, 10, 100_000)
+    assert status(None, fake, None, fake, fake, fake, None, 4) == b"MLPF_ERR_INVALID_ARG"
+    assert status(ctypes.byref(neg), fake, None, fake, fake, fake, None, 4) == b"MLPF_ERR_INVALID_ARG"
+    assert status(ctypes.byref(big), fake, None, fake, fake, fake, None, 4) == b"MLPF_ERR_UNSUPPORTED"
+    assert status(ctypes.byref(good), None, None, fake, fake, fake, None, 4) == b"MLPF_ERR_INVALID_ARG"
+    assert status(ctypes.byref(good), fake, None, None, fake, fake, None, 4) == b"MLPF_ERR_INVALID_ARG"
+    assert status(ctypes.byref(good), fake, None, fake, fake, fake, None, -1) == b"MLPF_ERR_INVALID_ARG"
+    assert status(ctypes.byref(good), fake, None, fake, None, fake, None, 4) == b"MLPF_ERR_INVALID_ARG"
+    assert status(ctypes.byref(good), fake, None, fake, fake, fake, fake, 4) == b"MLPF_ERR_INVALID_ARG"
+    assert b"decoded" in lib.mlpf_last_error()
+    assert status(ctypes.byref(good), fake, odd, fake, fake, fake, fake, 4) == b"MLPF_ERR_INVALID_ARG"
+    assert b"aligned" in lib.mlpf_last_error()
+
+
 def test_no_cpu_fallback_when_library_missing(monkeypatch):
     from paper_2601_17554_amd import binding as B
     monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libmlpf.so")
