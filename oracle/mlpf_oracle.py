@@ -24,7 +24,8 @@ Readings where the paper is silent (each is listed with its reason in the design
   * serial topology by default (one stack of L blocks read by all heads); 'parallel2' is the
     paper's two-encoder form: stack A = first L/2 blocks -> classification head, stack B = last
     L/2 blocks -> regression heads, both fed by the same embedding;
-  * activation: exact-erf GELU after every hidden linear layer, none after output layers;
+  * activation: exact-erf GELU after every hidden linear layer, none after output layers; the
+    paper's own network uses ReLU there (Sec. 5.3), available as cfg.activation = 'relu';
   * pre-LN blocks: H += MHA(LN1(H)); H += FFN(LN2(H)); no final LayerNorm; eps 1e-5; biased
     variance; affine gamma/beta;
   * attention: Q/K/V/O biases, contiguous head split (head j owns columns j*d_h..(j+1)*d_h-1),
@@ -50,6 +51,14 @@ def gelu(z: np.ndarray) -> np.ndarray:
     """GELU(z) = z * Phi(z) = z/2 * (1 + erf(z / sqrt 2)), the exact (erf) form."""
     z = np.asarray(z, dtype=np.float64)
     return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
+
+
+def relu(z: np.ndarray) -> np.ndarray:
+    """ReLU(z) = max(z, 0), the activation of the paper's network (Sec. 5.3)."""
+    return np.maximum(np.asarray(z, dtype=np.float64), 0.0)
+
+
+ACTIVATIONS = {"gelu": gelu, "relu": relu}
 
 
 def layer_norm(z: np.ndarray, gamma: np.ndarray, beta: np.ndarray, eps: float) -> np.ndarray:
@@ -89,23 +98,24 @@ def mha(y: np.ndarray, w_qkv, b_qkv, w_o, b_o, n_heads: int) -> np.ndarray:
     return o @ w_o + b_o
 
 
-def encoder_block(h: np.ndarray, p: Mapping[str, np.ndarray], n_heads: int, eps: float) -> np.ndarray:
+def encoder_block(h: np.ndarray, p: Mapping[str, np.ndarray], n_heads: int, eps: float,
+                  act=gelu) -> np.ndarray:
     """One pre-LN transformer block: LayerNorm before attention and before the FFN."""
     y = layer_norm(h, p["ln1.gamma"], p["ln1.beta"], eps)
     h = h + mha(y, p["W_qkv"], p["b_qkv"], p["W_o"], p["b_o"], n_heads)
     y = layer_norm(h, p["ln2.gamma"], p["ln2.beta"], eps)
-    return h + gelu(y @ p["W_1"] + p["b_1"]) @ p["W_2"] + p["b_2"]
+    return h + act(y @ p["W_1"] + p["b_1"]) @ p["W_2"] + p["b_2"]
 
 
-def embed(x: np.ndarray, w: Mapping[str, np.ndarray]) -> np.ndarray:
-    """Element embedding FFN: Linear(F, d) -> GELU -> Linear(d, d)."""
-    return gelu(x @ w["embed.W1"] + w["embed.b1"]) @ w["embed.W2"] + w["embed.b2"]
+def embed(x: np.ndarray, w: Mapping[str, np.ndarray], act=gelu) -> np.ndarray:
+    """Element embedding FFN: Linear(F, d) -> activation -> Linear(d, d)."""
+    return act(x @ w["embed.W1"] + w["embed.b1"]) @ w["embed.W2"] + w["embed.b2"]
 
 
-def head(h: np.ndarray, w: Mapping[str, np.ndarray], name: str) -> np.ndarray:
-    """Two-layer FFN head: Linear(d, d) -> GELU -> Linear(d, width)."""
+def head(h: np.ndarray, w: Mapping[str, np.ndarray], name: str, act=gelu) -> np.ndarray:
+    """Two-layer FFN head: Linear(d, d) -> activation -> Linear(d, width)."""
     p = f"heads.{name}."
-    return gelu(h @ w[p + "W1"] + w[p + "b1"]) @ w[p + "W2"] + w[p + "b2"]
+    return act(h @ w[p + "W1"] + w[p + "b1"]) @ w[p + "W2"] + w[p + "b2"]
 
 
 def argmax_lowest(logits: np.ndarray) -> np.ndarray:
@@ -130,24 +140,25 @@ def forward(x: np.ndarray, weights: Mapping[str, np.ndarray], cfg) -> Dict[str, 
     w = _as64(weights)
     x = np.asarray(x, dtype=np.float64)
     n_layers, n_heads, eps = cfg.n_layers, cfg.n_heads, cfg.ln_eps
-    h0 = embed(x, w)
+    act = ACTIVATIONS[getattr(cfg, "activation", "gelu")]
+    h0 = embed(x, w, act)
     if cfg.topology == "serial":
         h = h0
         for layer in range(n_layers):
-            h = encoder_block(h, _layer_params(w, layer), n_heads, eps)
+            h = encoder_block(h, _layer_params(w, layer), n_heads, eps, act)
         h_cls = h_reg = h
     elif cfg.topology == "parallel2":
         half = n_layers // 2
         h_cls = h0
         for layer in range(half):
-            h_cls = encoder_block(h_cls, _layer_params(w, layer), n_heads, eps)
+            h_cls = encoder_block(h_cls, _layer_params(w, layer), n_heads, eps, act)
         h_reg = h0
         for layer in range(half, n_layers):
-            h_reg = encoder_block(h_reg, _layer_params(w, layer), n_heads, eps)
+            h_reg = encoder_block(h_reg, _layer_params(w, layer), n_heads, eps, act)
     else:
         raise ValueError(f"unknown topology {cfg.topology!r}")
-    logits = head(h_cls, w, "cls")
-    reg = np.concatenate([head(h_reg, w, name) for name, _ in HEAD_WIDTHS[1:]], axis=-1)
+    logits = head(h_cls, w, "cls", act)
+    reg = np.concatenate([head(h_reg, w, name, act) for name, _ in HEAD_WIDTHS[1:]], axis=-1)
     return {"logits": logits, "reg": reg, "cls": argmax_lowest(logits), "h_cls": h_cls, "h_reg": h_reg}
 
 

@@ -44,6 +44,7 @@ class Config:
     n_layers: int = 6
     topology: str = "serial"
     ln_eps: float = 1e-5
+    activation: str = "gelu"  # or "relu" (the paper's network, Sec. 5.3)
 
     @property
     def d_head(self) -> int:

@@ -3,6 +3,7 @@
 Each test names what pins it: a printed table, a closed form, an invariant of the method, a
 library routine that computes the same textbook operation, or brute force on tiny inputs.
 """
+import dataclasses
 import math
 import os
 
@@ -156,14 +157,17 @@ def test_encoder_block_vs_torch_transformer_layer(cfg):
     np.testing.assert_allclose(got, ref[:n_valid], rtol=0, atol=1e-11)
 
 
-def test_embed_and_heads_vs_torch_mlp():
+@pytest.mark.parametrize("act", ["gelu", "relu"])
+def test_embed_and_heads_vs_torch_mlp(act):
     cfg = synth.SMALL
     w = synth.make_weights(cfg, seed=8)
     x = synth.make_features(np.random.default_rng(9), 21)
     t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
+    f = O.ACTIVATIONS[act]
 
     def mlp(W1, b1, W2, b2):
-        m = torch.nn.Sequential(torch.nn.Linear(W1.shape[0], W1.shape[1]), torch.nn.GELU(),
+        layer = torch.nn.GELU() if act == "gelu" else torch.nn.ReLU()
+        m = torch.nn.Sequential(torch.nn.Linear(W1.shape[0], W1.shape[1]), layer,
                                 torch.nn.Linear(W2.shape[0], W2.shape[1])).double()
         with torch.no_grad():
             m[0].weight.copy_(t(W1).T); m[0].bias.copy_(t(b1))
@@ -172,12 +176,12 @@ def test_embed_and_heads_vs_torch_mlp():
 
     e = mlp(w["embed.W1"], w["embed.b1"], w["embed.W2"], w["embed.b2"])
     with torch.no_grad():
-        np.testing.assert_allclose(O.embed(x.astype(np.float64), w), e(t(x)).numpy(), atol=1e-13)
+        np.testing.assert_allclose(O.embed(x.astype(np.float64), w, f), e(t(x)).numpy(), atol=1e-13)
         h = np.random.default_rng(1).standard_normal((21, cfg.d_model))
         for name, _ in synth.HEADS:
             p = f"heads.{name}."
             m = mlp(w[p + "W1"], w[p + "b1"], w[p + "W2"], w[p + "b2"])
-            np.testing.assert_allclose(O.head(h, O._as64(w), name), m(t(h)).numpy(), atol=1e-13)
+            np.testing.assert_allclose(O.head(h, O._as64(w), name, f), m(t(h)).numpy(), atol=1e-13)
 
 
 # ---------------------------------------------------------------- whole forward
@@ -185,7 +189,10 @@ def test_embed_and_heads_vs_torch_mlp():
 def _brute_forward(x, w, cfg):
     """The whole forward as scalar pure-Python loops with math.fsum (tiny sizes only)."""
     erf = math.erf
-    g = lambda z: 0.5 * z * (1 + erf(z / math.sqrt(2)))
+    if getattr(cfg, "activation", "gelu") == "relu":
+        g = lambda z: z if z > 0 else 0.0
+    else:
+        g = lambda z: 0.5 * z * (1 + erf(z / math.sqrt(2)))
     W = {k: np.asarray(v, np.float64).tolist() for k, v in w.items()}
 
     def lin(rows, Wm, b, act=False):
@@ -231,12 +238,13 @@ def _brute_forward(x, w, cfg):
     return logits, reg
 
 
-@pytest.mark.parametrize("n", [1, 3, 6])
-def test_forward_brute_force_tiny(n):
-    w = synth.make_weights(TINY, seed=11, sharpen=8.0)
+@pytest.mark.parametrize("n,act", [(1, "gelu"), (3, "gelu"), (6, "gelu"), (5, "relu")])
+def test_forward_brute_force_tiny(n, act):
+    cfg = dataclasses.replace(TINY, activation=act)
+    w = synth.make_weights(cfg, seed=11, sharpen=8.0)
     x = synth.make_features(np.random.default_rng(n), n)
-    out = O.forward(x, w, TINY)
-    logits, reg = _brute_forward(x, w, TINY)
+    out = O.forward(x, w, cfg)
+    logits, reg = _brute_forward(x, w, cfg)
     np.testing.assert_allclose(out["logits"], logits, rtol=0, atol=1e-13)
     np.testing.assert_allclose(out["reg"], reg, rtol=0, atol=1e-13)
 
