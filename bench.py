@@ -34,18 +34,29 @@ EVENTS_PER_BATCH = 64
 # HBM bytes per launch of the BF16 attention kernel on these batches, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) of paper_2601_17554_amd/profile_run.py scaled by a 256 MiB copy
 # (profiles/attention_bf16_varlen64_hbm_traffic.md). Valid only for the kernel source it was
-# measured on: reported as null once attention.hip, common.h or kernels.h change.
-ATTN_TRAFFIC = {"sha256": "3528ad0b50c001057b56d90b28aab254a017575145a18cb6a7d529cb214cc545",
+# measured on: reported as null once that source changes (attention.hip, common.h, and the
+# attention declarations of kernels.h: AttnArgs, AttnTile and the launchers).
+ATTN_TRAFFIC = {"sha256": "fa6d24065d23f92277ca6ef0aed565adbbd3e54eebf56e9316dc7df0a11036b9",
                 "bytes_per_launch": 457956322.2}
 
 
-def attention_traffic():
+def attention_source_hash() -> str:
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2601_17554_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("attention.hip", "common.h", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_2601_17554_amd", "csrc", f), "rb") as fh:
+    for f in ("attention.hip", "common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    return ATTN_TRAFFIC["bytes_per_launch"] if h.hexdigest() == ATTN_TRAFFIC["sha256"] else None
+    with open(os.path.join(csrc, "kernels.h"), "r") as fh:
+        k = fh.read()
+    a = k.index("// Attention over a device work list")
+    b = k.index("\n", k.index("hipError_t launch_keynorm("))
+    h.update(k[a:b].encode())
+    return h.hexdigest()
+
+
+def attention_traffic():
+    return ATTN_TRAFFIC["bytes_per_launch"] if attention_source_hash() == ATTN_TRAFFIC["sha256"] else None
 
 
 def attention_flops(n: np.ndarray, cfg) -> float:
