@@ -66,6 +66,9 @@ typedef enum {
                              regression heads */
 } mlpf_topology_t;
 
+/* The hidden-layer activation: the exact (erf) GELU, or ReLU as in the paper's network (Sec. 5.3). */
+typedef enum { MLPF_ACT_GELU = 0, MLPF_ACT_RELU = 1 } mlpf_activation_t;
+
 typedef struct {
   int32_t n_features; /* F: features per element, 1..32 */
   int32_t d_model;    /* d: multiple of 64, 64..1024 */
@@ -74,6 +77,7 @@ typedef struct {
   int32_t n_layers;   /* >= 1; even for MLPF_TOPO_PARALLEL2 */
   int32_t topology;   /* mlpf_topology_t */
   float ln_eps;       /* LayerNorm epsilon (> 0) */
+  int32_t activation; /* mlpf_activation_t: after every hidden linear layer (embedding, FFN, heads) */
 } mlpf_config_t;
 
 typedef struct mlpf_model_s* mlpf_model_t;

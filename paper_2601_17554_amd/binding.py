@@ -34,7 +34,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("n_features", ctypes.c_int32), ("d_model", ctypes.c_int32),
                 ("n_heads", ctypes.c_int32), ("d_ff", ctypes.c_int32),
                 ("n_layers", ctypes.c_int32), ("topology", ctypes.c_int32),
-                ("ln_eps", ctypes.c_float)]
+                ("ln_eps", ctypes.c_float), ("activation", ctypes.c_int32)]
 
 
 class _Batch(ctypes.Structure):
@@ -99,6 +99,7 @@ def exported_symbols() -> Sequence[str]:
             "mlpf_tune_shape", "mlpf_candidates", "mlpf_status_string", "mlpf_last_error")
 
 
+ACTIVATIONS = {"gelu": 0, "relu": 1}
 PROF_CLASSES = ("embed", "qkv", "attention", "outproj", "ffn1", "ffn2", "heads", "worklist")
 OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1", "attention", "ffn",
        "heads")
@@ -132,7 +133,8 @@ def _stream(stream: Optional[torch.cuda.Stream]) -> int:
 def make_config(cfg) -> _Config:
     """From any object with the config attributes (n_features, d_model, ...)."""
     return _Config(cfg.n_features, cfg.d_model, cfg.n_heads, cfg.d_ff, cfg.n_layers,
-                   TOPOLOGIES[cfg.topology], cfg.ln_eps)
+                   TOPOLOGIES[cfg.topology], cfg.ln_eps,
+                   ACTIVATIONS[getattr(cfg, "activation", "gelu")])
 
 
 def flatten_weights(weights: Mapping[str, np.ndarray], cfg) -> np.ndarray:

@@ -171,6 +171,8 @@ mlpf_status_t check_config(const mlpf_config_t* c) {
     return fail(MLPF_ERR_INVALID_ARG, "PARALLEL2 needs an even n_layers");
   if (!(c->ln_eps > 0.f) || !std::isfinite(c->ln_eps))
     return fail(MLPF_ERR_INVALID_ARG, "ln_eps must be positive");
+  if (c->activation != MLPF_ACT_GELU && c->activation != MLPF_ACT_RELU)
+    return fail(MLPF_ERR_INVALID_ARG, "unknown activation %d", c->activation);
   return MLPF_OK;
 }
 
@@ -307,6 +309,7 @@ int attn_tile_of(const mlpf_model_s* m) {
 
 mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a, int prec = -1) {
   a.m_dev = cx.n_rows;
+  a.relu = cx.m->cfg.activation == MLPF_ACT_RELU;
   const int pr = prec >= 0 ? prec : (int)cx.m->kprec;
   const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N, (Prec)pr);
   HIP_TRY(launch_gemm((Prec)pr, al, ep, tile, a, cx.s), "gemm launch");
@@ -526,6 +529,7 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
     a.b1 = m->atf(L.b1);
     a.w2p = m->at(L.w2p);
     a.b2 = m->atf(L.b2);
+    a.relu = c.activation == MLPF_ACT_RELU;
     a.h = h;
     if (fuse_next_ln) {
       const Layer& Ln = m->plan.layers[layer + 1];
@@ -623,7 +627,8 @@ mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, 
       a.w2 = m->atf(m->plan.h_w2);
       a.hout = (float*)cx.p(cx.w.u);
       a.head0 = c0 / d;
-      HIP_TRY(launch_gemm(P_BF16, A_PLAIN, E_HEADS, kHeadsTile, a, cx.s), "gemm launch");
+      a.relu = m->cfg.activation == MLPF_ACT_RELU;
+    HIP_TRY(launch_gemm(P_BF16, A_PLAIN, E_HEADS, kHeadsTile, a, cx.s), "gemm launch");
       continue;
     }
     if ((st = run_gemm(cx, MLPF_OP_HEADS1, m->hbytes == 2 ? A_PLAIN : A_F32, E_GELU, a))) return st;

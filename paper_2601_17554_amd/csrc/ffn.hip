@@ -24,6 +24,13 @@ namespace {
 
 constexpr int kFfnHC = 64;  // hidden units per chunk
 
+// The hidden activation: exact (erf) GELU, or ReLU (the paper's network).
+template <bool RELU>
+__device__ __forceinline__ float hidden_act(float z) {
+  if constexpr (RELU) return fmaxf(z, 0.f);
+  else return gelu_erf(z);
+}
+
 // LDS image of one workgroup: W1 and W2^T chunk buffers (two of each when double buffered), the U
 // tile, and (reusing the same bytes after the chunk loop) the FP32 epilogue staging.
 template <int D, int BM, bool DBUF>
@@ -125,7 +132,7 @@ __device__ __forceinline__ void ln_fragments(u32x4* yf, int h, const float* gam,
 // chunk (one workgroup per CU at d_model 256). Single buffered: W1 of chunk c+1 is fetched during
 // phase 2 of chunk c, W2 after it, and the LDS image is small enough for two workgroups per CU,
 // which then hide each other's waits.
-template <int D, int BM, int NW, bool DBUF>
+template <int D, int BM, int NW, bool DBUF, bool RELU>
 __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
   using L = FfnLayout<D, BM, DBUF>;
   constexpr int NT = NW * 64;
@@ -227,8 +234,8 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         *(u32x2*)(urow + 16 * q) =
-            pack_bf16x4(gelu_erf(u[4 * q] + bq[q][0]), gelu_erf(u[4 * q + 1] + bq[q][1]),
-                        gelu_erf(u[4 * q + 2] + bq[q][2]), gelu_erf(u[4 * q + 3] + bq[q][3]));
+            pack_bf16x4(hidden_act<RELU>(u[4 * q] + bq[q][0]), hidden_act<RELU>(u[4 * q + 1] + bq[q][1]),
+                        hidden_act<RELU>(u[4 * q + 2] + bq[q][2]), hidden_act<RELU>(u[4 * q + 3] + bq[q][3]));
       }
     }
     __syncthreads();
@@ -331,7 +338,7 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
 // loaded once. The epilogue stages half a tile at a time in the weight buffer the last chunk used.
 // Chunk buffers alternate across tiles (par = buffer of a tile's first chunk), so any chunk count
 // works. Arithmetic and summation order are those of ffn_fused_kernel (same bits).
-template <int D>
+template <int D, bool RELU>
 __global__ __launch_bounds__(512) void ffn_persistent_kernel(const FfnArgs p) {
   constexpr int BM = 128, NW = 8, NT = NW * 64, HALF = BM / 2;
   constexpr int W1RS = 2 * D + 16, W1CH = kFfnHC * W1RS;
@@ -438,8 +445,8 @@ __global__ __launch_bounds__(512) void ffn_persistent_kernel(const FfnArgs p) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           *(u32x2*)(urow + 16 * q) =
-              pack_bf16x4(gelu_erf(u[4 * q] + bq[q][0]), gelu_erf(u[4 * q + 1] + bq[q][1]),
-                          gelu_erf(u[4 * q + 2] + bq[q][2]), gelu_erf(u[4 * q + 3] + bq[q][3]));
+              pack_bf16x4(hidden_act<RELU>(u[4 * q] + bq[q][0]), hidden_act<RELU>(u[4 * q + 1] + bq[q][1]),
+                          hidden_act<RELU>(u[4 * q + 2] + bq[q][2]), hidden_act<RELU>(u[4 * q + 3] + bq[q][3]));
         }
       }
       __syncthreads();
@@ -546,7 +553,7 @@ __global__ __launch_bounds__(512) void ffn_persistent_kernel(const FfnArgs p) {
 // c%2 and W2, b1 of c+1 to buffer (c+1)%2. The epilogue stages in buffer 1 (the last chunk's);
 // the next tile's W1 and W2 of chunk 0 arrive in buffer 0 during the last two chunks, its W1 of
 // chunk 1 at the tile's start. Arithmetic and summation order are those of ffn_fused_kernel.
-template <int D>
+template <int D, bool RELU>
 __global__ __launch_bounds__(512) void ffn_pipelined_kernel(const FfnArgs p) {
   constexpr int BM = 128, NW = 8, NT = NW * 64, HALF = BM / 2;
   constexpr int W1RS = 2 * D + 16, W1CH = kFfnHC * W1RS;
@@ -615,8 +622,8 @@ __global__ __launch_bounds__(512) void ffn_pipelined_kernel(const FfnArgs p) {
   auto gelu_part = [&](const f32x16& u, int q, const float* b1s) {
     const f32x4 bq = *(const f32x4*)(b1s + 8 * q);
     *(u32x2*)(urow + 16 * q) =
-        pack_bf16x4(gelu_erf(u[4 * q] + bq[0]), gelu_erf(u[4 * q + 1] + bq[1]),
-                    gelu_erf(u[4 * q + 2] + bq[2]), gelu_erf(u[4 * q + 3] + bq[3]));
+        pack_bf16x4(hidden_act<RELU>(u[4 * q] + bq[0]), hidden_act<RELU>(u[4 * q + 1] + bq[1]),
+                    hidden_act<RELU>(u[4 * q + 2] + bq[2]), hidden_act<RELU>(u[4 * q + 3] + bq[3]));
   };
 
   if (p.ln_in_g) {
@@ -771,7 +778,7 @@ __global__ __launch_bounds__(512) void ffn_pipelined_kernel(const FfnArgs p) {
   }
 }
 
-template <int D>
+template <int D, bool RELU>
 hipError_t launch_pipelined(const FfnArgs& p, hipStream_t s) {
   if ((p.d_ff / kFfnHC) & 1) return hipErrorInvalidValue;
   const int64_t tiles = ((int64_t)p.M + 127) / 128;
@@ -785,16 +792,16 @@ hipError_t launch_pipelined(const FfnArgs& p, hipStream_t s) {
     int cus = 0, per_cu = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ffn_pipelined_kernel<D>, 512, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ffn_pipelined_kernel<D, RELU>, 512, 0);
     if (e != hipSuccess) return e;
     slots[dev] = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
   }
   const unsigned grid = (unsigned)(tiles < slots[dev] ? tiles : slots[dev]);
-  hipLaunchKernelGGL((ffn_pipelined_kernel<D>), dim3(grid), dim3(512), 0, s, p);
+  hipLaunchKernelGGL((ffn_pipelined_kernel<D, RELU>), dim3(grid), dim3(512), 0, s, p);
   return hipGetLastError();
 }
 
-template <int D>
+template <int D, bool RELU>
 hipError_t launch_persistent(const FfnArgs& p, hipStream_t s) {
   const int64_t tiles = ((int64_t)p.M + 127) / 128;
   if (tiles == 0) return hipSuccess;
@@ -809,24 +816,24 @@ hipError_t launch_persistent(const FfnArgs& p, hipStream_t s) {
     int cus = 0, per_cu = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ffn_persistent_kernel<D>, 512, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ffn_persistent_kernel<D, RELU>, 512, 0);
     if (e != hipSuccess) return e;
     slots[dev] = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
   }
   const unsigned grid = (unsigned)(tiles < slots[dev] ? tiles : slots[dev]);
-  hipLaunchKernelGGL((ffn_persistent_kernel<D>), dim3(grid), dim3(512), 0, s, p);
+  hipLaunchKernelGGL((ffn_persistent_kernel<D, RELU>), dim3(grid), dim3(512), 0, s, p);
   return hipGetLastError();
 }
 
-template <int BM, int NW, bool DBUF>
+template <int BM, int NW, bool DBUF, bool RELU>
 hipError_t launch_v(const FfnArgs& p, hipStream_t s) {
   const int64_t grid = ((int64_t)p.M + BM - 1) / BM;
   if (grid == 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
   switch (p.d_model) {
-    case 64: hipLaunchKernelGGL((ffn_fused_kernel<64, BM, NW, DBUF>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
-    case 128: hipLaunchKernelGGL((ffn_fused_kernel<128, BM, NW, DBUF>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
-    default: hipLaunchKernelGGL((ffn_fused_kernel<256, BM, NW, DBUF>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
+    case 64: hipLaunchKernelGGL((ffn_fused_kernel<64, BM, NW, DBUF, RELU>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
+    case 128: hipLaunchKernelGGL((ffn_fused_kernel<128, BM, NW, DBUF, RELU>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
+    default: hipLaunchKernelGGL((ffn_fused_kernel<256, BM, NW, DBUF, RELU>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
   }
   return hipGetLastError();
 }
@@ -859,25 +866,32 @@ void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, u
 
 // Variants 1 and 2 as declared; 3 = variant 1 as a persistent kernel (ffn_persistent_kernel);
 // 4 = the software-pipelined persistent kernel (even chunk counts).
-hipError_t launch_ffn_fused(const FfnArgs& p, int variant, hipStream_t s) {
-  if (!ffn_fused_supported(p.d_model, p.d_ff)) return hipErrorInvalidValue;
-  if (variant == 1) return launch_v<128, 8, true>(p, s);
-  if (variant == 2) return launch_v<64, 4, false>(p, s);
+namespace {
+template <bool RELU>
+hipError_t launch_variant(const FfnArgs& p, int variant, hipStream_t s) {
+  if (variant == 1) return launch_v<128, 8, true, RELU>(p, s);
+  if (variant == 2) return launch_v<64, 4, false, RELU>(p, s);
   if (variant == 3) {
     switch (p.d_model) {
-      case 64: return launch_persistent<64>(p, s);
-      case 128: return launch_persistent<128>(p, s);
-      default: return launch_persistent<256>(p, s);
+      case 64: return launch_persistent<64, RELU>(p, s);
+      case 128: return launch_persistent<128, RELU>(p, s);
+      default: return launch_persistent<256, RELU>(p, s);
     }
   }
   if (variant == 4) {
     switch (p.d_model) {
-      case 64: return launch_pipelined<64>(p, s);
-      case 128: return launch_pipelined<128>(p, s);
-      default: return launch_pipelined<256>(p, s);
+      case 64: return launch_pipelined<64, RELU>(p, s);
+      case 128: return launch_pipelined<128, RELU>(p, s);
+      default: return launch_pipelined<256, RELU>(p, s);
     }
   }
   return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_ffn_fused(const FfnArgs& p, int variant, hipStream_t s) {
+  if (!ffn_fused_supported(p.d_model, p.d_ff)) return hipErrorInvalidValue;
+  return p.relu ? launch_variant<true>(p, variant, s) : launch_variant<false>(p, variant, s);
 }
 
 }  // namespace mlpf

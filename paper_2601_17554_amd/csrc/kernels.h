@@ -40,6 +40,7 @@ struct GemmArgs {
   float acc_scale = 1.f;   // multiplies A W before the bias (FP8 dequantisation s_a * s_w)
   float out_scale = 1.f;   // E_GELU into FP8: multiplies GELU(...) before rounding (1 / s_out)
   float* amax = nullptr;   // E_GELU: optional running max |GELU(...)| (calibration; atomic max)
+  int relu = 0;            // E_GELU, E_HEADS: ReLU instead of GELU
   // E_QKV
   void* q = nullptr;
   void* k = nullptr;
@@ -80,6 +81,7 @@ struct FfnArgs {
   const float* b1 = nullptr;
   const void* w2p = nullptr;
   const float* b2 = nullptr;
+  int relu = 0;                 // ReLU instead of GELU
   void* h = nullptr;            // bf16 [M][d_model], updated in place (sum taken in FP32)
   // Optional: the next block's LN1 of the updated h, written as bf16 [M][d_model] (the operand of
   // the next QKV projection), bitwise equal to the LayerNorm kernel's output.

@@ -35,6 +35,13 @@ def test_sizes_and_validation_without_gpu():
     fp32 = lib.mlpf_weights_bytes(ctypes.byref(cfg), 0)
     bf16 = lib.mlpf_weights_bytes(ctypes.byref(cfg), 1)
     assert fp32 >= 4 * synth.param_count(synth.FULL) and bf16 < fp32
+    import dataclasses
+    act = B.make_config(dataclasses.replace(synth.FULL, activation="relu"))
+    assert act.activation == 1
+    act.activation = 7
+    h0 = ctypes.c_void_p()
+    st = lib.mlpf_model_create(ctypes.byref(act), 0, None, 0, None, None, 0, None, ctypes.byref(h0))
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG" and b"activation" in lib.mlpf_last_error()
     bad = B.make_config(synth.Config(d_model=96, n_heads=3))
     assert lib.mlpf_weights_bytes(ctypes.byref(bad), 0) == 0
     h = ctypes.c_void_p()

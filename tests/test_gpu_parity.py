@@ -326,6 +326,29 @@ def test_persistent_ffn_many_tiles(B):
         check_event(pers, oracle(pk.x[rows], w, cfg), rows, TOL["bf16"], f"persistent FFN event {e}")
 
 
+@pytest.mark.parametrize("prec,cfg", [("fp32", synth.SMALL), ("bf16", synth.FULL), ("bf16", synth.PAPER)],
+                         ids=["fp32-small", "bf16-full", "bf16-paper_parallel2"])
+def test_relu_activation(B, prec, cfg):
+    """The ReLU form of every hidden layer (the paper's network) against the oracle on ragged
+    events with garbage padding; in BF16 the fused FFN shapes and the two-product FFN give the
+    same bits."""
+    import dataclasses
+    cfg = dataclasses.replace(cfg, activation="relu")
+    w, m = _model(B, cfg, 31, prec, sharpen=2.0)
+    evs = [synth.make_event(5200 + i, n) for i, n in enumerate([200, 1, 77, 300])]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=11)
+    got = run_gpu(m, pk)
+    _check_all(got, pk, w, cfg, TOL[prec], f"relu {prec}")
+    if prec == "bf16":
+        for variant in (0, 1, 2, 3, 4):
+            m.tune_set("ffn", variant)
+            other = run_gpu(m, pk)
+            for e in range(pk.n_events):
+                r = pk.event_rows(e)
+                for k in ("logits", "reg", "cls"):
+                    np.testing.assert_array_equal(got[k][r], other[k][r], err_msg=f"ffn {variant} {k}")
+
+
 @pytest.mark.parametrize("cfg", [synth.FULL, synth.PAPER], ids=["d256", "paper_parallel2"])
 def test_fused_heads(B, cfg):
     """The head GEMM with the second head layer in its epilogue (BF16, d_model 256) against the
