@@ -318,6 +318,7 @@ def main():
     ap.add_argument("--small-reps", type=int, default=2000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-layout", action="store_true")
     ap.add_argument("--serve-rates", type=int, nargs="*", default=[200, 500, 1000, 2000])
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     args = ap.parse_args()
@@ -339,6 +340,26 @@ def main():
     print("bench: fp32 plain done", file=sys.stderr, flush=True)
     pb = bench_plain(args, cfg, w, "bf16")
     print("bench: bf16 plain done", file=sys.stderr, flush=True)
+    pl_layout = None
+    if not args.no_paper_layout:
+        # The paper's own layout (two parallel 3-block encoders, 16 heads of width 16) on the same
+        # batches: twice the exponentials per score FLOP of the d_head 32 model.
+        pargs = argparse.Namespace(**vars(args))
+        pargs.steps, pargs.warmup = min(args.steps, 10), 1
+        pc = synth.PAPER
+        pr = bench_varlen(pargs, pc, synth.make_weights(pc, 1))
+        a_ms = pr["attn_ms"] / max(pr["attn_launches"], 1)
+        a_fl = pr["attn_flops"] / max(pr["attn_launches"], 1)
+        pl_layout = {
+            "model": "d256 h16 (d_head 16) ffn1024, two parallel stacks of 3 blocks",
+            "value": round(pr["events"] / pr["wall_s"], 2), "unit": "events/s",
+            "ms_per_step": round(pr["wall_s"] * 1e3 / pargs.steps, 3), "steps": pargs.steps,
+            "attention_avg_launch_ms": round(a_ms, 4),
+            "attention_frac_bf16_peak": round(a_fl / (a_ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"], 4),
+            "attention_exp_frac": round(a_fl * pc.n_heads / (4.0 * pc.d_model) / (a_ms * 1e-3) / 1e12
+                                        / PEAK_EXP_T_PER_S, 4),
+            "tiles": pr["tiles"]}
+        print(f"bench: paper layout {pl_layout['value']} events/s", file=sys.stderr, flush=True)
     vr = bench_varlen(args, cfg, w)
     print(f"bench: varlen {vr['events'] / vr['wall_s']:.1f} events/s", file=sys.stderr, flush=True)
 
@@ -381,6 +402,7 @@ def main():
                                      "unit": "Texp/s", "frac": round(exp_rate / PEAK_EXP_T_PER_S, 4)}},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in vr["prof"].items()},
         "candidates": vr["candidates"],
+        "paper_layout_bf16": pl_layout,
     }
     if args.serve_rates:
         line["serving"] = bench_serving(args, cfg, w)
