@@ -191,3 +191,35 @@ def test_candidates_from_forward(B):
         assert abs(dphi) <= np.sqrt(2) * tol * scale / hyp, (r, g, kin, hyp)
         checked += 1
     assert checked > 50
+
+
+def test_candidates_graph_capture(B):
+    """mlpf_candidates captured in a HIP graph (through torch's graph API) and replayed after the
+    classes are rewritten in place: every replay equals the oracle on the current classes."""
+    import torch
+    rng = np.random.default_rng(12)
+    lens = rng.integers(0, 300, 20)
+    rs = np.concatenate([[0], np.cumsum(lens)])
+    T = int(rs[-1])
+    batch = B.Batch.from_host(rs, None, max_seqlen=8192)
+    cls = torch.zeros(T, dtype=torch.int32, device="cuda")
+    kin = torch.as_tensor(rng.standard_normal((T, 4)).astype(np.float32)).cuda()
+    out = {"offsets": torch.empty(len(rs), dtype=torch.int32, device="cuda"),
+           "rows": torch.empty(T, dtype=torch.int32, device="cuda"),
+           "cls": torch.empty(T, dtype=torch.int32, device="cuda"),
+           "kin": torch.empty(T, 4, dtype=torch.float32, device="cuda")}
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        B.mlpf_candidates(batch, cls, kin, out["offsets"], out["rows"], out["cls"], out["kin"], T, s)
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            B.mlpf_candidates(batch, cls, kin, out["offsets"], out["rows"], out["cls"], out["kin"], T, s)
+    for rep, p_zero in enumerate([0.5, 0.0, 0.9, 1.0]):
+        c = np.where(rng.random(T) < p_zero, 0, rng.integers(1, 6, T)).astype(np.int32)
+        cls.copy_(torch.as_tensor(c))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = B.candidates_to_host(out)
+        _compare(got, O.candidates(c, kin.cpu().numpy(), rs))
