@@ -32,7 +32,9 @@ Readings where the paper is silent (each is listed with its reason in the design
     bidirectional, only the event's own valid elements are keys, no dropout;
   * embedding: Linear(F, d) -> GELU -> Linear(d, d), one network for all element types;
   * heads (cls 6, p_T' 1, eta 1, phi 2, E' 1): Linear(d, d) -> GELU -> Linear(d, width);
-  * class 0 means "no particle"; argmax ties go to the lowest index.
+  * class 0 means "no particle"; argmax ties go to the lowest index. With cfg.decision = 'binary'
+    output 0 is read as the paper's binary score and 1..5 as its particle-type scores (Sec. 5.3):
+    kept when the sigmoid of output 0 exceeds 0.5, typed by the largest of 1..5.
 
 Every function works in float64 on one event at a time; events never interact.
 """
@@ -123,6 +125,15 @@ def argmax_lowest(logits: np.ndarray) -> np.ndarray:
     return np.argmax(logits, axis=-1).astype(np.int32)
 
 
+def decide_binary(logits: np.ndarray) -> np.ndarray:
+    """The paper's inference rule (Sec. 5.3) with output 0 a binary "is a particle" logit and
+    outputs 1..5 the particle-type logits: keep the element when sigmoid(logit_0) > 0.5, and give it
+    the type of the largest probability (softmax is monotone, so the largest logit); 0 otherwise."""
+    logits = np.asarray(logits, dtype=np.float64)
+    keep = 1.0 / (1.0 + np.exp(-logits[:, 0])) > 0.5
+    return np.where(keep, 1 + argmax_lowest(logits[:, 1:]), 0).astype(np.int32)
+
+
 def _as64(w: Mapping[str, np.ndarray]) -> Dict[str, np.ndarray]:
     return {k: np.asarray(v, dtype=np.float64) for k, v in w.items()}
 
@@ -159,7 +170,9 @@ def forward(x: np.ndarray, weights: Mapping[str, np.ndarray], cfg) -> Dict[str, 
         raise ValueError(f"unknown topology {cfg.topology!r}")
     logits = head(h_cls, w, "cls", act)
     reg = np.concatenate([head(h_reg, w, name, act) for name, _ in HEAD_WIDTHS[1:]], axis=-1)
-    return {"logits": logits, "reg": reg, "cls": argmax_lowest(logits), "h_cls": h_cls, "h_reg": h_reg}
+    rule = getattr(cfg, "decision", "argmax")
+    cls = decide_binary(logits) if rule == "binary" else argmax_lowest(logits)
+    return {"logits": logits, "reg": reg, "cls": cls, "h_cls": h_cls, "h_reg": h_reg}
 
 
 def forward_packed(packed, weights, cfg) -> Dict[str, np.ndarray]:

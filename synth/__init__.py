@@ -45,6 +45,7 @@ class Config:
     topology: str = "serial"
     ln_eps: float = 1e-5
     activation: str = "gelu"  # or "relu" (the paper's network, Sec. 5.3)
+    decision: str = "argmax"  # or "binary": output 0 a binary score, 1..5 particle types (Sec. 5.3)
 
     @property
     def d_head(self) -> int:

@@ -313,6 +313,23 @@ def test_argmax_ties_lowest_index():
     np.testing.assert_array_equal(O.argmax_lowest(lg), [1, 0, 5])
 
 
+def test_binary_decision_rule():
+    """Sec. 5.3 inference rule on hand-worked rows: sigmoid(0) = 0.5 is not above 0.5 (dropped);
+    a kept row takes the largest particle-type logit (lowest index on ties), whatever logit 0 is;
+    and sigmoid > 0.5 is exactly logit > 0 (closed form)."""
+    lg = np.array([[0.0, 5, 1, 1, 1, 1],        # binary logit 0: sigmoid 0.5 -> dropped
+                   [1e-9, 0, 2, 2, 1, 0],       # kept, tie between types 2 and 3 -> 2
+                   [-3.0, 9, 9, 9, 9, 9],       # dropped
+                   [0.2, -1, -2, -0.5, -3, -4],  # kept, largest type logit is output 3
+                   [40.0, 1, 1, 1, 1, 1]])      # kept, all types tie -> 1
+    np.testing.assert_array_equal(O.decide_binary(lg), [0, 2, 0, 3, 1])
+    z = np.random.default_rng(3).standard_normal((1000, 6)) * 3
+    z[:, 0] = np.where(np.abs(z[:, 0]) < 1e-12, 1.0, z[:, 0])
+    keep = O.decide_binary(z) != 0
+    np.testing.assert_array_equal(keep, z[:, 0] > 0)
+    np.testing.assert_array_equal(O.decide_binary(z)[keep], 1 + np.argmax(z[keep, 1:], axis=1))
+
+
 def test_decode_inverts_eq2():
     rng = np.random.default_rng(16)
     prim = np.exp(rng.standard_normal((50, 2)))
