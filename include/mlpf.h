@@ -68,6 +68,11 @@ typedef enum {
 
 /* The hidden-layer activation: the exact (erf) GELU, or ReLU as in the paper's network (Sec. 5.3). */
 typedef enum { MLPF_ACT_GELU = 0, MLPF_ACT_RELU = 1 } mlpf_activation_t;
+/* The class rule (Sec. 5.3). ARGMAX: cls = argmax of the six logits, class 0 = no particle.
+ * BINARY: output 0 is a binary "is a particle" logit and outputs 1..5 the particle-type logits;
+ * cls = 0 unless sigmoid(output 0) > 0.5 (output 0 > 0), else 1 + argmax of outputs 1..5. Ties go
+ * to the lowest index in both. */
+typedef enum { MLPF_DECIDE_ARGMAX = 0, MLPF_DECIDE_BINARY = 1 } mlpf_decision_t;
 
 typedef struct {
   int32_t n_features; /* F: features per element, 1..32 */
@@ -78,6 +83,7 @@ typedef struct {
   int32_t topology;   /* mlpf_topology_t */
   float ln_eps;       /* LayerNorm epsilon (> 0) */
   int32_t activation; /* mlpf_activation_t: after every hidden linear layer (embedding, FFN, heads) */
+  int32_t decision;   /* mlpf_decision_t: how cls is taken from the six classification outputs */
 } mlpf_config_t;
 
 typedef struct mlpf_model_s* mlpf_model_t;

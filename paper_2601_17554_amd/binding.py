@@ -34,7 +34,8 @@ class _Config(ctypes.Structure):
     _fields_ = [("n_features", ctypes.c_int32), ("d_model", ctypes.c_int32),
                 ("n_heads", ctypes.c_int32), ("d_ff", ctypes.c_int32),
                 ("n_layers", ctypes.c_int32), ("topology", ctypes.c_int32),
-                ("ln_eps", ctypes.c_float), ("activation", ctypes.c_int32)]
+                ("ln_eps", ctypes.c_float), ("activation", ctypes.c_int32),
+                ("decision", ctypes.c_int32)]
 
 
 class _Batch(ctypes.Structure):
@@ -100,6 +101,7 @@ def exported_symbols() -> Sequence[str]:
 
 
 ACTIVATIONS = {"gelu": 0, "relu": 1}
+DECISIONS = {"argmax": 0, "binary": 1}
 PROF_CLASSES = ("embed", "qkv", "attention", "outproj", "ffn1", "ffn2", "heads", "worklist")
 OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1", "attention", "ffn",
        "heads")
@@ -134,7 +136,8 @@ def make_config(cfg) -> _Config:
     """From any object with the config attributes (n_features, d_model, ...)."""
     return _Config(cfg.n_features, cfg.d_model, cfg.n_heads, cfg.d_ff, cfg.n_layers,
                    TOPOLOGIES[cfg.topology], cfg.ln_eps,
-                   ACTIVATIONS[getattr(cfg, "activation", "gelu")])
+                   ACTIVATIONS[getattr(cfg, "activation", "gelu")],
+                   DECISIONS[getattr(cfg, "decision", "argmax")])
 
 
 def flatten_weights(weights: Mapping[str, np.ndarray], cfg) -> np.ndarray:

@@ -173,6 +173,8 @@ mlpf_status_t check_config(const mlpf_config_t* c) {
     return fail(MLPF_ERR_INVALID_ARG, "ln_eps must be positive");
   if (c->activation != MLPF_ACT_GELU && c->activation != MLPF_ACT_RELU)
     return fail(MLPF_ERR_INVALID_ARG, "unknown activation %d", c->activation);
+  if (c->decision != MLPF_DECIDE_ARGMAX && c->decision != MLPF_DECIDE_BINARY)
+    return fail(MLPF_ERR_INVALID_ARG, "unknown decision %d", c->decision);
   return MLPF_OK;
 }
 
@@ -634,6 +636,7 @@ mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, 
     if ((st = run_gemm(cx, MLPF_OP_HEADS1, m->hbytes == 2 ? A_PLAIN : A_F32, E_GELU, a))) return st;
   }
   Heads2Args p;
+  p.binary = m->cfg.decision == MLPF_DECIDE_BINARY;
   p.uh = cx.p(cx.w.u);
   p.d = d;
   p.rows = T;

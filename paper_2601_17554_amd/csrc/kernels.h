@@ -153,6 +153,7 @@ struct Heads2Args {
   int32_t* cls = nullptr;
   const float* prim = nullptr;
   float* decoded = nullptr;
+  int binary = 0;  // class rule: 0 argmax of six (class 0 = none), 1 binary logit > 0 then PID argmax
 };
 hipError_t launch_heads2(Prec prec, const Heads2Args& args, hipStream_t stream);
 // From the E_HEADS partial outputs (uh = hout [rows][11] FP32): adds b2, writes logits, reg,

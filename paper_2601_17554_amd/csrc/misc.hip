@@ -88,6 +88,26 @@ hipError_t launch_worklist(const WorklistArgs& p, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// The class of a row from its six classification outputs (Sec. 5.3 inference rule). binary = 0:
+// argmax of the six logits, class 0 = no particle, the lowest index on exact ties. binary = 1:
+// output 0 is the binary "is a particle" logit, kept when sigmoid > 0.5, i.e. logit > 0; the class
+// is then 1 + the argmax of the five particle-type logits (lowest index on ties), else 0.
+__device__ __forceinline__ int decide_class(const float (&acc)[11], int binary) {
+  if (binary) {
+    if (!(acc[0] > 0.f)) return 0;
+    int best = 1;
+#pragma unroll
+    for (int c = 2; c < 6; ++c)
+      if (acc[c] > acc[best]) best = c;
+    return best;
+  }
+  int best = 0;
+#pragma unroll
+  for (int c = 1; c < 6; ++c)
+    if (acc[c] > acc[best]) best = c;
+  return best;
+}
+
 // Second layer of the five heads (block diagonal [5d] -> 11), argmax, decode. One wave per row:
 // lanes read the row's hidden activations coalesced, each keeps 11 partial dot products, and the
 // wave reduces them.
@@ -117,10 +137,7 @@ __global__ __launch_bounds__(256) void heads2_kernel(const Heads2Args p) {
 #pragma unroll
   for (int c = 0; c < 11; ++c) acc[c] = wave_sum(acc[c]) + p.b2[c];
   if (lane == 0) {
-    int best = 0;
-#pragma unroll
-    for (int c = 1; c < 6; ++c)
-      if (acc[c] > acc[best]) best = c;
+    const int best = decide_class(acc, p.binary);
     float* lg = p.logits + (int64_t)row * 6;
 #pragma unroll
     for (int c = 0; c < 6; ++c) lg[c] = acc[c];
@@ -159,10 +176,7 @@ __global__ __launch_bounds__(256) void heads_finish_kernel(const Heads2Args p) {
   float acc[11];
 #pragma unroll
   for (int c = 0; c < 11; ++c) acc[c] = u[c] + p.b2[c];
-  int best = 0;
-#pragma unroll
-  for (int c = 1; c < 6; ++c)
-    if (acc[c] > acc[best]) best = c;
+  const int best = decide_class(acc, p.binary);
   float* lg = p.logits + (int64_t)row * 6;
 #pragma unroll
   for (int c = 0; c < 6; ++c) lg[c] = acc[c];

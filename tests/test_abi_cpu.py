@@ -42,6 +42,11 @@ def test_sizes_and_validation_without_gpu():
     h0 = ctypes.c_void_p()
     st = lib.mlpf_model_create(ctypes.byref(act), 0, None, 0, None, None, 0, None, ctypes.byref(h0))
     assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG" and b"activation" in lib.mlpf_last_error()
+    dec = B.make_config(dataclasses.replace(synth.FULL, decision="binary"))
+    assert dec.decision == 1
+    dec.decision = -2
+    st = lib.mlpf_model_create(ctypes.byref(dec), 0, None, 0, None, None, 0, None, ctypes.byref(h0))
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG" and b"decision" in lib.mlpf_last_error()
     bad = B.make_config(synth.Config(d_model=96, n_heads=3))
     assert lib.mlpf_weights_bytes(ctypes.byref(bad), 0) == 0
     h = ctypes.c_void_p()

@@ -349,6 +349,45 @@ def test_relu_activation(B, prec, cfg):
                     np.testing.assert_array_equal(got[k][r], other[k][r], err_msg=f"ffn {variant} {k}")
 
 
+@pytest.mark.parametrize("prec,cfg", [("fp32", synth.SMALL), ("bf16", synth.FULL)], ids=["fp32-small", "bf16-full"])
+def test_binary_decision(B, prec, cfg):
+    """The paper's class rule (binary score > 0.5, then the particle-type argmax) against the
+    oracle's: equal classes on every element whose decision is not a near-tie (binary logit or the
+    top-2 type logits within twice the logit tolerance), the logits within tolerance; in BF16 both
+    head paths (fused and two-layer) apply the rule."""
+    import dataclasses
+    cfg = dataclasses.replace(cfg, decision="binary")
+    w = synth.make_weights(cfg, 32, sharpen=2.0)
+    evs = [synth.make_event(5300 + i, n) for i, n in enumerate([150, 1, 90])]
+    lg = np.concatenate([O.forward(e.x, w, cfg)["logits"] for e in evs])
+    w["heads.cls.b2"] = w["heads.cls.b2"].copy()
+    w["heads.cls.b2"][0] -= np.float32(np.median(lg[:, 0]))  # about half the elements kept
+    m = B.Model(cfg, w, prec)
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=12)
+    paths = [None, 0] if prec == "bf16" else [None]
+    for heads in paths:
+        if heads is not None:
+            m.tune_set("heads", heads)
+        got = run_gpu(m, pk)
+        kept = total = checked = 0
+        for e, ev in enumerate(evs):
+            r = pk.event_rows(e)
+            ref = O.forward(ev.x, w, cfg)
+            g = {k: v[r.start:r.start + ev.n] for k, v in got.items()}
+            scale = np.abs(ref["logits"]).max()
+            assert np.abs(g["logits"] - ref["logits"]).max() <= TOL[prec] * scale
+            srt = np.sort(ref["logits"][:, 1:], axis=1)
+            clear = (np.abs(ref["logits"][:, 0]) > 2 * TOL[prec] * scale) & (
+                (ref["logits"][:, 0] <= 0) | (srt[:, -1] - srt[:, -2] > 2 * TOL[prec] * scale))
+            np.testing.assert_array_equal(g["cls"][clear], ref["cls"][clear])
+            assert set(np.unique(g["cls"])) <= set(range(6))
+            kept += int((ref["cls"] != 0).sum())
+            total += ev.n
+            checked += int(clear.sum())
+        print(f"binary rule {prec} heads={heads}: {kept} of {total} kept by the oracle, {checked} clear")
+        assert 0.2 * total < kept < 0.8 * total and checked > total // 4
+
+
 @pytest.mark.parametrize("cfg", [synth.FULL, synth.PAPER], ids=["d256", "paper_parallel2"])
 def test_fused_heads(B, cfg):
     """The head GEMM with the second head layer in its epilogue (BF16, d_model 256) against the
