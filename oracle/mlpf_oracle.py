@@ -30,7 +30,8 @@ Readings where the paper is silent (each is listed with its reason in the design
     variance; affine gamma/beta;
   * attention: Q/K/V/O biases, contiguous head split (head j owns columns j*d_h..(j+1)*d_h-1),
     bidirectional, only the event's own valid elements are keys, no dropout;
-  * embedding: Linear(F, d) -> GELU -> Linear(d, d), one network for all element types;
+  * embedding: Linear(F, d) -> GELU -> Linear(d, d), one network for all element types; with
+    cfg.embed_per_type, type-0 elements (tracks) and the others use separate networks (Sec. 5.3);
   * heads (cls 6, p_T' 1, eta 1, phi 2, E' 1): Linear(d, d) -> GELU -> Linear(d, width);
   * class 0 means "no particle"; argmax ties go to the lowest index. With cfg.decision = 'binary'
     output 0 is read as the paper's binary score and 1..5 as its particle-type scores (Sec. 5.3):
@@ -114,6 +115,16 @@ def embed(x: np.ndarray, w: Mapping[str, np.ndarray], act=gelu) -> np.ndarray:
     return act(x @ w["embed.W1"] + w["embed.b1"]) @ w["embed.W2"] + w["embed.b2"]
 
 
+def embed_per_type(x: np.ndarray, w: Mapping[str, np.ndarray], act=gelu) -> np.ndarray:
+    """Separate embeddings for tracks and the other elements (Sec. 5.3): a row whose element type
+    is 0 (feature 0, the one-hot of type 0, is set) goes through the 'embed' network, any other row
+    through the 'embed_cl' network of the same shape."""
+    track = np.asarray(x)[:, 0] > 0.5
+    h_t = act(x @ w["embed.W1"] + w["embed.b1"]) @ w["embed.W2"] + w["embed.b2"]
+    h_c = act(x @ w["embed_cl.W1"] + w["embed_cl.b1"]) @ w["embed_cl.W2"] + w["embed_cl.b2"]
+    return np.where(track[:, None], h_t, h_c)
+
+
 def head(h: np.ndarray, w: Mapping[str, np.ndarray], name: str, act=gelu) -> np.ndarray:
     """Two-layer FFN head: Linear(d, d) -> activation -> Linear(d, width)."""
     p = f"heads.{name}."
@@ -152,7 +163,7 @@ def forward(x: np.ndarray, weights: Mapping[str, np.ndarray], cfg) -> Dict[str, 
     x = np.asarray(x, dtype=np.float64)
     n_layers, n_heads, eps = cfg.n_layers, cfg.n_heads, cfg.ln_eps
     act = ACTIVATIONS[getattr(cfg, "activation", "gelu")]
-    h0 = embed(x, w, act)
+    h0 = embed_per_type(x, w, act) if getattr(cfg, "embed_per_type", False) else embed(x, w, act)
     if cfg.topology == "serial":
         h = h0
         for layer in range(n_layers):

@@ -46,6 +46,7 @@ class Config:
     ln_eps: float = 1e-5
     activation: str = "gelu"  # or "relu" (the paper's network, Sec. 5.3)
     decision: str = "argmax"  # or "binary": output 0 a binary score, 1..5 particle types (Sec. 5.3)
+    embed_per_type: bool = False  # tracks (type 0) and other elements embedded separately (Sec. 5.3)
 
     @property
     def d_head(self) -> int:
@@ -64,6 +65,9 @@ def param_shapes(cfg: Config) -> List[Tuple[str, Tuple[int, ...]]]:
     out: List[Tuple[str, Tuple[int, ...]]] = [
         ("embed.W1", (f, d)), ("embed.b1", (d,)), ("embed.W2", (d, d)), ("embed.b2", (d,)),
     ]
+    if cfg.embed_per_type:
+        out += [("embed_cl.W1", (f, d)), ("embed_cl.b1", (d,)), ("embed_cl.W2", (d, d)),
+                ("embed_cl.b2", (d,))]
     for layer in range(cfg.n_layers):
         p = f"layers.{layer}."
         out += [

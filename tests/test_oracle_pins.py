@@ -313,6 +313,27 @@ def test_argmax_ties_lowest_index():
     np.testing.assert_array_equal(O.argmax_lowest(lg), [1, 0, 5])
 
 
+def test_embed_per_type():
+    """Separate track / other-element embeddings (Sec. 5.3): each row equals the network of its
+    type run alone, and with both networks given the same weights the result is the single
+    embedding (closed form)."""
+    cfg = dataclasses.replace(synth.SMALL, embed_per_type=True)
+    w = O._as64(synth.make_weights(cfg, seed=19))
+    x = synth.make_features(np.random.default_rng(4), 40).astype(np.float64)
+    h = O.embed_per_type(x, w)
+    track = x[:, 0] > 0.5
+    assert 0 < track.sum() < len(x)
+    alt = {k.replace("embed_cl.", "embed."): v for k, v in w.items() if k.startswith("embed_cl.")}
+    np.testing.assert_allclose(h[track], O.embed(x[track], w), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(h[~track], O.embed(x[~track], alt), rtol=0, atol=1e-14)
+    same = dict(w)
+    for k in ("W1", "b1", "W2", "b2"):
+        same["embed_cl." + k] = w["embed." + k]
+    np.testing.assert_allclose(O.embed_per_type(x, same), O.embed(x, w), rtol=0, atol=1e-14)
+    out = O.forward(x, synth.make_weights(cfg, seed=19), cfg)
+    assert out["logits"].shape == (40, 6)
+
+
 def test_binary_decision_rule():
     """Sec. 5.3 inference rule on hand-worked rows: sigmoid(0) = 0.5 is not above 0.5 (dropped);
     a kept row takes the largest particle-type logit (lowest index on ties), whatever logit 0 is;
