@@ -84,6 +84,10 @@ typedef struct {
   float ln_eps;       /* LayerNorm epsilon (> 0) */
   int32_t activation; /* mlpf_activation_t: after every hidden linear layer (embedding, FFN, heads) */
   int32_t decision;   /* mlpf_decision_t: how cls is taken from the six classification outputs */
+  int32_t embed_per_type; /* 0: one embedding network; 1: tracks (feature 0 > 0.5, the one-hot of
+                           * element type 0) use the embedding network, every other element a
+                           * second one of the same shape (the paper's separate track and cluster
+                           * embeddings, Sec. 5.3) */
 } mlpf_config_t;
 
 typedef struct mlpf_model_s* mlpf_model_t;
@@ -107,6 +111,7 @@ size_t mlpf_weights_bytes(const mlpf_config_t* cfg, mlpf_precision_t precision);
 /* Number of FP32 values of the host master weight blob for cfg. The blob is the concatenation,
  * in this order, of row-major arrays with Linear weights stored [in][out] (y = x W + b):
  *   embed: W1[F][d], b1[d], W2[d][d], b2[d]
+ *   only with embed_per_type: the second (non-track) embedding, W1[F][d], b1[d], W2[d][d], b2[d]
  *   for each layer: ln1_gamma[d], ln1_beta[d], W_qkv[d][3d], b_qkv[3d], W_o[d][d], b_o[d],
  *                   ln2_gamma[d], ln2_beta[d], W_1[d][d_ff], b_1[d_ff], W_2[d_ff][d], b_2[d]
  *   heads cls, pt, eta, phi, e (widths 6, 1, 1, 2, 1): W1[d][d], b1[d], W2[d][w], b2[w]

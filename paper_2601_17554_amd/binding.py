@@ -35,7 +35,7 @@ class _Config(ctypes.Structure):
                 ("n_heads", ctypes.c_int32), ("d_ff", ctypes.c_int32),
                 ("n_layers", ctypes.c_int32), ("topology", ctypes.c_int32),
                 ("ln_eps", ctypes.c_float), ("activation", ctypes.c_int32),
-                ("decision", ctypes.c_int32)]
+                ("decision", ctypes.c_int32), ("embed_per_type", ctypes.c_int32)]
 
 
 class _Batch(ctypes.Structure):
@@ -137,12 +137,15 @@ def make_config(cfg) -> _Config:
     return _Config(cfg.n_features, cfg.d_model, cfg.n_heads, cfg.d_ff, cfg.n_layers,
                    TOPOLOGIES[cfg.topology], cfg.ln_eps,
                    ACTIVATIONS[getattr(cfg, "activation", "gelu")],
-                   DECISIONS[getattr(cfg, "decision", "argmax")])
+                   DECISIONS[getattr(cfg, "decision", "argmax")],
+                   1 if getattr(cfg, "embed_per_type", False) else 0)
 
 
 def flatten_weights(weights: Mapping[str, np.ndarray], cfg) -> np.ndarray:
     """The master FP32 blob in the library's documented order (include/mlpf.h)."""
     names = ["embed.W1", "embed.b1", "embed.W2", "embed.b2"]
+    if getattr(cfg, "embed_per_type", False):
+        names += ["embed_cl.W1", "embed_cl.b1", "embed_cl.W2", "embed_cl.b2"]
     for layer in range(cfg.n_layers):
         names += [f"layers.{layer}.{s}" for s in
                   ("ln1.gamma", "ln1.beta", "W_qkv", "b_qkv", "W_o", "b_o",

@@ -67,6 +67,7 @@ struct Layer {
 // Byte offsets of every packed tensor inside the device weight buffer.
 struct WeightPlan {
   size_t e_w1, e_b1, e_w2, e_b2;
+  size_t c_w1 = 0, c_b1 = 0, c_w2 = 0, c_b2 = 0;  // second (non-track) embedding, embed_per_type
   bool ffn_fused = false;  // the fused BF16 FFN kernel applies (its weight images are packed)
   bool heads_fused = false;  // the head GEMM can take the second head layer into its epilogue
   std::vector<Layer> layers;
@@ -113,6 +114,12 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
   w.e_b1 = take(d * 4);
   w.e_w2 = take(d * d * eb);
   w.e_b2 = take(d * 4);
+  if (c.embed_per_type) {
+    w.c_w1 = take(d * kEmbedKp * eb);
+    w.c_b1 = take(d * 4);
+    w.c_w2 = take(d * d * eb);
+    w.c_b2 = take(d * 4);
+  }
   w.layers.resize(c.n_layers);
   w.ffn_fused = prec == MLPF_BF16 && ffn_fused_supported(c.d_model, c.d_ff);
   w.heads_fused = prec != MLPF_FP32 && c.d_model == 256;
@@ -144,7 +151,7 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
 
 size_t master_count(const mlpf_config_t& c) {
   const size_t d = c.d_model, f = c.n_features, ff = c.d_ff;
-  size_t n = f * d + d + d * d + d;
+  size_t n = (c.embed_per_type ? 2 : 1) * (f * d + d + d * d + d);
   n += (size_t)c.n_layers * (2 * d + 3 * d * d + 3 * d + d * d + d + 2 * d + d * ff + ff + ff * d + d);
   n += 5 * (d * d + d) + d * 11 + 11;
   return n;
@@ -175,6 +182,8 @@ mlpf_status_t check_config(const mlpf_config_t* c) {
     return fail(MLPF_ERR_INVALID_ARG, "unknown activation %d", c->activation);
   if (c->decision != MLPF_DECIDE_ARGMAX && c->decision != MLPF_DECIDE_BINARY)
     return fail(MLPF_ERR_INVALID_ARG, "unknown decision %d", c->decision);
+  if (c->embed_per_type != 0 && c->embed_per_type != 1)
+    return fail(MLPF_ERR_INVALID_ARG, "embed_per_type must be 0 or 1");
   return MLPF_OK;
 }
 
@@ -337,11 +346,11 @@ mlpf_status_t run_layernorm(const Ctx& cx, const void* h, size_t g_off, size_t b
   return MLPF_OK;
 }
 
-mlpf_status_t do_embed(const Ctx& cx, const float* x, void* h) {
+// One embedding network (W1, b1, W2, b2 at the given plan offsets) over every row, into out.
+mlpf_status_t embed_net(const Ctx& cx, const float* x, void* out, size_t w1, size_t b1, size_t w2,
+                        size_t b2) {
   const mlpf_model_s* m = cx.m;
-  ProfScope prof(cx.m, MLPF_PROF_EMBED, cx.s);
   const int T = cx.b->total_rows, d = m->cfg.d_model;
-  if (T == 0) return MLPF_OK;
   GemmArgs a;
   a.a = x;
   a.lda = m->cfg.n_features;
@@ -349,8 +358,8 @@ mlpf_status_t do_embed(const Ctx& cx, const float* x, void* h) {
   a.N = d;
   a.K = m->cfg.n_features;
   a.Kp = kEmbedKp;
-  a.wt = m->at(m->plan.e_w1);
-  a.bias = m->atf(m->plan.e_b1);
+  a.wt = m->at(w1);
+  a.bias = m->atf(b1);
   a.out = cx.p(cx.w.u);
   a.ldo = d;
   mlpf_status_t st = run_gemm(cx, MLPF_OP_EMBED1, A_SCALAR, E_GELU, a);
@@ -362,11 +371,29 @@ mlpf_status_t do_embed(const Ctx& cx, const float* x, void* h) {
   b.N = d;
   b.K = d;
   b.Kp = d;
-  b.wt = m->at(m->plan.e_w2);
-  b.bias = m->atf(m->plan.e_b2);
-  b.out = h;
+  b.wt = m->at(w2);
+  b.bias = m->atf(b2);
+  b.out = out;
   b.ldo = d;
   return run_gemm(cx, MLPF_OP_EMBED2, A_PLAIN, m->hbytes == 2 ? E_BIAS_B : E_BIAS, b);
+}
+
+// The embedding (Sec. 5.3). embed_per_type: the track network into h, the other network into the
+// LN buffer y (free at this point, rows of the same type and width), then the non-track rows of h
+// are replaced from y.
+mlpf_status_t do_embed(const Ctx& cx, const float* x, void* h) {
+  const mlpf_model_s* m = cx.m;
+  ProfScope prof(cx.m, MLPF_PROF_EMBED, cx.s);
+  const int T = cx.b->total_rows, d = m->cfg.d_model;
+  if (T == 0) return MLPF_OK;
+  const WeightPlan& P = m->plan;
+  mlpf_status_t st = embed_net(cx, x, h, P.e_w1, P.e_b1, P.e_w2, P.e_b2);
+  if (st || !m->cfg.embed_per_type) return st;
+  void* y = cx.p(cx.w.y);
+  if ((st = embed_net(cx, x, y, P.c_w1, P.c_b1, P.c_w2, P.c_b2))) return st;
+  HIP_TRY(launch_select_rows(h, y, x, m->cfg.n_features, T, cx.n_rows, d * m->hbytes, cx.s),
+          "embedding select");
+  return MLPF_OK;
 }
 
 mlpf_status_t do_worklist(Ctx& cx) {
@@ -752,6 +779,12 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
   put_f32(plan.e_b1, d);
   put_wt(plan.e_w2, d, d, d);
   put_f32(plan.e_b2, d);
+  if (c.embed_per_type) {
+    put_wt(plan.c_w1, f, d, kEmbedKp);
+    put_f32(plan.c_b1, d);
+    put_wt(plan.c_w2, d, d, d);
+    put_f32(plan.c_b2, d);
+  }
   for (int l = 0; l < c.n_layers; ++l) {
     const Layer L = plan.layers[l];
     put_f32(L.ln1g, d);

@@ -179,6 +179,11 @@ hipError_t launch_layernorm(Prec prec, const LayerNormArgs& args, hipStream_t st
 hipError_t launch_scale(Prec prec, void* dst, const void* src, int64_t n, float scale,
                         hipStream_t stream);
 
+// Rows r < min(rows, *m_dev) whose x[r][0] is not above 0.5 get row r of alt (row_bytes each, a
+// multiple of 16): the non-track rows of a per-type embedding.
+hipError_t launch_select_rows(void* h, const void* alt, const float* x, int n_features, int rows,
+                              const int32_t* m_dev, int row_bytes, hipStream_t stream);
+
 // Copies n 4-byte words (duplicates the embedding into the second stack of PARALLEL2).
 hipError_t launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t stream);
 

@@ -324,6 +324,29 @@ __global__ __launch_bounds__(256) void copy_f32_kernel(float* dst, const float* 
     dst[i] = src[i];
 }
 
+// One wave per row: 16-byte chunks of alt's row replace h's when the row is not a track.
+__global__ __launch_bounds__(256) void select_rows_kernel(char* h, const char* alt, const float* x,
+                                                          int F, int rows, const int32_t* m_dev,
+                                                          int row_bytes) {
+  int M = rows;
+  if (m_dev) M = min(M, max(*m_dev, 0));
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= M) return;
+  if (x[(int64_t)row * F] > 0.5f) return;  // a track keeps the track embedding
+  const int64_t base = (int64_t)row * row_bytes;
+  for (int o = (threadIdx.x & 63) * 16; o < row_bytes; o += 64 * 16)
+    *(u32x4*)(h + base + o) = *(const u32x4*)(alt + base + o);
+}
+
+hipError_t launch_select_rows(void* h, const void* alt, const float* x, int n_features, int rows,
+                              const int32_t* m_dev, int row_bytes, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (row_bytes % 16 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(select_rows_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, (char*)h,
+                     (const char*)alt, x, n_features, rows, m_dev, row_bytes);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t grid = (n / 4 + 255) / 256;

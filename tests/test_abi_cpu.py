@@ -47,6 +47,9 @@ def test_sizes_and_validation_without_gpu():
     dec.decision = -2
     st = lib.mlpf_model_create(ctypes.byref(dec), 0, None, 0, None, None, 0, None, ctypes.byref(h0))
     assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG" and b"decision" in lib.mlpf_last_error()
+    pt = B.make_config(dataclasses.replace(synth.FULL, embed_per_type=True))
+    assert lib.mlpf_weights_count(ctypes.byref(pt)) == synth.param_count(dataclasses.replace(synth.FULL, embed_per_type=True))
+    assert lib.mlpf_weights_count(ctypes.byref(pt)) > synth.param_count(synth.FULL)
     bad = B.make_config(synth.Config(d_model=96, n_heads=3))
     assert lib.mlpf_weights_bytes(ctypes.byref(bad), 0) == 0
     h = ctypes.c_void_p()

@@ -349,6 +349,20 @@ def test_relu_activation(B, prec, cfg):
                     np.testing.assert_array_equal(got[k][r], other[k][r], err_msg=f"ffn {variant} {k}")
 
 
+@pytest.mark.parametrize("prec,cfg", [("fp32", synth.SMALL), ("bf16", synth.FULL), ("bf16", synth.PAPER)],
+                         ids=["fp32-small", "bf16-full", "bf16-paper_parallel2"])
+def test_embed_per_type(B, prec, cfg):
+    """Separate track / other-element embeddings (the paper's, Sec. 5.3) against the oracle on
+    ragged events with garbage padding (tracks are ~8% of the elements)."""
+    import dataclasses
+    cfg = dataclasses.replace(cfg, embed_per_type=True)
+    w, m = _model(B, cfg, 33, prec, sharpen=2.0)
+    evs = [synth.make_event(5400 + i, n) for i, n in enumerate([180, 1, 65, 250])]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=13)
+    assert 0 < (pk.x[:, 0] > 0.5).sum() < pk.total_rows
+    _check_all(run_gpu(m, pk), pk, w, cfg, TOL[prec], f"per-type embedding {prec}")
+
+
 @pytest.mark.parametrize("prec,cfg", [("fp32", synth.SMALL), ("bf16", synth.FULL)], ids=["fp32-small", "bf16-full"])
 def test_binary_decision(B, prec, cfg):
     """The paper's class rule (binary score > 0.5, then the particle-type argmax) against the
