@@ -342,16 +342,18 @@ def main():
     print("bench: bf16 plain done", file=sys.stderr, flush=True)
     pl_layout = None
     if not args.no_paper_layout:
-        # The paper's own layout (two parallel 3-block encoders, 16 heads of width 16) on the same
-        # batches: twice the exponentials per score FLOP of the d_head 32 model.
+        # The paper's own network (two parallel 3-block encoders, 16 heads of width 16, ReLU,
+        # separate track embeddings, binary-score rule) on the same batches: twice the exponentials
+        # per score FLOP of the d_head 32 model.
         pargs = argparse.Namespace(**vars(args))
         pargs.steps, pargs.warmup = min(args.steps, 10), 1
-        pc = synth.PAPER
+        pc = synth.PAPER_MODEL
         pr = bench_varlen(pargs, pc, synth.make_weights(pc, 1))
         a_ms = pr["attn_ms"] / max(pr["attn_launches"], 1)
         a_fl = pr["attn_flops"] / max(pr["attn_launches"], 1)
         pl_layout = {
-            "model": "d256 h16 (d_head 16) ffn1024, two parallel stacks of 3 blocks",
+            "model": "d256 h16 (d_head 16) ffn1024, two parallel stacks of 3 blocks, ReLU, "
+                     "track/other embeddings, binary-score class rule",
             "value": round(pr["events"] / pr["wall_s"], 2), "unit": "events/s",
             "ms_per_step": round(pr["wall_s"] * 1e3 / pargs.steps, 3), "steps": pargs.steps,
             "attention_avg_launch_ms": round(a_ms, 4),

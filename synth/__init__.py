@@ -57,6 +57,10 @@ SMALL = Config(d_model=64, n_heads=4, d_ff=256, n_layers=3)
 FULL = Config(d_model=256, n_heads=8, d_ff=1024, n_layers=6)
 # The paper's own layout (Sec. 5.3): 2 parallel encoders of 3 blocks, 16 heads of width 16.
 PAPER = Config(d_model=256, n_heads=16, d_ff=1024, n_layers=6, topology="parallel2")
+# The paper's network in full (Sec. 5.3): that layout with ReLU activations, separate track and
+# other-element embeddings, and the binary-score class rule.
+PAPER_MODEL = Config(d_model=256, n_heads=16, d_ff=1024, n_layers=6, topology="parallel2",
+                     activation="relu", decision="binary", embed_per_type=True)
 
 
 def param_shapes(cfg: Config) -> List[Tuple[str, Tuple[int, ...]]]:

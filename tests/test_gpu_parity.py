@@ -6,7 +6,7 @@ import pytest
 
 import synth
 from oracle import mlpf_oracle as O
-from parity_util import TOL, check_event, run_gpu
+from parity_util import TOL, check_event, errors, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -361,6 +361,30 @@ def test_embed_per_type(B, prec, cfg):
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=13)
     assert 0 < (pk.x[:, 0] > 0.5).sum() < pk.total_rows
     _check_all(run_gpu(m, pk), pk, w, cfg, TOL[prec], f"per-type embedding {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_paper_model(B, prec):
+    """The paper's network in full (parallel encoders, d_head 16, ReLU, track/other embeddings,
+    binary-score rule) against the oracle on ragged events with garbage padding."""
+    cfg = synth.PAPER_MODEL
+    w, m = _model(B, cfg, 34, prec, sharpen=2.0)
+    evs = [synth.make_event(5500 + i, n) for i, n in enumerate([120, 1, 70])]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=14)
+    got = run_gpu(m, pk)
+    for e, ev in enumerate(evs):
+        r = pk.event_rows(e)
+        ref = oracle(ev.x, w, cfg)
+        rows = slice(r.start, r.start + ev.n)
+        g = {k: v[rows] for k, v in got.items()}
+        err = errors(g, ref)
+        bad = {k: v for k, v in err.items() if not k.startswith("diag_") and not v <= TOL[prec]}
+        assert not bad, (e, err)
+        scale = np.abs(ref["logits"]).max()
+        srt = np.sort(ref["logits"][:, 1:], axis=1)
+        clear = (np.abs(ref["logits"][:, 0]) > 2 * TOL[prec] * scale) & (
+            (ref["logits"][:, 0] <= 0) | (srt[:, -1] - srt[:, -2] > 2 * TOL[prec] * scale))
+        np.testing.assert_array_equal(g["cls"][clear], ref["cls"][clear])
 
 
 @pytest.mark.parametrize("prec,cfg", [("fp32", synth.SMALL), ("bf16", synth.FULL)], ids=["fp32-small", "bf16-full"])
