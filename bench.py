@@ -93,14 +93,15 @@ def _timed_steps(stream, steps, fn):
     return wall, np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
 
 
-def bench_varlen(args, cfg, w):
+def bench_varlen(args, cfg, w, model=None):
     """Graph-replayed varlen batches (timed region), then the same steps eagerly with the
     per-kernel HIP-event profiler (kernel durations for the roofline)."""
     import torch
     from paper_2601_17554_amd import autotune
     from paper_2601_17554_amd import binding as B
 
-    model = B.Model(cfg, w, args.precision)
+    if model is None:
+        model = B.Model(cfg, w, args.precision)
     batches = make_batches(args.batches)
     stream = torch.cuda.Stream()
     res = {}
@@ -319,6 +320,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-layout", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--serve-rates", type=int, nargs="*", default=[200, 500, 1000, 2000])
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     args = ap.parse_args()
@@ -362,6 +364,22 @@ def main():
                                         / PEAK_EXP_T_PER_S, 4),
             "tiles": pr["tiles"]}
         print(f"bench: paper layout {pl_layout['value']} events/s", file=sys.stderr, flush=True)
+    fp8 = None
+    if not args.no_fp8:
+        # BF16 with the FFN products in FP8-E4M3 (activation scales calibrated on the FP32 model
+        # over the first batch), on the same batches.
+        from paper_2601_17554_amd import binding as B
+        pk0 = make_batches(1)[0]
+        m8 = B.build_fp8_model(cfg, w, [(pk0.x, pk0.row_start, pk0.n_valid)])
+        fargs = argparse.Namespace(**vars(args))
+        fargs.steps, fargs.warmup = min(args.steps, 10), 1
+        fr = bench_varlen(fargs, cfg, w, model=m8)
+        fp8 = {"value": round(fr["events"] / fr["wall_s"], 2), "unit": "events/s",
+               "ms_per_step": round(fr["wall_s"] * 1e3 / fargs.steps, 3), "steps": fargs.steps,
+               "ffn_ms_per_step": round((fr["prof"]["ffn1"][0] + fr["prof"]["ffn2"][0]) / fargs.steps, 4),
+               "tiles": fr["tiles"]}
+        del m8
+        print(f"bench: fp8 ffn {fp8['value']} events/s", file=sys.stderr, flush=True)
     vr = bench_varlen(args, cfg, w)
     print(f"bench: varlen {vr['events'] / vr['wall_s']:.1f} events/s", file=sys.stderr, flush=True)
 
@@ -405,6 +423,7 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in vr["prof"].items()},
         "candidates": vr["candidates"],
         "paper_layout_bf16": pl_layout,
+        "bf16_fp8ffn": fp8,
     }
     if args.serve_rates:
         line["serving"] = bench_serving(args, cfg, w)
