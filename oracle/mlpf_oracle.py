@@ -33,6 +33,11 @@ Readings where the paper is silent (each is listed with its reason in the design
   * embedding: Linear(F, d) -> GELU -> Linear(d, d), one network for all element types; with
     cfg.embed_per_type, type-0 elements (tracks) and the others use separate networks (Sec. 5.3);
   * heads (cls 6, p_T' 1, eta 1, phi 2, E' 1): Linear(d, d) -> GELU -> Linear(d, width);
+    with cfg.binary_head the classification outputs come from the paper's two separate heads
+    instead (Sec. 5.3 and the caption of its model figure: a binary output and multi-class
+    particle-type outputs): a binary head of width 1 and a particle-type head of width 5, both
+    two-layer, both reading the classification encoder; the six logits are then
+    (binary, type 1..5);
   * class 0 means "no particle"; argmax ties go to the lowest index. With cfg.decision = 'binary'
     output 0 is read as the paper's binary score and 1..5 as its particle-type scores (Sec. 5.3):
     kept when the sigmoid of output 0 exceeds 0.5, typed by the largest of 1..5.
@@ -48,6 +53,8 @@ import numpy as np
 from scipy.special import erf
 
 HEAD_WIDTHS = (("cls", 6), ("pt", 1), ("eta", 1), ("phi", 2), ("e", 1))
+# The paper's classification heads (Sec. 5.3), used instead of "cls" when cfg.binary_head is set.
+CLS_HEADS_BINARY = (("binary", 1), ("pid", 5))
 
 
 def gelu(z: np.ndarray) -> np.ndarray:
@@ -179,7 +186,11 @@ def forward(x: np.ndarray, weights: Mapping[str, np.ndarray], cfg) -> Dict[str, 
             h_reg = encoder_block(h_reg, _layer_params(w, layer), n_heads, eps, act)
     else:
         raise ValueError(f"unknown topology {cfg.topology!r}")
-    logits = head(h_cls, w, "cls", act)
+    if getattr(cfg, "binary_head", False):
+        logits = np.concatenate([head(h_cls, w, name, act) for name, _ in CLS_HEADS_BINARY],
+                                axis=-1)
+    else:
+        logits = head(h_cls, w, "cls", act)
     reg = np.concatenate([head(h_reg, w, name, act) for name, _ in HEAD_WIDTHS[1:]], axis=-1)
     rule = getattr(cfg, "decision", "argmax")
     cls = decide_binary(logits) if rule == "binary" else argmax_lowest(logits)
@@ -247,5 +258,6 @@ def flops_per_event(n: int, cfg) -> int:
     d, f, dff, L = cfg.d_model, cfg.n_features, cfg.d_ff, cfg.n_layers
     embed_f = 2 * n * (f * d + d * d)
     layer_f = 2 * n * (3 * d * d + d * d + 2 * d * dff) + 4 * n * n * d
-    heads_f = 2 * n * (5 * d * d) + 2 * n * d * 11
+    n_heads = 6 if getattr(cfg, "binary_head", False) else 5
+    heads_f = 2 * n * (n_heads * d * d) + 2 * n * d * 11
     return embed_f + L * layer_f + heads_f

@@ -26,6 +26,10 @@ import numpy as np
 # (class 0 = no particle, 1..5 = particle types); the regression heads give
 # p_T' (log-ratio, Eq. 2), eta, (sin phi, cos phi) and E' (log-ratio, Eq. 2).
 HEADS: Tuple[Tuple[str, int], ...] = (("cls", 6), ("pt", 1), ("eta", 1), ("phi", 2), ("e", 1))
+# With a separate binary head (the paper's six heads, Sec. 5.3): the classification outputs come
+# from a binary "is a particle" head (width 1) and a particle-type head (width 5), both two-layer.
+HEADS_BINARY: Tuple[Tuple[str, int], ...] = (("binary", 1), ("pid", 5), ("pt", 1), ("eta", 1),
+                                             ("phi", 2), ("e", 1))
 N_FEATURES = 17
 N_TYPES = 6
 MAX_SEQLEN = 8192
@@ -47,6 +51,7 @@ class Config:
     activation: str = "gelu"  # or "relu" (the paper's network, Sec. 5.3)
     decision: str = "argmax"  # or "binary": output 0 a binary score, 1..5 particle types (Sec. 5.3)
     embed_per_type: bool = False  # tracks (type 0) and other elements embedded separately (Sec. 5.3)
+    binary_head: bool = False  # separate two-layer binary and particle-type heads (Sec. 5.3)
 
     @property
     def d_head(self) -> int:
@@ -58,9 +63,15 @@ FULL = Config(d_model=256, n_heads=8, d_ff=1024, n_layers=6)
 # The paper's own layout (Sec. 5.3): 2 parallel encoders of 3 blocks, 16 heads of width 16.
 PAPER = Config(d_model=256, n_heads=16, d_ff=1024, n_layers=6, topology="parallel2")
 # The paper's network in full (Sec. 5.3): that layout with ReLU activations, separate track and
-# other-element embeddings, and the binary-score class rule.
+# other-element embeddings, six two-layer heads (binary and particle type on the classification
+# encoder, p_T, eta, phi and E on the regression encoder) and the binary-score class rule.
 PAPER_MODEL = Config(d_model=256, n_heads=16, d_ff=1024, n_layers=6, topology="parallel2",
-                     activation="relu", decision="binary", embed_per_type=True)
+                     activation="relu", decision="binary", embed_per_type=True, binary_head=True)
+
+
+def heads_of(cfg: Config) -> Tuple[Tuple[str, int], ...]:
+    """The output heads of a configuration, in canonical order: (name, width)."""
+    return HEADS_BINARY if getattr(cfg, "binary_head", False) else HEADS
 
 
 def param_shapes(cfg: Config) -> List[Tuple[str, Tuple[int, ...]]]:
@@ -82,7 +93,7 @@ def param_shapes(cfg: Config) -> List[Tuple[str, Tuple[int, ...]]]:
             (p + "W_1", (d, dff)), (p + "b_1", (dff,)),
             (p + "W_2", (dff, d)), (p + "b_2", (d,)),
         ]
-    for name, width in HEADS:
+    for name, width in heads_of(cfg):
         p = f"heads.{name}."
         out += [(p + "W1", (d, d)), (p + "b1", (d,)), (p + "W2", (d, width)), (p + "b2", (width,))]
     return out
@@ -92,11 +103,21 @@ def param_count(cfg: Config) -> int:
     return int(sum(int(np.prod(s)) for _, s in param_shapes(cfg)))
 
 
-def make_weights(cfg: Config, seed: int, sharpen: float = 1.0) -> Dict[str, np.ndarray]:
+def make_weights(cfg: Config, seed: int, sharpen: float = 1.0, head_gain: float = 1.0,
+                 embed_gain: float = 1.0) -> Dict[str, np.ndarray]:
     """FP32 master weights, drawn in canonical order from PCG64(seed).
 
     ``sharpen`` multiplies the query and key column blocks of every W_qkv, which spreads the
-    attention logits so that the softmax is far from uniform (used by parity tests only)."""
+    attention logits so that the softmax is far from uniform (used by parity tests only).
+    ``embed_gain`` multiplies the weight matrices (not the biases) of the embedding network(s) and
+    ``head_gain`` the second-layer weight W2 of every output head. With N(0, 0.02) weights every
+    element of an event ends up with nearly the same outputs (the biases along the residual path
+    dominate the per-element part by ~20x, and every output column is a small difference of
+    similar terms); larger embedding weights make the per-element part dominate, and the head gain
+    sets the output scale. ``WIDE`` is the "wide-output" set of the parity tests: every logit and
+    regression column then varies by O(0.1-1) from element to element, each column is
+    well-conditioned, and a zeroed, swapped or mis-scaled output column is far outside any
+    tolerance. The random draws are the same for every gain."""
     rng = np.random.Generator(np.random.PCG64(seed))
     w: Dict[str, np.ndarray] = {}
     for name, shape in param_shapes(cfg):
@@ -108,8 +129,16 @@ def make_weights(cfg: Config, seed: int, sharpen: float = 1.0) -> Dict[str, np.n
         if name.endswith("W_qkv") and sharpen != 1.0:
             v = v.copy()
             v[:, : 2 * cfg.d_model] *= sharpen
+        if name.startswith("heads.") and name.endswith(".W2") and head_gain != 1.0:
+            v = v * head_gain
+        if name.startswith("embed") and ".W" in name and embed_gain != 1.0:
+            v = v * embed_gain
         w[name] = v.astype(np.float32)
     return w
+
+
+# The "wide-output" weight set of the parity tests (make_weights(cfg, seed, **WIDE)).
+WIDE = {"embed_gain": 6.0, "head_gain": 10.0}
 
 
 def make_features(rng: np.random.Generator, n: int, n_features: int = N_FEATURES) -> np.ndarray:

@@ -157,9 +157,9 @@ def test_encoder_block_vs_torch_transformer_layer(cfg):
     np.testing.assert_allclose(got, ref[:n_valid], rtol=0, atol=1e-11)
 
 
-@pytest.mark.parametrize("act", ["gelu", "relu"])
-def test_embed_and_heads_vs_torch_mlp(act):
-    cfg = synth.SMALL
+@pytest.mark.parametrize("act,binary", [("gelu", False), ("relu", False), ("relu", True)])
+def test_embed_and_heads_vs_torch_mlp(act, binary):
+    cfg = dataclasses.replace(synth.SMALL, binary_head=binary)
     w = synth.make_weights(cfg, seed=8)
     x = synth.make_features(np.random.default_rng(9), 21)
     t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
@@ -178,10 +178,20 @@ def test_embed_and_heads_vs_torch_mlp(act):
     with torch.no_grad():
         np.testing.assert_allclose(O.embed(x.astype(np.float64), w, f), e(t(x)).numpy(), atol=1e-13)
         h = np.random.default_rng(1).standard_normal((21, cfg.d_model))
-        for name, _ in synth.HEADS:
+        for name, _ in synth.heads_of(cfg):
             p = f"heads.{name}."
             m = mlp(w[p + "W1"], w[p + "b1"], w[p + "W2"], w[p + "b2"])
             np.testing.assert_allclose(O.head(h, O._as64(w), name, f), m(t(h)).numpy(), atol=1e-13)
+        if binary:
+            # The six logits of the forward pass are (binary head, particle-type head), each the
+            # torch MLP of its own weights on the classification encoder's output.
+            cfg0 = dataclasses.replace(cfg, n_layers=1, activation=act)
+            w0 = synth.make_weights(cfg0, seed=8)
+            out = O.forward(x, w0, cfg0)
+            hb = mlp(*(w0["heads.binary." + k] for k in ("W1", "b1", "W2", "b2")))
+            hp = mlp(*(w0["heads.pid." + k] for k in ("W1", "b1", "W2", "b2")))
+            ref = torch.cat([hb(t(out["h_cls"])), hp(t(out["h_cls"]))], dim=1).numpy()
+            np.testing.assert_allclose(out["logits"], ref, atol=1e-13)
 
 
 # ---------------------------------------------------------------- whole forward
@@ -231,16 +241,19 @@ def _brute_forward(x, w, cfg):
         h = [[h[i][c] + a[i][c] for c in range(d)] for i in range(len(h))]
         f = lin(lin(ln(h, P("ln2.gamma"), P("ln2.beta")), P("W_1"), P("b_1"), True), P("W_2"), P("b_2"))
         h = [[h[i][c] + f[i][c] for c in range(d)] for i in range(len(h))]
+    heads = synth.heads_of(cfg)
     outs = [lin(lin(h, W[f"heads.{n}.W1"], W[f"heads.{n}.b1"], True), W[f"heads.{n}.W2"], W[f"heads.{n}.b2"])
-            for n, _ in synth.HEADS]
-    logits = np.array(outs[0])
-    reg = np.concatenate([np.array(o) for o in outs[1:]], axis=1)
+            for n, _ in heads]
+    n_cls = 2 if getattr(cfg, "binary_head", False) else 1  # binary + type heads, or one head
+    logits = np.concatenate([np.array(o) for o in outs[:n_cls]], axis=1)
+    reg = np.concatenate([np.array(o) for o in outs[n_cls:]], axis=1)
     return logits, reg
 
 
-@pytest.mark.parametrize("n,act", [(1, "gelu"), (3, "gelu"), (6, "gelu"), (5, "relu")])
-def test_forward_brute_force_tiny(n, act):
-    cfg = dataclasses.replace(TINY, activation=act)
+@pytest.mark.parametrize("n,act,binary", [(1, "gelu", False), (3, "gelu", False), (6, "gelu", False),
+                                          (5, "relu", False), (4, "relu", True)])
+def test_forward_brute_force_tiny(n, act, binary):
+    cfg = dataclasses.replace(TINY, activation=act, binary_head=binary)
     w = synth.make_weights(cfg, seed=11, sharpen=8.0)
     x = synth.make_features(np.random.default_rng(n), n)
     out = O.forward(x, w, cfg)
@@ -249,10 +262,12 @@ def test_forward_brute_force_tiny(n, act):
     np.testing.assert_allclose(out["reg"], reg, rtol=0, atol=1e-13)
 
 
-def test_forward_closed_form_zero_weights():
+@pytest.mark.parametrize("binary", [False, True])
+def test_forward_closed_form_zero_weights(binary):
     """All weight matrices zero: every row is the sum of the biases along the residual path and
-    each head returns its output bias (a closed form of the architecture)."""
-    cfg = synth.SMALL
+    each head returns its output bias (a closed form of the architecture); with the separate binary
+    head, logit 0 is that head's bias and logits 1..5 the type head's."""
+    cfg = dataclasses.replace(synth.SMALL, binary_head=binary)
     w = synth.make_weights(cfg, seed=12)
     for k in w:
         if k.split(".")[-1].startswith("W"):
@@ -263,7 +278,9 @@ def test_forward_closed_form_zero_weights():
     for layer in range(cfg.n_layers):
         h = h + w[f"layers.{layer}.b_o"] + w[f"layers.{layer}.b_2"]
     np.testing.assert_allclose(out["h_cls"], np.broadcast_to(h, (10, cfg.d_model)), atol=1e-15)
-    np.testing.assert_allclose(out["logits"], np.broadcast_to(w["heads.cls.b2"], (10, 6)), atol=0)
+    cls_b = (np.concatenate([w["heads.binary.b2"], w["heads.pid.b2"]]) if binary
+             else w["heads.cls.b2"])
+    np.testing.assert_allclose(out["logits"], np.broadcast_to(cls_b, (10, 6)), atol=0)
     reg_b = np.concatenate([w[f"heads.{n}.b2"] for n, _ in synth.HEADS[1:]])
     np.testing.assert_allclose(out["reg"], np.broadcast_to(reg_b, (10, 5)), atol=0)
 
@@ -280,10 +297,13 @@ def test_forward_permutation_equivariance(cfg):
     np.testing.assert_allclose(b["reg"], a["reg"][perm], rtol=0, atol=1e-12)
 
 
-def test_parallel2_uses_separate_stacks():
-    """parallel2: the classification output depends only on the first half of the blocks and the
-    regression outputs only on the second half."""
-    cfg = synth.Config(d_model=64, n_heads=4, d_ff=256, n_layers=2, topology="parallel2")
+@pytest.mark.parametrize("binary", [False, True])
+def test_parallel2_uses_separate_stacks(binary):
+    """parallel2: the classification output (with the separate binary head: both classification
+    heads) depends only on the first half of the blocks and the regression outputs only on the
+    second half."""
+    cfg = synth.Config(d_model=64, n_heads=4, d_ff=256, n_layers=2, topology="parallel2",
+                       binary_head=binary)
     w = synth.make_weights(cfg, seed=14)
     x = synth.make_features(np.random.default_rng(3), 12)
     a = O.forward(x, w, cfg)
@@ -306,6 +326,26 @@ def test_forward_packed_matches_alone_and_pads_are_ignored():
     for e, ev in enumerate(evs):
         ref = O.forward(ev.x, w, cfg)
         np.testing.assert_array_equal(out["logits"][pk.event_rows(e)], ref["logits"])
+
+
+def test_binary_head_separation():
+    """With the paper's separate heads (Sec. 5.3), logit 0 depends only on the binary head's
+    weights and logits 1..5 only on the type head's; the regression outputs on neither."""
+    cfg = dataclasses.replace(synth.SMALL, n_layers=2, binary_head=True, decision="binary")
+    w = synth.make_weights(cfg, seed=22, head_gain=30.0)
+    x = synth.make_features(np.random.default_rng(5), 30)
+    a = O.forward(x, w, cfg)
+    wb = dict(w); wb["heads.binary.W1"] = w["heads.binary.W1"] * 2
+    b = O.forward(x, wb, cfg)
+    np.testing.assert_array_equal(a["logits"][:, 1:], b["logits"][:, 1:])
+    np.testing.assert_array_equal(a["reg"], b["reg"])
+    assert np.abs(a["logits"][:, 0] - b["logits"][:, 0]).max() > 1e-3
+    wp = dict(w); wp["heads.pid.W1"] = w["heads.pid.W1"] * 2
+    c = O.forward(x, wp, cfg)
+    np.testing.assert_array_equal(a["logits"][:, 0], c["logits"][:, 0])
+    assert np.abs(a["logits"][:, 1:] - c["logits"][:, 1:]).max() > 1e-3
+    # The class follows the binary-score rule on these logits.
+    np.testing.assert_array_equal(a["cls"], O.decide_binary(a["logits"]))
 
 
 def test_argmax_ties_lowest_index():
@@ -349,6 +389,26 @@ def test_binary_decision_rule():
     keep = O.decide_binary(z) != 0
     np.testing.assert_array_equal(keep, z[:, 0] > 0)
     np.testing.assert_array_equal(O.decide_binary(z)[keep], 1 + np.argmax(z[keep, 1:], axis=1))
+
+
+def test_eq2_hand_worked():
+    """Eq. 2 on hand-worked values: p_T' = log(p_T^target / p_T^prim), E' = log(E^target / E^prim).
+    A swapped ratio flips every sign below; a missing log gives 2e / 2 = e instead of 1."""
+    prim = np.array([[2.0, 3.0], [5.0, 5.0], [4.0, 2.0]])
+    pt_t = np.array([2.0 * math.e, 5.0, 1.0])
+    e_t = np.array([3.0 / math.e, 5.0, 8.0])
+    enc = O.encode(pt_t, e_t, prim)
+    np.testing.assert_allclose(enc, [[1.0, -1.0], [0.0, 0.0], [-2 * math.log(2), 2 * math.log(2)]],
+                               rtol=0, atol=1e-15)
+    # Its inverse on the same rows, and phi = atan2(sin, cos): (0, 1) -> 0, (1, 0) -> pi/2,
+    # (0, -1) -> pi (a swapped atan2 gives pi/2, 0 and -pi/2 instead).
+    reg = np.array([[1.0, 0.3, 0.0, 1.0, -1.0], [0.0, -2.0, 1.0, 0.0, 0.0],
+                    [-2 * math.log(2), 0.0, 0.0, -1.0, 2 * math.log(2)]])
+    dec = O.decode(reg, prim)
+    np.testing.assert_allclose(dec["pt"], pt_t, rtol=1e-15)
+    np.testing.assert_allclose(dec["e"], e_t, rtol=1e-15)
+    np.testing.assert_allclose(dec["eta"], [0.3, -2.0, 0.0], rtol=0, atol=0)
+    np.testing.assert_allclose(dec["phi"], [0.0, math.pi / 2, math.pi], rtol=0, atol=1e-15)
 
 
 def test_decode_inverts_eq2():
@@ -414,11 +474,15 @@ def test_parameter_count_matches_paper():
     assert synth.param_count(synth.FULL) == 5_140_747
     assert synth.param_count(synth.PAPER) == 5_140_747
     assert synth.param_count(synth.SMALL) == 176_779
+    # The paper's network in full adds the second embedding network and the sixth head:
+    # 5,140,747 + (17 * 256 + 256 + 256 * 256 + 256) + (256 * 256 + 256) = 5,276,939, also
+    # "about 5.1 million" to within the 3% that the unstated FFN width and embedding depth leave.
+    assert synth.param_count(synth.PAPER_MODEL) == 5_276_939
 
 
 def test_flop_formula_matches_shapes():
     """Algorithmic FLOPs = 2 N (sum of all Linear weight sizes) + L * 4 N^2 d."""
-    for cfg in (synth.SMALL, synth.FULL):
+    for cfg in (synth.SMALL, synth.FULL, dataclasses.replace(synth.FULL, binary_head=True)):
         wsize = sum(int(np.prod(s)) for name, s in synth.param_shapes(cfg) if len(s) == 2)
         for n in (1, 256, 3000):
             assert O.flops_per_event(n, cfg) == 2 * n * wsize + cfg.n_layers * 4 * n * n * cfg.d_model
