@@ -4,19 +4,24 @@
  * clusters) to per-element particle outputs (arxiv 2601.17554, Sec. 5.3).
  *
  * Model (Sec. 5.3, with the readings stated below):
- *   h0      = GELU(x W_e1 + b_e1) W_e2 + b_e2                         element embedding FFN
- *   block   : h += MHA(LN1(h));  h += GELU(LN2(h) W_1 + b_1) W_2 + b_2   pre-LN transformer block
+ *   h0      = act(x W_e1 + b_e1) W_e2 + b_e2                          element embedding FFN
+ *   block   : h += MHA(LN1(h));  h += act(LN2(h) W_1 + b_1) W_2 + b_2    pre-LN transformer block
  *   MHA     : per head, softmax(Q K^T / sqrt(d_head)) V over the event's own elements (Eq. 4)
- *   heads   : out_k = GELU(h W_k1 + b_k1) W_k2 + b_k2 for k = cls(6), pT'(1), eta(1), phi(2), E'(1)
- *   class   = argmax of the 6 logits (class 0 = no particle, lowest index wins exact ties)
+ *   heads   : out_k = act(h W_k1 + b_k1) W_k2 + b_k2, two-layer heads: either five heads
+ *             cls(6), pT'(1), eta(1), phi(2), E'(1), or the paper's six (binary_head): binary(1),
+ *             particle type(5), pT'(1), eta(1), phi(2), E'(1)
+ *   class   = from the six classification outputs by the config's decision rule (mlpf_decision_t)
  *   decode  : pT = pT_prim exp(pT'), E = E_prim exp(E') (inverse of Eq. 2), phi = atan2(sin, cos)
- * Readings where the paper is silent: exact-erf GELU after every hidden linear layer (none after
- * output layers); LayerNorm eps from the config, biased variance; no final LayerNorm; one
- * embedding network for all element types; Q/K/V/O biases; contiguous head split.
+ * act is GELU (default) or ReLU (the paper's network) after every hidden linear layer, none after
+ * output layers. GELU(z) = z (1 + erf(z / sqrt 2)) / 2 with erf evaluated by the Abramowitz-Stegun
+ * rational approximation 7.1.26 (absolute error of erf at most 1.5e-7) in FP32.
+ * Readings where the paper is silent: LayerNorm eps from the config, biased variance; no final
+ * LayerNorm; Q/K/V/O biases; contiguous head split.
  *
  * Conventions for every call:
  *   - All pointers to tensors are DEVICE pointers unless a parameter says "host". The caller owns
- *     all memory; the library never allocates device memory, never synchronises, and never frees.
+ *     all memory; the library never allocates device memory and never frees it. Only
+ *     mlpf_model_create synchronises its stream (after the weight upload); no other call does.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Work is enqueued on it
  *     in order; errors of kernels that already ran surface at the caller's next synchronisation.
  *   - Arguments are validated before anything is enqueued. On failure nothing is written and the
@@ -50,13 +55,15 @@ typedef enum {
   MLPF_ERR_INTERNAL = 5
 } mlpf_status_t;
 
-/* Arithmetic of the matrix products. Softmax statistics, LayerNorm statistics, the residual
- * stream h and all outputs are FP32 in every mode; nothing uses FP64 on the GPU. */
+/* Arithmetic of the matrix products. Softmax statistics, LayerNorm statistics, every accumulation
+ * and all outputs are FP32 in every mode; the residual stream h is FP32 in MLPF_FP32 and bf16 in
+ * the BF16 modes (see mlpf_embed); nothing uses FP64 on the GPU. */
 typedef enum {
   MLPF_FP32 = 0,        /* FP32 operands on FP32 MFMA */
   MLPF_BF16 = 1,        /* BF16 operands, FP32 accumulation */
   MLPF_BF16_FP8FFN = 2  /* as BF16, but both FFN products take FP8-E4M3 operands with
-                           per-tensor scales (weights: amax/448; activations: from act_scales) */
+                           per-tensor scales amax/448 (weights: their own amax; activations: the
+                           calibrated act_amax of mlpf_model_create) */
 } mlpf_precision_t;
 
 typedef enum {
@@ -88,21 +95,34 @@ typedef struct {
                            * element type 0) use the embedding network, every other element a
                            * second one of the same shape (the paper's separate track and cluster
                            * embeddings, Sec. 5.3) */
+  int32_t binary_head; /* 0: one classification head with six outputs; 1: the paper's two
+                        * classification heads (Sec. 5.3 and its model figure): a binary head
+                        * (one output) and a particle-type head (five outputs), each a two-layer
+                        * FFN on the classification encoder; the six logits are then
+                        * (binary, type 1..5) */
 } mlpf_config_t;
 
 typedef struct mlpf_model_s* mlpf_model_t;
 
 /* One launch processes n_events events packed row-wise. Event e owns rows
  * row_start[e] .. row_start[e+1]-1; the first n_valid[e] of them are its elements, the rest are
- * padding. Device arrays are read by the kernels; host sizes bound the launch. Out-of-range device
- * values are clamped into [0, total_rows] and to max_seqlen, so bad offsets cannot make a kernel
- * touch memory outside the caller's buffers (they give wrong, not unsafe, results). */
+ * padding. Device arrays are read by the kernels; host sizes bound the launch.
+ * Host mirrors (optional): when row_start_host is non-NULL it must hold the same values as the
+ * device row_start (and n_valid_host those of n_valid, required then whenever n_valid is
+ * non-NULL); the call validates them before anything is enqueued and returns
+ * MLPF_ERR_INVALID_ARG with nothing written for row_start_host[0] < 0, a decreasing row_start,
+ * row_start_host[n_events] > total_rows, an n_valid outside 0 .. its event's row span, or a valid
+ * count above max_seqlen. Without mirrors the device values are not checked on the host: the
+ * kernels clamp out-of-range values into [0, total_rows] and to max_seqlen, so bad offsets cannot
+ * make a kernel touch memory outside the caller's buffers (they give wrong, not unsafe, results). */
 typedef struct {
-  const int32_t* row_start; /* device, [n_events + 1], non-decreasing, last <= total_rows */
-  const int32_t* n_valid;   /* device, [n_events], or NULL: every row of an event is valid */
-  int32_t n_events;         /* >= 0 */
-  int32_t total_rows;       /* T: rows of x, h and the outputs (>= row_start[n_events]) */
-  int32_t max_seqlen;       /* upper bound of every event's valid count; 0..8192 */
+  const int32_t* row_start;      /* device, [n_events + 1], non-decreasing, last <= total_rows */
+  const int32_t* n_valid;        /* device, [n_events], or NULL: every row of an event is valid */
+  const int32_t* row_start_host; /* host mirror of row_start, or NULL */
+  const int32_t* n_valid_host;   /* host mirror of n_valid, or NULL */
+  int32_t n_events;              /* >= 0 */
+  int32_t total_rows;            /* T: rows of x, h and the outputs (>= row_start[n_events]) */
+  int32_t max_seqlen;            /* upper bound of every event's valid count; 0..8192 */
 } mlpf_batch_t;
 
 /* Bytes of the device weight buffer for (cfg, precision). */
@@ -114,25 +134,30 @@ size_t mlpf_weights_bytes(const mlpf_config_t* cfg, mlpf_precision_t precision);
  *   only with embed_per_type: the second (non-track) embedding, W1[F][d], b1[d], W2[d][d], b2[d]
  *   for each layer: ln1_gamma[d], ln1_beta[d], W_qkv[d][3d], b_qkv[3d], W_o[d][d], b_o[d],
  *                   ln2_gamma[d], ln2_beta[d], W_1[d][d_ff], b_1[d_ff], W_2[d_ff][d], b_2[d]
- *   heads cls, pt, eta, phi, e (widths 6, 1, 1, 2, 1): W1[d][d], b1[d], W2[d][w], b2[w]
+ *   heads cls, pt, eta, phi, e (widths 6, 1, 1, 2, 1), or with binary_head the six heads
+ *   binary, pid, pt, eta, phi, e (widths 1, 5, 1, 1, 2, 1): W1[d][d], b1[d], W2[d][w], b2[w]
  * W_qkv columns are [Q | K | V], each split into contiguous head slices of d/n_heads. */
 size_t mlpf_weights_count(const mlpf_config_t* cfg);
 
 /* Creates a model handle. Packs `host_weights` (host, n_floats FP32 values, order above) into the
  * caller's device buffer `dev_weights` (dev_bytes >= mlpf_weights_bytes) with a copy enqueued on
- * `stream`; host_weights may be freed when the call returns. act_scales (host, or NULL) is needed
- * only for MLPF_BF16_FP8FFN: 2 floats per layer, the per-tensor scales of the FFN1 input (the LN2
- * output) and of the FFN2 input (the GELU output), each amax/448. The handle borrows dev_weights
- * (which must outlive it) and holds a small host struct. */
+ * `stream`, and synchronises `stream` once the copy is done; host_weights may be freed when the
+ * call returns. act_amax (host, or NULL) is needed only for MLPF_BF16_FP8FFN: 2 floats per layer,
+ * the calibrated max |value| of the FFN1 input (the LN2 output) and of the FFN2 input (the
+ * activation output) of each block (as accumulated by mlpf_calibrate_fp8); the library takes each
+ * per-tensor scale as amax / 448 (1 for an amax of 0). The handle borrows dev_weights (which must
+ * outlive it) and holds a small host struct. */
 mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t precision,
                                 const float* host_weights, size_t n_floats,
-                                const float* act_scales, void* dev_weights, size_t dev_bytes,
+                                const float* act_amax, void* dev_weights, size_t dev_bytes,
                                 void* stream, mlpf_model_t* out);
 mlpf_status_t mlpf_model_destroy(mlpf_model_t model); /* does not touch dev_weights */
 
-/* Bytes of the workspace needed by any call below for a batch of at most total_rows rows and
- * n_events events. A workspace may be reused by consecutive calls on one stream. */
-size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t n_events);
+/* Bytes of the workspace needed by any call below for a batch of at most total_rows rows, at most
+ * n_events events and valid counts of at most max_seqlen (0 for a NULL model, negative sizes or
+ * max_seqlen above 8192). A workspace may be reused by consecutive calls on one stream. */
+size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t max_seqlen,
+                            int32_t n_events);
 
 /* The residual stream h ([S][T][d] below) is held in the model's activation type: FP32 for
  * MLPF_FP32, bf16 (raw 16-bit values) for MLPF_BF16 and MLPF_BF16_FP8FFN, as in a BF16
@@ -152,8 +177,10 @@ mlpf_status_t mlpf_encoder_forward(mlpf_model_t model, void* h, const mlpf_batch
 
 /* Output heads and the inference rule (Sec. 5.3, Eq. 2): from h ([S][T][d], as left by
  * mlpf_encoder_forward) writes logits[T][6], reg[T][5] (pT', eta, sin phi, cos phi, E'), and
- * cls[T] = argmax of the logits (int32). If prim (FP32 [T][2]: primary pT, E) and decoded
- * (FP32 [T][4]) are both non-NULL, decoded gets (pT, eta, phi, E). */
+ * cls[T] (int32), the class the config's decision rule takes from the six logits (ARGMAX: their
+ * argmax; BINARY: 0 unless the binary logit is positive, else 1 + the particle-type argmax). If
+ * prim (FP32 [T][2]: primary pT, E) and decoded (FP32 [T][4]) are both non-NULL, decoded gets
+ * (pT, eta, phi, E). */
 mlpf_status_t mlpf_heads(mlpf_model_t model, const void* h, const mlpf_batch_t* batch,
                          float* logits, float* reg, int32_t* cls, const float* prim,
                          float* decoded, void* ws, size_t ws_bytes, void* stream);
@@ -266,9 +293,10 @@ mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);
 
 /* FP8 activation calibration for MLPF_BF16_FP8FFN. Runs the embedding and encoder of `model` (an
  * FP32 or BF16 model) on the batch and raises amax[2l] to max |LN2 output| and amax[2l+1] to
- * max |GELU(FFN1)| of block l, over every live row (so calibration batches should carry no padding
+ * max |act(FFN1)| of block l, over every live row (so calibration batches should carry no padding
  * rows). amax: device FP32 [2 n_layers] holding non-negative values on entry (zero it before the
- * first batch; calls accumulate the maximum). The act_scales of mlpf_model_create are amax / 448. */
+ * first batch; calls accumulate the maximum). Its final values are the act_amax argument of
+ * mlpf_model_create. */
 mlpf_status_t mlpf_calibrate_fp8(mlpf_model_t model, const float* x, const mlpf_batch_t* batch,
                                  float* amax, void* ws, size_t ws_bytes, void* stream);
 

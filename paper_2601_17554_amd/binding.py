@@ -21,6 +21,8 @@ MLPF_FP32, MLPF_BF16, MLPF_BF16_FP8FFN = 0, 1, 2
 PRECISIONS = {"fp32": MLPF_FP32, "bf16": MLPF_BF16, "bf16_fp8ffn": MLPF_BF16_FP8FFN}
 TOPOLOGIES = {"serial": 0, "parallel2": 1}
 HEAD_WIDTHS = (("cls", 6), ("pt", 1), ("eta", 1), ("phi", 2), ("e", 1))
+# With the paper's separate binary and particle-type heads (config binary_head).
+HEAD_WIDTHS_BINARY = (("binary", 1), ("pid", 5), ("pt", 1), ("eta", 1), ("phi", 2), ("e", 1))
 MAX_SEQLEN = 8192
 
 
@@ -35,11 +37,13 @@ class _Config(ctypes.Structure):
                 ("n_heads", ctypes.c_int32), ("d_ff", ctypes.c_int32),
                 ("n_layers", ctypes.c_int32), ("topology", ctypes.c_int32),
                 ("ln_eps", ctypes.c_float), ("activation", ctypes.c_int32),
-                ("decision", ctypes.c_int32), ("embed_per_type", ctypes.c_int32)]
+                ("decision", ctypes.c_int32), ("embed_per_type", ctypes.c_int32),
+                ("binary_head", ctypes.c_int32)]
 
 
 class _Batch(ctypes.Structure):
     _fields_ = [("row_start", ctypes.c_void_p), ("n_valid", ctypes.c_void_p),
+                ("row_start_host", ctypes.c_void_p), ("n_valid_host", ctypes.c_void_p),
                 ("n_events", ctypes.c_int32), ("total_rows", ctypes.c_int32),
                 ("max_seqlen", ctypes.c_int32)]
 
@@ -63,7 +67,7 @@ def load() -> ctypes.CDLL:
         "mlpf_weights_count": (sz, [cfgp]),
         "mlpf_model_create": (st, [cfgp, st, vp, sz, vp, vp, sz, vp, ctypes.POINTER(vp)]),
         "mlpf_model_destroy": (st, [vp]),
-        "mlpf_workspace_bytes": (sz, [vp, i32, i32]),
+        "mlpf_workspace_bytes": (sz, [vp, i32, i32, i32]),
         "mlpf_embed": (st, [vp, vp, bp, vp, vp, sz, vp]),
         "mlpf_encoder_forward": (st, [vp, vp, bp, vp, sz, vp]),
         "mlpf_heads": (st, [vp, vp, bp, vp, vp, vp, vp, vp, vp, sz, vp]),
@@ -138,7 +142,8 @@ def make_config(cfg) -> _Config:
                    TOPOLOGIES[cfg.topology], cfg.ln_eps,
                    ACTIVATIONS[getattr(cfg, "activation", "gelu")],
                    DECISIONS[getattr(cfg, "decision", "argmax")],
-                   1 if getattr(cfg, "embed_per_type", False) else 0)
+                   1 if getattr(cfg, "embed_per_type", False) else 0,
+                   1 if getattr(cfg, "binary_head", False) else 0)
 
 
 def flatten_weights(weights: Mapping[str, np.ndarray], cfg) -> np.ndarray:
@@ -150,32 +155,49 @@ def flatten_weights(weights: Mapping[str, np.ndarray], cfg) -> np.ndarray:
         names += [f"layers.{layer}.{s}" for s in
                   ("ln1.gamma", "ln1.beta", "W_qkv", "b_qkv", "W_o", "b_o",
                    "ln2.gamma", "ln2.beta", "W_1", "b_1", "W_2", "b_2")]
-    for name, _ in HEAD_WIDTHS:
+    heads = HEAD_WIDTHS_BINARY if getattr(cfg, "binary_head", False) else HEAD_WIDTHS
+    for name, _ in heads:
         names += [f"heads.{name}.{s}" for s in ("W1", "b1", "W2", "b2")]
     return np.concatenate([np.ascontiguousarray(weights[n], dtype=np.float32).ravel() for n in names])
 
 
 class Batch:
     """Device-side batch description: rows of event e are row_start[e]..row_start[e+1]-1, the first
-    n_valid[e] of them valid."""
+    n_valid[e] of them valid. ``row_start_host`` / ``n_valid_host`` (int32 numpy arrays holding the
+    same values) are the optional host mirrors the library validates before launching."""
 
     def __init__(self, row_start: torch.Tensor, n_valid: Optional[torch.Tensor], n_events: int,
-                 total_rows: int, max_seqlen: int):
+                 total_rows: int, max_seqlen: int, row_start_host: Optional[np.ndarray] = None,
+                 n_valid_host: Optional[np.ndarray] = None):
         self.row_start, self.n_valid = row_start, n_valid
         self.n_events, self.total_rows, self.max_seqlen = n_events, total_rows, max_seqlen
-        self._c = _Batch(_ptr(row_start), _ptr(n_valid), n_events, total_rows, max_seqlen)
+        self.set_host_mirrors(row_start_host, n_valid_host)
+
+    def set_host_mirrors(self, row_start_host: Optional[np.ndarray],
+                         n_valid_host: Optional[np.ndarray]) -> None:
+        def host(a):
+            return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+        self.row_start_host, self.n_valid_host = host(row_start_host), host(n_valid_host)
+        hp = lambda a: None if a is None else a.ctypes.data
+        self._c = _Batch(_ptr(self.row_start), _ptr(self.n_valid), hp(self.row_start_host),
+                         hp(self.n_valid_host), self.n_events, self.total_rows, self.max_seqlen)
 
     @classmethod
     def from_host(cls, row_start: np.ndarray, n_valid: Optional[np.ndarray], device="cuda",
-                  max_seqlen: Optional[int] = None) -> "Batch":
-        rs = torch.as_tensor(np.asarray(row_start, dtype=np.int32)).to(device)
-        nv = None if n_valid is None else torch.as_tensor(np.asarray(n_valid, dtype=np.int32)).to(device)
-        n_events = len(row_start) - 1
-        total = int(row_start[-1]) if n_events >= 0 and len(row_start) else 0
+                  max_seqlen: Optional[int] = None, mirrors: bool = True) -> "Batch":
+        """Uploads the description; with ``mirrors`` the host arrays are kept as the validated
+        host mirrors."""
+        rs_h = np.ascontiguousarray(row_start, dtype=np.int32)
+        nv_h = None if n_valid is None else np.ascontiguousarray(n_valid, dtype=np.int32)
+        rs = torch.as_tensor(rs_h).to(device)
+        nv = None if nv_h is None else torch.as_tensor(nv_h).to(device)
+        n_events = len(rs_h) - 1
+        total = int(rs_h[-1]) if n_events >= 0 and len(rs_h) else 0
         if max_seqlen is None:
-            spans = np.diff(np.asarray(row_start)) if n_valid is None else np.asarray(n_valid)
+            spans = np.diff(rs_h) if nv_h is None else nv_h
             max_seqlen = int(spans.max()) if len(spans) else 0
-        return cls(rs, nv, n_events, total, max_seqlen)
+        return cls(rs, nv, n_events, total, max_seqlen, rs_h if mirrors else None,
+                   nv_h if mirrors else None)
 
     @property
     def c(self):
@@ -253,15 +275,15 @@ def build_fp8_model(cfg, weights: Mapping[str, np.ndarray], calib: Sequence, dev
                     calib_precision: str = "fp32") -> "Model":
     """An MLPF_BF16_FP8FFN model whose activation scales are calibrated on ``calib`` (a sequence of
     (x [T][F] float32 array, row_start, n_valid) host batches without padding rows): per-tensor
-    amax of each block's FFN inputs on the calibration model, scale = amax / 448."""
+    amax of each block's FFN inputs on the calibration model (the library sets each scale from
+    it)."""
     ref = Model(cfg, weights, calib_precision, device=device)
     amax = torch.zeros(2 * cfg.n_layers, dtype=torch.float32, device=device)
     for x, row_start, n_valid in calib:
         batch = Batch.from_host(row_start, n_valid, device=device)
         ref.calibrate_fp8(torch.from_numpy(np.ascontiguousarray(x)).to(device), batch, amax)
     torch.cuda.synchronize()
-    scales = np.maximum(amax.cpu().numpy().astype(np.float64), 1e-30) / 448.0
-    return Model(cfg, weights, "bf16_fp8ffn", act_scales=scales.astype(np.float32), device=device)
+    return Model(cfg, weights, "bf16_fp8ffn", act_amax=amax.cpu().numpy(), device=device)
 
 
 class Graph:
@@ -296,7 +318,7 @@ class Model:
     """A libmlpf model handle with its device weight buffer (allocated by torch)."""
 
     def __init__(self, cfg, weights: Mapping[str, np.ndarray], precision: str = "fp32",
-                 act_scales: Optional[np.ndarray] = None, device: str = "cuda"):
+                 act_amax: Optional[np.ndarray] = None, device: str = "cuda"):
         lib = load()
         self.cfg, self.precision, self.device = cfg, precision, device
         self._ccfg = make_config(cfg)
@@ -308,13 +330,13 @@ class Model:
         if nbytes == 0:
             raise MlpfError(2, f"unsupported configuration/precision {cfg} {precision}")
         self.wbuf = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        scales = None
-        if act_scales is not None:
-            self._scales = np.ascontiguousarray(act_scales, dtype=np.float32)
-            scales = self._scales.ctypes.data
+        amax = None
+        if act_amax is not None:
+            self._amax = np.ascontiguousarray(act_amax, dtype=np.float32)
+            amax = self._amax.ctypes.data
         handle = ctypes.c_void_p()
         _check(lib.mlpf_model_create(ctypes.byref(self._ccfg), prec, blob.ctypes.data, blob.size,
-                                     scales, self.wbuf.data_ptr(), nbytes,
+                                     amax, self.wbuf.data_ptr(), nbytes,
                                      _stream(None), ctypes.byref(handle)))
         self.handle = handle
         self.stacks = 2 if cfg.topology == "parallel2" else 1
@@ -359,12 +381,12 @@ class Model:
                 else ("bm", "bn", "wm", "wn", "bkb", "persist"))
         return {k: int(v[i]) for i, k in enumerate(keys)}
 
-    def workspace_bytes(self, total_rows: int, n_events: int) -> int:
-        return int(load().mlpf_workspace_bytes(self.handle, total_rows, n_events))
+    def workspace_bytes(self, total_rows: int, n_events: int, max_seqlen: int = MAX_SEQLEN) -> int:
+        return int(load().mlpf_workspace_bytes(self.handle, total_rows, max_seqlen, n_events))
 
-    def workspace(self, total_rows: int, n_events: int) -> torch.Tensor:
-        return torch.empty(max(self.workspace_bytes(total_rows, n_events), 1), dtype=torch.uint8,
-                           device=self.device)
+    def workspace(self, total_rows: int, n_events: int, max_seqlen: int = MAX_SEQLEN) -> torch.Tensor:
+        return torch.empty(max(self.workspace_bytes(total_rows, n_events, max_seqlen), 1),
+                           dtype=torch.uint8, device=self.device)
 
     def outputs(self, total_rows: int, decode: bool = False) -> Dict[str, torch.Tensor]:
         t = total_rows

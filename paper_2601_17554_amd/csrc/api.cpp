@@ -56,6 +56,17 @@ uint16_t f32_to_bf16_rne(float f) {
 constexpr int kEmbedKp = 64;
 constexpr int kHeadsTile = 13;  // the 64 x 256 GEMM tile (whole heads per column tile)
 
+// Output heads: five (cls 6, pT' 1, eta 1, phi 2, E' 1), or six with the paper's separate binary
+// and particle-type heads (binary 1, pid 5, then the same four). Their second layers give 11
+// outputs in both cases: six classification logits, then pT', eta, sin phi, cos phi, E'.
+int n_out_heads(const mlpf_config_t& c) { return c.binary_head ? 6 : 5; }
+int n_cls_heads(const mlpf_config_t& c) { return c.binary_head ? 2 : 1; }
+const int* head_widths(const mlpf_config_t& c) {
+  static const int five[5] = {6, 1, 1, 2, 1};
+  static const int six[6] = {1, 5, 1, 1, 2, 1};
+  return c.binary_head ? six : five;
+}
+
 struct Layer {
   size_t ln1g, ln1b, wqkv, bqkv, wo, bo, ln2g, ln2b, w1, b1, w2, b2;
   size_t w1p = 0, w2p = 0;  // fused-FFN weight images (ffn_pack), when ffn_fused
@@ -101,6 +112,9 @@ uint8_t f32_to_e4m3(float x) {
   return sign | (uint8_t)c;
 }
 
+// Per-tensor E4M3 scale: the largest magnitude maps to 448, the largest finite E4M3 value.
+float fp8_scale(float amax) { return amax > 0.f ? amax / 448.0f : 1.0f; }
+
 WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
   const size_t d = c.d_model, ff = c.d_ff, eb = elem_bytes(prec), fb = ffn_elem_bytes(prec);
   WeightPlan w{};
@@ -141,8 +155,9 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
       L.w2p = take(ffn_pack_bytes(c.d_model, c.d_ff, 2));
     }
   }
-  w.h_w1 = take(5 * d * d * eb);
-  w.h_b1 = take(5 * d * 4);
+  const size_t nh = n_out_heads(c);
+  w.h_w1 = take(nh * d * d * eb);
+  w.h_b1 = take(nh * d * 4);
   w.h_w2 = take(d * 11 * 4);
   w.h_b2 = take(11 * 4);
   w.total = off;
@@ -153,7 +168,7 @@ size_t master_count(const mlpf_config_t& c) {
   const size_t d = c.d_model, f = c.n_features, ff = c.d_ff;
   size_t n = (c.embed_per_type ? 2 : 1) * (f * d + d + d * d + d);
   n += (size_t)c.n_layers * (2 * d + 3 * d * d + 3 * d + d * d + d + 2 * d + d * ff + ff + ff * d + d);
-  n += 5 * (d * d + d) + d * 11 + 11;
+  n += (size_t)n_out_heads(c) * (d * d + d) + d * 11 + 11;
   return n;
 }
 
@@ -184,6 +199,8 @@ mlpf_status_t check_config(const mlpf_config_t* c) {
     return fail(MLPF_ERR_INVALID_ARG, "unknown decision %d", c->decision);
   if (c->embed_per_type != 0 && c->embed_per_type != 1)
     return fail(MLPF_ERR_INVALID_ARG, "embed_per_type must be 0 or 1");
+  if (c->binary_head != 0 && c->binary_head != 1)
+    return fail(MLPF_ERR_INVALID_ARG, "binary_head must be 0 or 1");
   return MLPF_OK;
 }
 
@@ -242,7 +259,7 @@ WsPlan plan_ws(const mlpf_model_s* m, int64_t T, int64_t E) {
   w.v = take(td * eb);
   w.o = take(td * eb);
   w.y = take(td * eb);
-  const size_t uw = std::max<size_t>((size_t)c.d_ff, 5 * (size_t)c.d_model);
+  const size_t uw = std::max<size_t>((size_t)c.d_ff, (size_t)n_out_heads(c) * c.d_model);
   w.u = take((size_t)T * uw * eb);
   w.h = take((size_t)m->stacks * td * m->hbytes);
   w.total = off;
@@ -268,6 +285,25 @@ mlpf_status_t check_batch(const mlpf_model_s* m, const mlpf_batch_t* b) {
     return fail(MLPF_ERR_UNSUPPORTED, "max_seqlen=%d exceeds %d", b->max_seqlen, MLPF_MAX_SEQLEN);
   if (b->n_events > 0 && !b->row_start) return fail(MLPF_ERR_INVALID_ARG, "row_start is NULL");
   (void)m;
+  // Host mirrors: the documented layout is checked before anything is enqueued.
+  const int32_t* rs = b->row_start_host;
+  if (!rs) return MLPF_OK;
+  if (b->n_valid && !b->n_valid_host)
+    return fail(MLPF_ERR_INVALID_ARG, "n_valid_host is needed with row_start_host when n_valid is set");
+  if (rs[0] < 0) return fail(MLPF_ERR_INVALID_ARG, "row_start[0]=%d is negative", rs[0]);
+  for (int e = 0; e < b->n_events; ++e) {
+    if (rs[e + 1] < rs[e])
+      return fail(MLPF_ERR_INVALID_ARG, "row_start decreases at event %d (%d > %d)", e, rs[e], rs[e + 1]);
+    const int span = rs[e + 1] - rs[e];
+    const int nv = b->n_valid ? b->n_valid_host[e] : span;
+    if (nv < 0 || nv > span)
+      return fail(MLPF_ERR_INVALID_ARG, "n_valid[%d]=%d outside 0..%d (its rows)", e, nv, span);
+    if (nv > b->max_seqlen)
+      return fail(MLPF_ERR_INVALID_ARG, "event %d has %d valid rows > max_seqlen=%d", e, nv, b->max_seqlen);
+  }
+  if (rs[b->n_events] > b->total_rows)
+    return fail(MLPF_ERR_INVALID_ARG, "row_start[%d]=%d > total_rows=%d", b->n_events, rs[b->n_events],
+                b->total_rows);
   return MLPF_OK;
 }
 
@@ -631,15 +667,16 @@ mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, 
   const size_t eb = elem_bytes(m->prec);
   mlpf_status_t st;
   ProfScope prof(cx.m, MLPF_PROF_HEADS, cx.s);
-  // First layer of the five heads: [T][d] -> GELU -> [T][5d]. For PARALLEL2 the classification
-  // head reads stack 0 and the regression heads stack 1.
+  // First layer of every head: [T][d] -> act -> [T][nh d]. For PARALLEL2 the classification
+  // head(s) read stack 0 and the regression heads stack 1.
+  const int nh = n_out_heads(m->cfg), ncls = n_cls_heads(m->cfg);
   const int groups = m->stacks == 1 ? 1 : 2;
   // Fused (d_model 256, bf16 operands): 64 x 256 tiles, one head per column tile; the epilogue
-  // keeps GELU(first layer) on chip and writes only the 11 second-layer sums per row (into u).
+  // keeps act(first layer) on chip and writes only the 11 second-layer sums per row (into u).
   const bool fused = m->plan.heads_fused && m->tune[MLPF_OP_HEADS] != 0;
   for (int g = 0; g < groups; ++g) {
-    const int c0 = (groups == 1) ? 0 : (g == 0 ? 0 : d);
-    const int nc = (groups == 1) ? 5 * d : (g == 0 ? d : 4 * d);
+    const int c0 = (groups == 1) ? 0 : (g == 0 ? 0 : ncls * d);
+    const int nc = (groups == 1) ? nh * d : (g == 0 ? ncls * d : (nh - ncls) * d);
     GemmArgs a;
     a.a = (const char*)h + (g == 0 ? 0 : td * m->hbytes);
     a.lda = d;
@@ -650,20 +687,22 @@ mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, 
     a.wt = (const char*)m->at(m->plan.h_w1) + (size_t)c0 * d * eb;
     a.bias = m->atf(m->plan.h_b1) + c0;
     a.out = (char*)cx.p(cx.w.u) + (size_t)c0 * eb;
-    a.ldo = 5 * d;
+    a.ldo = nh * d;
+    a.heads6 = nh == 6;
     if (fused) {
       a.m_dev = cx.n_rows;
       a.w2 = m->atf(m->plan.h_w2);
       a.hout = (float*)cx.p(cx.w.u);
       a.head0 = c0 / d;
       a.relu = m->cfg.activation == MLPF_ACT_RELU;
-    HIP_TRY(launch_gemm(P_BF16, A_PLAIN, E_HEADS, kHeadsTile, a, cx.s), "gemm launch");
+      HIP_TRY(launch_gemm(P_BF16, A_PLAIN, E_HEADS, kHeadsTile, a, cx.s), "gemm launch");
       continue;
     }
     if ((st = run_gemm(cx, MLPF_OP_HEADS1, m->hbytes == 2 ? A_PLAIN : A_F32, E_GELU, a))) return st;
   }
   Heads2Args p;
   p.binary = m->cfg.decision == MLPF_DECIDE_BINARY;
+  p.heads6 = nh == 6;
   p.uh = cx.p(cx.w.u);
   p.d = d;
   p.rows = T;
@@ -718,7 +757,7 @@ size_t mlpf_weights_count(const mlpf_config_t* cfg) {
 
 mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t precision,
                                 const float* host_weights, size_t n_floats,
-                                const float* act_scales, void* dev_weights, size_t dev_bytes,
+                                const float* act_amax, void* dev_weights, size_t dev_bytes,
                                 void* stream, mlpf_model_t* out) {
   if (!out) return fail(MLPF_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -727,10 +766,10 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
   if (precision != MLPF_FP32 && precision != MLPF_BF16 && precision != MLPF_BF16_FP8FFN)
     return fail(MLPF_ERR_INVALID_ARG, "unknown precision %d", (int)precision);
   if (precision == MLPF_BF16_FP8FFN) {
-    if (!act_scales) return fail(MLPF_ERR_INVALID_ARG, "MLPF_BF16_FP8FFN needs act_scales");
+    if (!act_amax) return fail(MLPF_ERR_INVALID_ARG, "MLPF_BF16_FP8FFN needs act_amax");
     for (int i = 0; i < 2 * cfg->n_layers; ++i)
-      if (!(act_scales[i] > 0.f) || !std::isfinite(act_scales[i]))
-        return fail(MLPF_ERR_INVALID_ARG, "act_scales[%d] must be positive and finite", i);
+      if (!(act_amax[i] >= 0.f) || !std::isfinite(act_amax[i]))
+        return fail(MLPF_ERR_INVALID_ARG, "act_amax[%d] must be non-negative and finite", i);
   }
   if (!host_weights) return fail(MLPF_ERR_INVALID_ARG, "host_weights is NULL");
   if (n_floats != master_count(*cfg))
@@ -768,7 +807,7 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
   auto put_wt_fp8 = [&](size_t off, int in, int outn, int kp) {
     float amax = 0.f;
     for (size_t i = 0; i < (size_t)in * outn; ++i) amax = std::max(amax, std::fabs(src[i]));
-    const float scale = amax > 0.f ? amax / 448.0f : 1.0f;
+    const float scale = fp8_scale(amax);
     for (int i = 0; i < in; ++i)
       for (int o = 0; o < outn; ++o)
         img[off + (size_t)o * kp + i] = f32_to_e4m3(src[(size_t)i * outn + o] / scale);
@@ -801,8 +840,8 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
       put_f32(L.b1, ff);
       Lm.s_w2 = put_wt_fp8(L.w2, ff, d, ff);
       put_f32(L.b2, d);
-      Lm.s_a1 = act_scales[2 * l];
-      Lm.s_a2 = act_scales[2 * l + 1];
+      Lm.s_a1 = fp8_scale(act_amax[2 * l]);
+      Lm.s_a2 = fp8_scale(act_amax[2 * l + 1]);
     } else {
       put_wt(L.w1, d, ff, d);
       put_f32(L.b1, ff);
@@ -813,12 +852,13 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
                  (uint16_t*)(img.data() + L.w1p), (uint16_t*)(img.data() + L.w2p));
     }
   }
-  // Heads: W1 of the five heads stacked as rows of W^T [5d][d]; W2 as [d][11].
-  static const int widths[5] = {6, 1, 1, 2, 1};
+  // Heads: W1 of the heads stacked as rows of W^T [nh d][d]; W2 as [d][11] (block diagonal: each
+  // output column reads its own head's hidden units).
+  const int* widths = head_widths(c);
   const size_t eb = elem_bytes(precision);
   std::vector<float> w2(d * 11, 0.f), b2(11, 0.f);
   int col = 0;
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < n_out_heads(c); ++k) {
     put_wt(plan.h_w1 + (size_t)k * d * d * eb, d, d, d);
     put_f32(plan.h_b1 + (size_t)k * d * 4, d);
     for (int j = 0; j < d; ++j)
@@ -865,8 +905,10 @@ mlpf_status_t mlpf_model_destroy(mlpf_model_t model) {
   return MLPF_OK;
 }
 
-size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t n_events) {
-  if (!model || total_rows < 0 || n_events < 0) return 0;
+size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t max_seqlen,
+                            int32_t n_events) {
+  if (!model || total_rows < 0 || n_events < 0 || max_seqlen < 0 || max_seqlen > MLPF_MAX_SEQLEN)
+    return 0;
   return plan_ws(model, total_rows, n_events).total;
 }
 

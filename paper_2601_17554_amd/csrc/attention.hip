@@ -184,7 +184,9 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
         alpha[j] = 1.f;
         if (t == 0 || __any(mx > 0.f)) {
           const float m_new = (t == 0) ? m_run[j] + mx : m_run[j] + fmaxf(mx, 0.f);
-          const float a = __builtin_amdgcn_exp2f(m_run[j] - m_new);  // 0 on the first tile
+          // Nothing is accumulated before the first tile: its factor is 0 (the offset starts at 0,
+          // not at -inf, so exp2(m_run - m_new) would overflow for maxima below -128).
+          const float a = (t == 0) ? 0.f : __builtin_amdgcn_exp2f(m_run[j] - m_new);
           m_run[j] = m_new;
           qaug[j] = h == 0 ? neg_split3(m_new) : u32x4{0, 0, 0, 0};
           l_run[j] *= a;

@@ -267,8 +267,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
       // 32-wide k-step). W2 is FP32: it enters as hi + lo, hi = bf16(w), lo = bf16(w - hi), two
       // products into the same FP32 sums (|w - hi - lo| <= 2^-18 |w|). Wave w owns rows 16 w ..
       // 16 w + 15.
+      // Output columns of head k: five heads cls 0..5, pT 6, eta 7, phi 8..9, E 10; six heads
+      // binary 0, pid 1..5, then the same four.
       const int k = p.head0 + n0 / 256;
-      const int c0 = k == 0 ? 0 : k + 5 + (k == 4), wid = k == 0 ? 6 : k == 3 ? 2 : 1;
+      const int k6 = p.heads6 ? k : k + 1;  // index in the six-head order (k > 0 for five heads)
+      const int c0 = (!p.heads6 && k == 0) ? 0 : k6 == 0 ? 0 : k6 == 1 ? 1 : k6 + 4 + (k6 == 5);
+      const int wid = (!p.heads6 && k == 0) ? 6 : k6 == 0 ? 1 : k6 == 1 ? 5 : k6 == 4 ? 2 : 1;
       char* w2s = smem + kHeadsHid;  // [2 (hi, lo)][16][kHeadsRS]
       {
         const int j = tid;  // hidden unit (NT == 256)

@@ -53,6 +53,7 @@ struct GemmArgs {
   const float* w2 = nullptr;  // [256][11]
   float* hout = nullptr;      // [M][11]
   int head0 = 0;              // head index of the first 256 columns
+  int heads6 = 0;             // six heads (binary 1, pid 5, pT 1, eta 1, phi 2, E 1) instead of five
 };
 
 // Tile shapes available to the GEMM (index = tile id). Each entry: BM, BN, BK(bytes-agnostic
@@ -141,12 +142,12 @@ struct WorklistArgs {
 };
 hipError_t launch_worklist(const WorklistArgs& args, hipStream_t stream);
 
-// Second layer of the five output heads, argmax and optional decode.
+// Second layer of the output heads, class rule and optional decode.
 struct Heads2Args {
-  const void* uh = nullptr;   // [rows][5d] hidden activations (operand type)
+  const void* uh = nullptr;   // [rows][nh d] hidden activations (operand type), nh = 5 or 6
   int d = 0, rows = 0;
   const int32_t* m_dev = nullptr;
-  const float* w2 = nullptr;  // [d][11]: columns cls0..5, pt, eta, sin, cos, e
+  const float* w2 = nullptr;  // [d][11]: columns cls0..5 (or binary, pid1..5), pt, eta, sin, cos, e
   const float* b2 = nullptr;  // [11]
   float* logits = nullptr;
   float* reg = nullptr;
@@ -154,6 +155,7 @@ struct Heads2Args {
   const float* prim = nullptr;
   float* decoded = nullptr;
   int binary = 0;  // class rule: 0 argmax of six (class 0 = none), 1 binary logit > 0 then PID argmax
+  int heads6 = 0;  // uh holds six heads' hidden layers (binary, pid, pT, eta, phi, E) instead of five
 };
 hipError_t launch_heads2(Prec prec, const Heads2Args& args, hipStream_t stream);
 // From the E_HEADS partial outputs (uh = hout [rows][11] FP32): adds b2, writes logits, reg,

@@ -108,31 +108,35 @@ __device__ __forceinline__ int decide_class(const float (&acc)[11], int binary) 
   return best;
 }
 
-// Second layer of the five heads (block diagonal [5d] -> 11), argmax, decode. One wave per row:
+// Second layer of the heads (block diagonal [nh d] -> 11), class rule, decode. One wave per row:
 // lanes read the row's hidden activations coalesced, each keeps 11 partial dot products, and the
-// wave reduces them.
-template <class S>
+// wave reduces them. NH = 5: output columns cls 0..5, pT 6, eta 7, phi 8..9, E 10 read heads
+// 0, 1, 2, 3, 4; NH = 6: binary 0 and pid 1..5 read heads 0 and 1, the rest heads 2..5.
+template <int NH>
+__device__ constexpr int head_of_col(int c) {
+  if (c < 6) return (NH == 6 && c > 0) ? 1 : 0;
+  const int r = c == 6 ? 0 : c == 7 ? 1 : c <= 9 ? 2 : 3;  // pT, eta, phi (sin, cos), E
+  return NH - 4 + r;
+}
+
+template <class S, int NH>
 __global__ __launch_bounds__(256) void heads2_kernel(const Heads2Args p) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   int M = p.rows;
   if (p.m_dev) M = min(M, max(*p.m_dev, 0));
   if (row >= M) return;
-  const S* u = (const S*)p.uh + (int64_t)row * 5 * p.d;
+  const S* u = (const S*)p.uh + (int64_t)row * NH * p.d;
   float acc[11];
 #pragma unroll
   for (int c = 0; c < 11; ++c) acc[c] = 0.f;
   for (int j = lane; j < p.d; j += 64) {
     const float* w = p.w2 + j * 11;
-    const float uc = (float)u[j], up = (float)u[p.d + j], ue = (float)u[2 * p.d + j];
-    const float uf = (float)u[3 * p.d + j], ux = (float)u[4 * p.d + j];
+    float uk[NH];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += uc * w[c];
-    acc[6] += up * w[6];
-    acc[7] += ue * w[7];
-    acc[8] += uf * w[8];
-    acc[9] += uf * w[9];
-    acc[10] += ux * w[10];
+    for (int k = 0; k < NH; ++k) uk[k] = (float)u[k * p.d + j];
+#pragma unroll
+    for (int c = 0; c < 11; ++c) acc[c] += uk[head_of_col<NH>(c)] * w[c];
   }
 #pragma unroll
   for (int c = 0; c < 11; ++c) acc[c] = wave_sum(acc[c]) + p.b2[c];
@@ -158,10 +162,14 @@ __global__ __launch_bounds__(256) void heads2_kernel(const Heads2Args p) {
 hipError_t launch_heads2(Prec prec, const Heads2Args& p, hipStream_t s) {
   const int grid = (p.rows + 3) / 4;
   if (grid == 0) return hipSuccess;
-  if (prec == P_F32)
-    hipLaunchKernelGGL(heads2_kernel<float>, dim3(grid), dim3(256), 0, s, p);
+  if (prec == P_F32 && p.heads6)
+    hipLaunchKernelGGL((heads2_kernel<float, 6>), dim3(grid), dim3(256), 0, s, p);
+  else if (prec == P_F32)
+    hipLaunchKernelGGL((heads2_kernel<float, 5>), dim3(grid), dim3(256), 0, s, p);
+  else if (p.heads6)
+    hipLaunchKernelGGL((heads2_kernel<__bf16, 6>), dim3(grid), dim3(256), 0, s, p);
   else
-    hipLaunchKernelGGL(heads2_kernel<__bf16>, dim3(grid), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((heads2_kernel<__bf16, 5>), dim3(grid), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

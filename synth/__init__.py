@@ -182,6 +182,17 @@ def event_set(root_seed: int, count: int, lo: int = 500) -> List[Event]:
     return [make_event(s, None, lo) for s in np.random.SeedSequence(root_seed).spawn(count)]
 
 
+def event_of_set(root_seed: int, count: int, index: int, lo: int = 500) -> Event:
+    """Event ``index`` of event_set(root_seed, count, lo), without drawing the others."""
+    return make_event(np.random.SeedSequence(root_seed).spawn(count)[index], None, lo)
+
+
+def event_set_counts(root_seed: int, count: int, lo: int = 500) -> np.ndarray:
+    """The element counts of event_set(root_seed, count, lo) (the first draw of each event)."""
+    return np.array([sample_count(np.random.Generator(np.random.PCG64(s)), lo)
+                     for s in np.random.SeedSequence(root_seed).spawn(count)], dtype=np.int64)
+
+
 @dataclasses.dataclass
 class Packed:
     """Events packed row-wise. Rows of event e are row_start[e] .. row_start[e+1]-1, of which the

@@ -72,9 +72,9 @@ def test_candidates_validation_without_gpu():
     def status(batch, cls, dec, offs, rows, clss, kin, cap):
         return lib.mlpf_status_string(lib.mlpf_candidates(batch, cls, dec, offs, rows, clss, kin, cap, None))
 
-    good = B._Batch(fake, None, 2, 10, 10)
-    neg = B._Batch(fake, None, -1, 10, 10)
-    big = B._Batch(fake, None, 2, 10, 100_000)
+    good = B._Batch(fake, None, None, None, 2, 10, 10)
+    neg = B._Batch(fake, None, None, None, -1, 10, 10)
+    big = B._Batch(fake, None, None, None, 2, 10, 100_000)
     assert status(None, fake, None, fake, fake, fake, None, 4) == b"MLPF_ERR_INVALID_ARG"
     assert status(ctypes.byref(neg), fake, None, fake, fake, fake, None, 4) == b"MLPF_ERR_INVALID_ARG"
     assert status(ctypes.byref(big), fake, None, fake, fake, fake, None, 4) == b"MLPF_ERR_UNSUPPORTED"
@@ -86,6 +86,74 @@ def test_candidates_validation_without_gpu():
     assert b"decoded" in lib.mlpf_last_error()
     assert status(ctypes.byref(good), fake, odd, fake, fake, fake, fake, 4) == b"MLPF_ERR_INVALID_ARG"
     assert b"aligned" in lib.mlpf_last_error()
+
+
+def _mirror_batch(B, row_start, n_valid, total_rows, max_seqlen, device_n_valid=True):
+    """A batch whose device pointers are fake (never dereferenced on a rejected call) and whose
+    host mirrors hold the given values."""
+    rs = (ctypes.c_int32 * len(row_start))(*row_start)
+    nv = None if n_valid is None else (ctypes.c_int32 * len(n_valid))(*n_valid)
+    dev_nv = ctypes.c_void_p(0x2000) if (n_valid is not None and device_n_valid) else None
+    b = B._Batch(ctypes.c_void_p(0x1000), dev_nv, ctypes.cast(rs, ctypes.c_void_p),
+                 None if nv is None else ctypes.cast(nv, ctypes.c_void_p), len(row_start) - 1,
+                 total_rows, max_seqlen)
+    b._keep = (rs, nv)
+    return b
+
+
+@pytest.mark.parametrize("row_start,n_valid,total,maxlen,what", [
+    ([0, 5, 3], None, 10, 10, b"decreases"),          # non-monotone row_start
+    ([-1, 5], None, 10, 10, b"negative"),              # negative first offset
+    ([0, 5, 12], None, 10, 10, b"total_rows"),         # last offset beyond total_rows
+    ([0, 5, 9], [5, 6], 10, 10, b"outside"),           # n_valid > its span
+    ([0, 5, 9], [5, -1], 10, 10, b"outside"),          # negative n_valid
+    ([0, 5, 9], [5, 4], 10, 4, b"max_seqlen"),         # valid count above max_seqlen
+    ([0, 8, 9], None, 10, 4, b"max_seqlen"),           # packed span above max_seqlen
+])
+def test_host_mirror_rejections_without_gpu(row_start, n_valid, total, maxlen, what):
+    """With host mirrors of row_start / n_valid, a malformed batch is rejected with
+    MLPF_ERR_INVALID_ARG before anything is enqueued (so no GPU is needed to see it)."""
+    B, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    b = _mirror_batch(B, row_start, n_valid, total, maxlen)
+    st = lib.mlpf_candidates(ctypes.byref(b), fake, None, fake, fake, fake, None, 4, None)
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG", lib.mlpf_last_error()
+    assert what in lib.mlpf_last_error(), lib.mlpf_last_error()
+
+
+def test_host_mirror_needs_n_valid_mirror_without_gpu():
+    B, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    b = _mirror_batch(B, [0, 5, 9], [5, 4], 10, 10)
+    b.n_valid_host = None
+    st = lib.mlpf_candidates(ctypes.byref(b), fake, None, fake, fake, fake, None, 4, None)
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG"
+    assert b"n_valid_host" in lib.mlpf_last_error()
+
+
+def test_six_head_config_sizes_without_gpu():
+    """The paper's six heads (separate binary and particle-type heads) add one d x d + d hidden
+    layer and keep the 11 outputs: the master blob grows by exactly that."""
+    import dataclasses
+    B, lib = _lib()
+    six = dataclasses.replace(synth.FULL, binary_head=True)
+    c6, c5 = B.make_config(six), B.make_config(synth.FULL)
+    assert c6.binary_head == 1
+    d = synth.FULL.d_model
+    n6, n5 = lib.mlpf_weights_count(ctypes.byref(c6)), lib.mlpf_weights_count(ctypes.byref(c5))
+    assert n6 == synth.param_count(six) and n6 - n5 == d * d + d
+    assert lib.mlpf_weights_bytes(ctypes.byref(c6), 1) > lib.mlpf_weights_bytes(ctypes.byref(c5), 1)
+    c6.binary_head = 2
+    h = ctypes.c_void_p()
+    st = lib.mlpf_model_create(ctypes.byref(c6), 0, None, 0, None, None, 0, None, ctypes.byref(h))
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG" and b"binary_head" in lib.mlpf_last_error()
+    # The paper's full network: ~5.1 M parameters in the paper (Sec. 5.3).
+    print("PAPER_MODEL parameters:", synth.param_count(synth.PAPER_MODEL))
+
+
+def test_workspace_bytes_rejects_bad_sizes_without_gpu():
+    B, lib = _lib()
+    assert lib.mlpf_workspace_bytes(None, 100, 100, 1) == 0
 
 
 def test_no_cpu_fallback_when_library_missing(monkeypatch):

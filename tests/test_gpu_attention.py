@@ -30,7 +30,8 @@ def B():
 
 
 def _operands(kind, H, T, dh, spread, rng):
-    """q, k, v of one of the input families: "random" (i.i.d. normal times spread), "shifted" (every
+    """q, k, v of one of the input families: "random" (i.i.d. normal times spread), "low" (every
+    score near -200 in log2 units), "shifted" (every
     query has a large component along a direction no key shares, and one key per event a large
     norm: the score bound |q| max|k| lies about 70 log2 units above the true maxima), "loose" (the
     same with the bound more than 96 above, which the BF16 kernel answers with an exact-maximum
@@ -38,6 +39,14 @@ def _operands(kind, H, T, dh, spread, rng):
     q = rng.standard_normal((H, T, dh)).astype(np.float32) * spread
     k = rng.standard_normal((H, T, dh)).astype(np.float32) * spread
     v = rng.standard_normal((H, T, dh)).astype(np.float32)
+    if kind == "low":
+        # Every score of every query lies near -200 (log2 units, after the log2(e)/sqrt(dh)
+        # prescale): the rows' maxima are far below 0, where an offset that starts at 0 instead
+        # of at the first tile's maximum would overflow exp2.
+        a = math.sqrt(200.0 * math.sqrt(dh) / 1.4426950408889634)
+        q[:, :, 0] = -a
+        k[:, :, 0] = a
+        return q, k, v
     if kind != "random":
         big_q, big_k = (20.0, 14.0) if kind == "shifted" else (30.0, 16.0)
         q[:, :, 0] = big_q
@@ -83,12 +92,21 @@ def _attention_case(B, prec, cfg, kind, spread, tile):
             got = o[r, j * dh:(j + 1) * dh]
             err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-6)
             worst = max(worst, err)
-            assert err <= TOL[prec], f"tile {tile} event {e} (n={sizes[e]}) head {j}: {err:.3e}"
+            tol = TOL[prec]
+            if prec == "fp32":
+                # FP32 scores of magnitude |s| (log2 units) carry an absolute rounding error of a
+                # few |s| 2^-24, i.e. a relative error of that times ln 2 on every softmax weight,
+                # which O passes on relative to max |v| (not to max |O|, which cancellation can make
+                # much smaller): negligible but for the "low" family's |s| ~ 200.
+                sv = np.abs(qs[j, r].astype(np.float64) @ k[j, r].astype(np.float64).T).max()
+                tol += 4 * 2.0 ** -24 * sv * math.log(2) * np.abs(v[j, r]).max() / max(np.abs(ref).max(), 1e-6)
+            assert err <= tol, f"tile {tile} event {e} (n={sizes[e]}) head {j}: {err:.3e} > {tol:.3e}"
     print(f"{prec} dh={dh} {kind} spread={spread} tile {tile}: worst normwise error {worst:.2e}")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("kind,spread", [("random", 3.0), ("loose", 0.5)], ids=["sharp", "loose"])
+@pytest.mark.parametrize("kind,spread", [("random", 3.0), ("loose", 0.5), ("low", 0.3)],
+                         ids=["sharp", "loose", "low"])
 def test_attention_every_tile(B, prec, kind, spread):
     """Every attention kernel shape the tuner may pick, on the head size of the full model."""
     from paper_2601_17554_amd import binding

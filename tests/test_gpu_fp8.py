@@ -1,23 +1,28 @@
 """FP8-E4M3 FFN path (MLPF_BF16_FP8FFN): calibrated per-tensor scales, errors against the FP64
-oracle reported per output, plus a bound and the tie-aware argmax agreement."""
+oracle reported per output. No FP8 tolerance is stated for the method; the assertions are only the
+sanity bounds the E4M3 format itself implies (below), which a zeroed, swapped or mis-scaled output
+column (norm-wise error >= 1 on the wide-output weights) cannot meet."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import mlpf_oracle as O
-from parity_util import argmax_agreement, errors, run_gpu
+from parity_util import TOL, argmax_agreement, errors, run_gpu
 
 pytestmark = pytest.mark.gpu
 
-# No tolerance is given for FP8; this bound is what E4M3 operands (3 mantissa bits) on both FFN
-# products leave after the residual stream (measured worst case with margin), see the design notes.
-FP8_BOUND = 0.1
+# E4M3 keeps 3 fraction bits: a value rounds with relative error at most U8 = 2^-4. One product
+# with both operands rounded is off by at most 2 U8 + U8^2 per term; the bound allows that for
+# each of the two FFN products.
+U8 = 2.0 ** -4
+FP8_SANITY = 2 * (2 * U8 + U8 * U8)
 
 
-def test_fp8_ffn_against_oracle():
+@pytest.mark.parametrize("wset", ["std", "wide"])
+def test_fp8_ffn_against_oracle(wset):
     from paper_2601_17554_amd import binding as B
     cfg = synth.FULL
-    w = synth.make_weights(cfg, 1)
+    w = synth.make_weights(cfg, 1, **(synth.WIDE if wset == "wide" else {}))
     calib = synth.event_set(500, 4, lo=200)
     cal = [(e.x, np.array([0, e.n], np.int32), None) for e in calib]
     m = B.build_fp8_model(cfg, w, cal)
@@ -30,9 +35,15 @@ def test_fp8_ffn_against_oracle():
         ref = O.forward(ev.x, w, cfg)
         e8 = errors({k: v[r] for k, v in got.items()}, ref)
         e16 = errors({k: v[r] for k, v in bf.items()}, ref)
-        agree, raw, ties = argmax_agreement(got["cls"][r], ref["logits"], 2e-2)
-        print(f"n={ev.n}: fp8 {({k: f'{v:.2e}' for k, v in e8.items() if not k.startswith('diag')})} "
-              f"bf16 logits {e16['logits']:.2e}; argmax {agree:.4f} raw {raw:.4f} ties {ties:.3f}")
-        for k in ("logits", "pt", "energy", "angles"):
-            assert e8[k] <= FP8_BOUND, (k, e8[k])
-        assert agree >= 0.99
+        agree, raw, ties = argmax_agreement(got["cls"][r], ref, TOL["bf16"])
+        agree8, _, ties8 = argmax_agreement(got["cls"][r], ref, U8)
+        print(f"{wset} n={ev.n}: fp8 " + ", ".join(f"{k} {v:.2e}" for k, v in e8.items())
+              + f" | bf16 logits {e16['logits']:.2e} | argmax at 2e-2 margin {agree:.4f} "
+              f"(raw {raw:.4f}, ties {ties:.3f}), at 2^-4 margin {agree8:.4f} (ties {ties8:.3f})")
+        # On the configurations' weights the regression columns are ill-conditioned (see
+        # test_gpu_parity.strict_columns): the five are bounded together there.
+        keys = ("logits", "pt_rel", "energy") + (("pt", "eta", "sin", "cos", "e") if wset == "wide"
+                                                  else ("reg_block",))
+        for k in keys:
+            assert e8[k] <= FP8_SANITY, (k, e8[k])
+        assert agree8 >= 0.99, agree8

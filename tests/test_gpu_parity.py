@@ -6,7 +6,7 @@ import pytest
 
 import synth
 from oracle import mlpf_oracle as O
-from parity_util import TOL, check_event, errors, run_gpu
+from parity_util import TOL, check_event, clear_mask, output_scale, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -31,63 +31,98 @@ def B():
     return binding
 
 
-def _model(B, cfg, seed, prec, sharpen=1.0):
-    w = synth.make_weights(cfg, seed, sharpen=sharpen)
+# The two weight sets every benchmark-configuration test runs on: the configurations' N(0, 0.02)
+# weights, and the "wide-output" set (larger embedding and head output weights, same draws) whose
+# logits and regression columns vary by O(0.1-1) between elements, so that a zeroed, swapped or
+# mis-scaled output column is far outside every tolerance.
+WEIGHT_SETS = ["std", "wide"]
+
+
+def strict_columns(tol, wset):
+    """Whether every regression column is checked norm-wise on its own. On the configurations'
+    N(0, 0.02) weights the regression columns are ill-conditioned: each is a small difference of
+    similar terms, so that rounding only the weights and features to bf16 (FP64 arithmetic
+    otherwise) already moves eta by ~2.5% of its column norm (pinned on the CPU in
+    test_oracle_pins.test_std_weights_columns_ill_conditioned_in_bf16). There the BF16 checks take
+    the five regression columns together; FP32 and the wide-output weights take each column."""
+    return tol <= TOL["fp32"] or wset == "wide"
+
+
+def _weights(cfg, seed, sharpen=1.0, wset="std"):
+    return synth.make_weights(cfg, seed, sharpen=sharpen, **(synth.WIDE if wset == "wide" else {}))
+
+
+def _model(B, cfg, seed, prec, sharpen=1.0, wset="std"):
+    w = _weights(cfg, seed, sharpen, wset)
     return w, B.Model(cfg, w, prec)
 
 
-def _check_all(got, pk, w, cfg, tol, tag, keys=None):
-    for e in range(pk.n_events):
+def _check_all(got, pk, w, cfg, tol, tag, keys=None, wset="std", events=None):
+    """Every (or the listed) event of a launch against the oracle; events of fewer than 16
+    elements take their norm-wise scales from the whole launch."""
+    rule = getattr(cfg, "decision", "argmax")
+    refs = {}
+    for e in (range(pk.n_events) if events is None else events):
         rows = pk.event_rows(e)
         if rows.stop == rows.start:
             continue
         key = None if keys is None else keys[e]
-        ref = oracle(pk.x[rows], w, cfg, key)
+        refs[e] = oracle(pk.x[rows], w, cfg, key)
+    scale = output_scale(refs.values())
+    for e, ref in refs.items():
+        rows = pk.event_rows(e)
         print(f"[{tag}] event {e} n={rows.stop - rows.start}", flush=True)
-        check_event(got, ref, rows, tol, f"{tag} event {e}")
+        check_event(got, ref, rows, tol, f"{tag} event {e}", rule=rule,
+                    columns=strict_columns(tol, wset), scale=scale)
 
 
-def test_fp32_small_single_event(B):
+@pytest.mark.parametrize("wset", WEIGHT_SETS)
+def test_fp32_small_single_event(B, wset):
     """256 elements, small model (d 64, 4 heads, 3 blocks), FP32."""
-    w, m = _model(B, synth.SMALL, 0, "fp32")
+    w, m = _model(B, synth.SMALL, 0, "fp32", wset=wset)
     pk = synth.pack([synth.make_event(100, 256)])
-    _check_all(run_gpu(m, pk), pk, w, synth.SMALL, TOL["fp32"], "C1")
+    _check_all(run_gpu(m, pk), pk, w, synth.SMALL, TOL["fp32"], f"C1 {wset}", wset=wset)
 
 
+@pytest.mark.parametrize("wset", WEIGHT_SETS)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_small_tile_edges_padded_garbage(B, prec):
+def test_small_tile_edges_padded_garbage(B, prec, wset):
     """Events whose sizes straddle the 32/64-row tiles, an empty event, padding rows holding
     +-1e4 garbage; sharpened Q/K so the softmax is far from uniform."""
-    w, m = _model(B, synth.SMALL, 3, prec, sharpen=8.0)
+    w, m = _model(B, synth.SMALL, 3, prec, sharpen=8.0, wset=wset)
     sizes = [1, 2, 31, 32, 33, 0, 63, 64, 65, 127, 128, 129, 300]
     evs = [synth.make_event(1000 + i, n) for i, n in enumerate(sizes)]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=5)
-    _check_all(run_gpu(m, pk), pk, w, synth.SMALL, TOL[prec], f"edges-{prec}")
+    _check_all(run_gpu(m, pk), pk, w, synth.SMALL, TOL[prec], f"edges-{prec}-{wset}", wset=wset)
 
 
+@pytest.mark.parametrize("wset", WEIGHT_SETS)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_full_varlen_ragged(B, prec):
-    """Full model, events packed without padding at unaligned row offsets."""
-    w, m = _model(B, synth.FULL, 2, prec, sharpen=4.0)
+def test_full_varlen_ragged(B, prec, wset):
+    """Full model, events packed without padding at unaligned row offsets (the varlen batching
+    form)."""
+    w, m = _model(B, synth.FULL, 2, prec, sharpen=4.0, wset=wset)
     evs = [synth.make_event(2000 + i, n) for i, n in enumerate([70, 1, 517, 200, 33])]
     pk = synth.pack(evs)
-    _check_all(run_gpu(m, pk), pk, w, synth.FULL, TOL[prec], f"varlen-{prec}",
-               keys=[("varlen", i) for i in range(len(evs))])
+    _check_all(run_gpu(m, pk), pk, w, synth.FULL, TOL[prec], f"varlen-{prec}-{wset}",
+               keys=[("varlen", wset, i) for i in range(len(evs))], wset=wset)
 
 
+@pytest.mark.parametrize("wset", WEIGHT_SETS)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_full_event_from_workload(B, prec):
+def test_full_event_from_workload(B, prec, wset):
     """Full-size model on the first events of the seeded single-event workload (log-normal N),
     one event per launch padded to a multiple of 64."""
-    w = synth.make_weights(synth.FULL, 1)
+    w = _weights(synth.FULL, 1, wset=wset)
     m = B.Model(synth.FULL, w, prec)
     evs = synth.event_set(200, 2, lo=500)
     for i, ev in enumerate(evs):
         pk = synth.pack([ev], pad_to=64)
         got = run_gpu(m, pk)
-        ref = oracle(ev.x, w, synth.FULL, ("workload", i))
-        print(f"[full-{prec}] event {i} n={ev.n}", flush=True)
-        check_event(got, ref, pk.event_rows(0), TOL[prec], f"full-{prec} event {i}")
+        ref = oracle(ev.x, w, synth.FULL, ("workload", wset, i))
+        print(f"[full-{prec}-{wset}] event {i} n={ev.n}", flush=True)
+        check_event(got, ref, pk.event_rows(0), TOL[prec], f"full-{prec}-{wset} event {i}",
+                    columns=strict_columns(TOL[prec], wset))
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -101,8 +136,11 @@ def test_max_seqlen_8192(B, prec):
     pk = synth.pack([ev, one])
     got = run_gpu(m, pk)
     ref = oracle(ev.x, w, cfg, ("max8192", 4))
-    check_event(got, ref, pk.event_rows(0), TOL[prec], f"8192 {prec}")
-    check_event(got, O.forward(one.x, w, cfg), pk.event_rows(1), TOL[prec], f"8192 + 1 {prec}")
+    ref1 = O.forward(one.x, w, cfg)
+    cols = strict_columns(TOL[prec], "std")
+    check_event(got, ref, pk.event_rows(0), TOL[prec], f"8192 {prec}", columns=cols)
+    check_event(got, ref1, pk.event_rows(1), TOL[prec], f"8192 + 1 {prec}", columns=cols,
+                scale=output_scale([ref, ref1]))
 
 
 @pytest.mark.parametrize("cfg", [
@@ -157,7 +195,8 @@ def test_permutation_equivariance(B, prec):
     a = run_gpu(m, synth.pack([ev]))
     b = run_gpu(m, synth.pack([synth.Event(ev.x[perm], ev.prim[perm])]))
     ref = {"logits": a["logits"][perm].astype(np.float64), "reg": a["reg"][perm].astype(np.float64)}
-    check_event(b, ref, slice(0, 333), TOL[prec], f"perm-{prec}")
+    check_event(b, ref, slice(0, 333), TOL[prec], f"perm-{prec}",
+                columns=strict_columns(TOL[prec], "std"))
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -230,7 +269,7 @@ GEMM_OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1")
 def test_every_gemm_tile(B, prec):
     """Every GEMM tile shape the tuner may pick, for all products at once, against the oracle on
     the ragged full-model batch."""
-    w, m = _model(B, synth.FULL, 2, prec, sharpen=4.0)
+    w, m = _model(B, synth.FULL, 2, prec, sharpen=4.0, wset="wide")
     evs = [synth.make_event(2000 + i, n) for i, n in enumerate([70, 1, 517, 200, 33])]
     pk = synth.pack(evs)
     m.tune_set("ffn", 0)  # the FFN as two products, so that their tiles apply
@@ -239,7 +278,7 @@ def test_every_gemm_tile(B, prec):
         for op in GEMM_OPS:
             m.tune_set(op, tile)
         _check_all(run_gpu(m, pk), pk, w, synth.FULL, TOL[prec], f"gemm tile {tile} {prec}",
-                   keys=[("varlen", i) for i in range(len(evs))])
+                   keys=[("varlen", "wide", i) for i in range(len(evs))], wset="wide")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -321,9 +360,8 @@ def test_persistent_ffn_many_tiles(B):
         np.testing.assert_array_equal(pers[k][live], one[k][live], err_msg=f"persistent vs one tile {k}")
         np.testing.assert_array_equal(pipe[k][live], one[k][live], err_msg=f"pipelined vs one tile {k}")
         np.testing.assert_array_equal(pers[k][live], two[k][live], err_msg=f"persistent vs two products {k}")
-    for e in (13, 14, 15):  # small events the oracle finishes quickly
-        rows = pk.event_rows(e)
-        check_event(pers, oracle(pk.x[rows], w, cfg), rows, TOL["bf16"], f"persistent FFN event {e}")
+    # Small events the oracle finishes quickly.
+    _check_all(pers, pk, w, cfg, TOL["bf16"], "persistent FFN", events=(13, 14, 15))
 
 
 @pytest.mark.parametrize("prec,cfg", [("fp32", synth.SMALL), ("bf16", synth.FULL), ("bf16", synth.PAPER)],
@@ -334,11 +372,11 @@ def test_relu_activation(B, prec, cfg):
     same bits."""
     import dataclasses
     cfg = dataclasses.replace(cfg, activation="relu")
-    w, m = _model(B, cfg, 31, prec, sharpen=2.0)
+    w, m = _model(B, cfg, 31, prec, sharpen=2.0, wset="wide")
     evs = [synth.make_event(5200 + i, n) for i, n in enumerate([200, 1, 77, 300])]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=11)
     got = run_gpu(m, pk)
-    _check_all(got, pk, w, cfg, TOL[prec], f"relu {prec}")
+    _check_all(got, pk, w, cfg, TOL[prec], f"relu {prec}", wset="wide")
     if prec == "bf16":
         for variant in (0, 1, 2, 3, 4):
             m.tune_set("ffn", variant)
@@ -356,35 +394,44 @@ def test_embed_per_type(B, prec, cfg):
     ragged events with garbage padding (tracks are ~8% of the elements)."""
     import dataclasses
     cfg = dataclasses.replace(cfg, embed_per_type=True)
-    w, m = _model(B, cfg, 33, prec, sharpen=2.0)
+    w, m = _model(B, cfg, 33, prec, sharpen=2.0, wset="wide")
     evs = [synth.make_event(5400 + i, n) for i, n in enumerate([180, 1, 65, 250])]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=13)
     assert 0 < (pk.x[:, 0] > 0.5).sum() < pk.total_rows
-    _check_all(run_gpu(m, pk), pk, w, cfg, TOL[prec], f"per-type embedding {prec}")
+    _check_all(run_gpu(m, pk), pk, w, cfg, TOL[prec], f"per-type embedding {prec}", wset="wide")
 
 
+@pytest.mark.parametrize("wset", WEIGHT_SETS)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_paper_model(B, prec):
-    """The paper's network in full (parallel encoders, d_head 16, ReLU, track/other embeddings,
-    binary-score rule) against the oracle on ragged events with garbage padding."""
+def test_paper_model(B, prec, wset):
+    """The paper's network in full (parallel encoders, d_head 16, ReLU, track/other embeddings, six
+    heads with separate binary and particle-type heads, binary-score rule) against the oracle on
+    ragged events with garbage padding; in BF16 both head paths (fused, two-layer)."""
     cfg = synth.PAPER_MODEL
-    w, m = _model(B, cfg, 34, prec, sharpen=2.0)
+    w, m = _model(B, cfg, 34, prec, sharpen=2.0, wset=wset)
+    if wset == "wide":
+        # Shift the binary logit so that about half of the elements are kept.
+        evs0 = [synth.make_event(5500 + i, n) for i, n in enumerate([120, 1, 70])]
+        lg = np.concatenate([O.forward(e.x, w, cfg)["logits"] for e in evs0])
+        w["heads.binary.b2"] = w["heads.binary.b2"] - np.float32(np.median(lg[:, 0]))
+        m = B.Model(cfg, w, prec)
     evs = [synth.make_event(5500 + i, n) for i, n in enumerate([120, 1, 70])]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=14)
-    got = run_gpu(m, pk)
-    for e, ev in enumerate(evs):
-        r = pk.event_rows(e)
-        ref = oracle(ev.x, w, cfg)
-        rows = slice(r.start, r.start + ev.n)
-        g = {k: v[rows] for k, v in got.items()}
-        err = errors(g, ref)
-        bad = {k: v for k, v in err.items() if not k.startswith("diag_") and not v <= TOL[prec]}
-        assert not bad, (e, err)
-        scale = np.abs(ref["logits"]).max()
-        srt = np.sort(ref["logits"][:, 1:], axis=1)
-        clear = (np.abs(ref["logits"][:, 0]) > 2 * TOL[prec] * scale) & (
-            (ref["logits"][:, 0] <= 0) | (srt[:, -1] - srt[:, -2] > 2 * TOL[prec] * scale))
-        np.testing.assert_array_equal(g["cls"][clear], ref["cls"][clear])
+    for heads in ([None, 0] if prec == "bf16" else [None]):
+        if heads is not None:
+            m.tune_set("heads", heads)
+        got = run_gpu(m, pk)
+        refs = [oracle(ev.x, w, cfg, ("paper", wset, e)) for e, ev in enumerate(evs)]
+        scale = output_scale(refs)
+        kept = 0
+        for e, (ev, ref) in enumerate(zip(evs, refs)):
+            r = pk.event_rows(e)
+            kept += int((ref["cls"] != 0).sum())
+            check_event(got, ref, slice(r.start, r.start + ev.n), TOL[prec],
+                        f"paper model {prec} {wset} heads={heads} event {e}", rule="binary",
+                        min_clear=0.3, columns=strict_columns(TOL[prec], wset), scale=scale)
+        if wset == "wide":
+            assert 0.2 * sum(e.n for e in evs) < kept < 0.8 * sum(e.n for e in evs), kept
 
 
 @pytest.mark.parametrize("prec,cfg", [("fp32", synth.SMALL), ("bf16", synth.FULL)], ids=["fp32-small", "bf16-full"])
@@ -414,9 +461,7 @@ def test_binary_decision(B, prec, cfg):
             g = {k: v[r.start:r.start + ev.n] for k, v in got.items()}
             scale = np.abs(ref["logits"]).max()
             assert np.abs(g["logits"] - ref["logits"]).max() <= TOL[prec] * scale
-            srt = np.sort(ref["logits"][:, 1:], axis=1)
-            clear = (np.abs(ref["logits"][:, 0]) > 2 * TOL[prec] * scale) & (
-                (ref["logits"][:, 0] <= 0) | (srt[:, -1] - srt[:, -2] > 2 * TOL[prec] * scale))
+            clear = clear_mask(ref["logits"], TOL[prec], "binary")
             np.testing.assert_array_equal(g["cls"][clear], ref["cls"][clear])
             assert set(np.unique(g["cls"])) <= set(range(6))
             kept += int((ref["cls"] != 0).sum())
@@ -426,18 +471,20 @@ def test_binary_decision(B, prec, cfg):
         assert 0.2 * total < kept < 0.8 * total and checked > total // 4
 
 
-@pytest.mark.parametrize("cfg", [synth.FULL, synth.PAPER], ids=["d256", "paper_parallel2"])
+@pytest.mark.parametrize("cfg", [synth.FULL, synth.PAPER, synth.Config(d_model=256, n_heads=8, d_ff=1024,
+                                                                    n_layers=2, binary_head=True)],
+                         ids=["d256", "paper_parallel2", "d256_six_heads"])
 def test_fused_heads(B, cfg):
     """The head GEMM with the second head layer in its epilogue (BF16, d_model 256) against the
     oracle, and against the unfused heads (same hidden layer bits, sums in another order), on
     ragged events with garbage padding; the paper's two-stack layout sends the classification head
     and the regression heads to separate launches."""
-    w, m = _model(B, cfg, 16, "bf16", sharpen=2.0)
+    w, m = _model(B, cfg, 16, "bf16", sharpen=2.0, wset="wide")
     evs = [synth.make_event(5100 + i, n) for i, n in enumerate([300, 1, 65, 64, 700])]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=10)
     assert B.Model.tune_shape("heads", 1) == {"fused": 1, "bm": 64, "bn": 256}
     fused = run_gpu(m, pk)
-    _check_all(fused, pk, w, cfg, TOL["bf16"], f"fused heads {cfg.topology}")
+    _check_all(fused, pk, w, cfg, TOL["bf16"], f"fused heads {cfg.topology}", wset="wide")
     m.tune_set("heads", 0)
     plain = run_gpu(m, pk)
     live = np.concatenate([np.arange(pk.event_rows(e).start, pk.event_rows(e).stop)
