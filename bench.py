@@ -32,7 +32,7 @@ PEAK_EXP_T_PER_S = 1024 * 8 * 2.4e9 / 1e12
 EVENTS_PER_BATCH = 64
 
 # HBM bytes per launch of the BF16 attention kernel on these batches, from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE) of paper_2601_17554_amd/profile_run.py scaled by a 256 MiB copy
+# (FETCH_SIZE, WRITE_SIZE) of profile_run.py scaled by a 256 MiB copy
 # (profiles/attention_bf16_varlen64_hbm_traffic.md). Valid only for the kernel source it was
 # measured on: reported as null once that source changes (attention.hip, common.h, and the
 # attention declarations of kernels.h: AttnArgs, AttnTile and the launchers).
@@ -126,6 +126,10 @@ def bench_varlen(args, cfg, w, model=None):
             stream=stream))
         res["prof"] = model.profiler_read()
         model.profiler_enable(False)
+        # The outputs of the first batch (its last run), for the error statistics.
+        res["out0"] = model.reconstruct(dev[0][0], dev[0][1], ws=wss[0], out=outs[0], stream=stream)
+        stream.synchronize()
+        res["out0"] = {k: v.cpu().numpy() for k, v in res["out0"].items()}
     res["eager_ms_per_step"] = eager_wall * 1e3 / args.steps
     n_timed = np.concatenate([batches[i % len(batches)].n_valid for i in range(args.steps)])
     res["events"] = len(n_timed)
@@ -264,48 +268,112 @@ def bench_small(args):
 
 def bench_serving(args, cfg, w):
     """Poisson arrivals at several rates through the continuous-batching server (BF16, up to 64
-    events per batch, slots bounded by a 64 GB activation budget); latency = arrival to result on
-    the host, including host packing and both PCIe copies."""
+    events per batch, admission bounded by a 64 GB activation budget, the Eq. 2 decode on); latency
+    = arrival to result on the host, including host packing and both PCIe copies. Per rate: the
+    latency percentiles, how they split into queue wait (arrival to admission) and batch service
+    (launch to result), the batch sizes and the budget's use."""
     from paper_2601_17554_amd import binding as B
     from paper_2601_17554_amd import serve
 
     model = B.Model(cfg, w, args.precision)
+    budget = 64 << 30
     ex = serve.GpuExecutor(model, max_rows=262144, max_events=EVENTS_PER_BATCH, slots=3,
-                           hbm_budget=64 << 30, buckets=4)
+                           hbm_budget=budget, buckets=4, decode=True)
+
+    def pct(a, q):
+        return round(float(np.percentile(a, q)), 3) if len(a) else None
     out = {}
     for rate in args.serve_rates:
         count = max(50, int(rate * args.serve_seconds))
         evs = synth.event_set(400 + int(rate), count, lo=200)
         arrivals = synth.poisson_arrivals(float(rate), count, seed=1400 + int(rate))
         srv = serve.Server(ex)
-        wall = serve.run_poisson(srv, [e.x for e in evs], arrivals - arrivals[0])
+        wall = serve.run_poisson(srv, [e.x for e in evs], arrivals - arrivals[0],
+                                 prims=[e.prim for e in evs])
         srv.close()
         lat = srv.latencies_ms()
-        out[str(rate)] = {"offered_events_per_s": rate, "events": count,
-                          "events_per_s": round(count / wall, 1),
-                          "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                          "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                          "batches": srv.stats["batches"],
-                          "max_slots_in_flight": srv.stats["max_inflight_slots"]}
+        wait = srv.queue_waits_ms()
+        log = np.array(srv.batch_log, dtype=np.float64).reshape(-1, 4)
+        sizes = log[:, 0].astype(int)
+        out[str(rate)] = {
+            "offered_events_per_s": rate, "events": count, "events_per_s": round(count / wall, 1),
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "queue_wait_ms": {"p50": pct(wait, 50), "p99": pct(wait, 99)},
+            "batch_service_ms": {"p50": pct(log[:, 3] * 1e3, 50), "p99": pct(log[:, 3] * 1e3, 99)},
+            "batches": srv.stats["batches"],
+            "batch_events": {"mean": round(float(sizes.mean()), 2), "max": int(sizes.max()),
+                             "histogram": {str(k): int(v) for k, v in
+                                           zip(*np.unique(np.minimum(sizes, 16), return_counts=True))}},
+            "max_slots_in_flight": srv.stats["max_inflight_slots"],
+            "max_inflight_gb": round(srv.stats["max_inflight_bytes"] / 2**30, 3),
+            "admission_blocked": srv.stats["admission_blocked"]}
         print(f"serving {rate}/s: {out[str(rate)]}", file=sys.stderr, flush=True)
-    return {"slots": ex.slots(), "slot_bytes": ex.slot_bytes, "rates": out}
+    return {"slots": ex.slots(), "slot_gb": round(ex.slot_bytes / 2**30, 3),
+            "budget_gb": budget / 2**30, "rates": out}
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may use (the job's CPU share: the
+    OMP_NUM_THREADS limit where one is set, else the affinity mask)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    affinity = len(os.sched_getaffinity(0))
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return {"model": model, "affinity_cores": affinity, "cores": min(env, affinity) if env else affinity}
 
 
 def cpu_baseline(cfg, w, budget_s: float):
-    """The FP64 oracle on the first events of the varlen workload until the time budget is spent."""
+    """The FP64 oracle on the host's cores, twice: with all the job's cores, then with one thread,
+    each on the first events of the varlen workload (its first 64-event batch) until its time budget
+    is spent (at least one event). Returns the record and the oracle outputs of the all-core run
+    (event index -> outputs), which the error statistics compare the GPU's outputs with."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import mlpf_oracle as O
-    evs = synth.event_set(300, 64, lo=200)
-    done, t0 = 0, time.perf_counter()
-    for e in evs:
-        O.forward(e.x, w, cfg)
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", "0")) or 0)
-    cores = threads or len(os.sched_getaffinity(0))
-    return {"value": done / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {done} events of the varlen workload (seed 300), FP64 NumPy, {dt:.1f} s"}
+    cpu = host_cpu()
+    evs = synth.event_set(300, EVENTS_PER_BATCH, lo=200)
+
+    def run(threads):
+        refs = {}
+        with threadpool_limits(threads):
+            t0 = time.perf_counter()
+            for i, e in enumerate(evs):
+                refs[i] = O.forward(e.x, w, cfg)
+                if time.perf_counter() - t0 > budget_s:
+                    break
+            dt = time.perf_counter() - t0
+        n = [evs[i].n for i in refs]
+        return {"value": round(len(refs) / dt, 4), "unit": "events/s", "cores": threads,
+                "kind": "oracle", "seconds": round(dt, 2),
+                "sample": f"first {len(refs)} events of the varlen workload (seed 300; elements "
+                          f"{', '.join(map(str, n))}), FP64 NumPy, {threads} thread(s)"}, refs
+
+    rec, refs = run(cpu["cores"])
+    one, _ = run(1)
+    rec["one_thread"] = one
+    rec["host"] = cpu
+    return rec, refs
+
+
+def output_errors(refs, outs: dict, pk) -> dict:
+    """Per-output error statistics (tests/parity_util.error_stats) of each precision's outputs on
+    the events the oracle ran."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity_util import TOL, error_stats
+    res = {"events": sorted(refs), "elements": int(sum(pk.n_valid[i] for i in refs))}
+    for name, out in outs.items():
+        if out is None:
+            continue
+        tol = TOL["fp32" if name == "fp32" else "bf16"]
+        pairs = [({k: v[pk.event_rows(i)] for k, v in out.items()}, ref) for i, ref in refs.items()]
+        st = error_stats(pairs, tol)
+        res[name] = {k: ({q: (x if isinstance(x, int) else float(f"{x:.3g}")) for q, x in v.items()}
+                         if isinstance(v, dict) else v) for k, v in st.items()}
+    return res
 
 
 def main():
@@ -365,6 +433,7 @@ def main():
             "tiles": pr["tiles"]}
         print(f"bench: paper layout {pl_layout['value']} events/s", file=sys.stderr, flush=True)
     fp8 = None
+    fp8_out0 = None
     if not args.no_fp8:
         # BF16 with the FFN products in FP8-E4M3 (activation scales calibrated on the FP32 model
         # over the first batch), on the same batches.
@@ -374,6 +443,7 @@ def main():
         fargs = argparse.Namespace(**vars(args))
         fargs.steps, fargs.warmup = min(args.steps, 10), 1
         fr = bench_varlen(fargs, cfg, w, model=m8)
+        fp8_out0 = fr["out0"]
         fp8 = {"value": round(fr["events"] / fr["wall_s"], 2), "unit": "events/s",
                "ms_per_step": round(fr["wall_s"] * 1e3 / fargs.steps, 3), "steps": fargs.steps,
                "ffn_ms_per_step": round((fr["prof"]["ffn1"][0] + fr["prof"]["ffn2"][0]) / fargs.steps, 4),
@@ -428,7 +498,18 @@ def main():
     if args.serve_rates:
         line["serving"] = bench_serving(args, cfg, w)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, w, args.cpu_budget)
+        line["cpu_baseline"], refs = cpu_baseline(cfg, w, args.cpu_budget)
+        # Error per output against the oracle on the events it ran, for each precision's outputs of
+        # the first varlen batch (BF16 and FP8 from their benchmark legs, FP32 from one launch).
+        from paper_2601_17554_amd import binding as B
+        import torch
+        pk0 = make_batches(1)[0]
+        m32 = B.Model(cfg, w, "fp32")
+        o32 = m32.reconstruct(torch.from_numpy(pk0.x).cuda(), B.Batch.from_host(pk0.row_start, pk0.n_valid))
+        torch.cuda.synchronize()
+        o32 = {k: v.cpu().numpy() for k, v in o32.items()}
+        line["errors"] = output_errors(refs, {"bf16": vr["out0"], "bf16_fp8ffn": fp8_out0,
+                                              "fp32": o32}, pk0)
     print(json.dumps(line), flush=True)
 
 

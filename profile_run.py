@@ -3,7 +3,7 @@
 as bench.py does; one warm-up pass, then one forward pass per batch, then a plain device copy of
 known size whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters.
 
-    python paper_2601_17554_amd/profile_run.py [--precision bf16] [--batches 4] [--copy-mib 256]
+    python profile_run.py [--precision bf16] [--batches 4] [--copy-mib 256]
         [--tiles '{"attention": 7, ...}']
 """
 from __future__ import annotations
@@ -21,7 +21,7 @@ def main() -> None:
     ap.add_argument("--batches", type=int, default=4)
     ap.add_argument("--tiles", default="", help="JSON {op: tile} to pin (default: autotune)")
     args = ap.parse_args()
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    root = os.path.dirname(os.path.abspath(__file__))
     sys.path.insert(0, root)
     import torch
 

@@ -1,11 +1,11 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
-    python paper_2601_17554_amd/profile_summary.py stats <prefix>_kernel_stats.csv [--top 20]
-    python paper_2601_17554_amd/profile_summary.py trace <prefix>_kernel_trace.csv
+    python profile_summary.py stats <prefix>_kernel_stats.csv [--top 20]
+    python profile_summary.py trace <prefix>_kernel_trace.csv
         --kernel <name substring> --last N
-    python paper_2601_17554_amd/profile_summary.py step <prefix>_kernel_trace.csv
+    python profile_summary.py step <prefix>_kernel_trace.csv
         --marker <name substring of a step's last kernel>
-    python paper_2601_17554_amd/profile_summary.py traffic --fetch <fetch counter csv>
+    python profile_summary.py traffic --fetch <fetch counter csv>
         --write <write counter csv> --kernel <name substring> --last N [--copy-mib 256]
 
 `trace` prints the average duration of the last N dispatches of one kernel in a kernel trace.

@@ -147,7 +147,7 @@ def error_stats(pairs, tol: float, rule: str = "argmax") -> Dict[str, object]:
         a = np.concatenate(v) if v else np.zeros(1)
         out[k] = {"max": float(a.max()), "p99": float(np.percentile(a, 99)),
                   "median": float(np.median(a))}
-    out["argmax"] = {"elements": n, "raw": raw_n / max(n, 1),
+    out["argmax"] = {"elements": int(n), "raw": raw_n / max(n, 1),
                      "clear_agreement": agree_n / max(clear_n, 1),
                      "tie_fraction": 1.0 - clear_n / max(n, 1), "margin_tol": tol}
     return out

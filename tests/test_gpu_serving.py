@@ -16,12 +16,12 @@ def test_serving_alone_vs_mix():
 
     cfg = synth.FULL
     m = B.Model(cfg, synth.make_weights(cfg, 1), "bf16")
-    ex = serve.GpuExecutor(m, max_rows=16384, max_events=16, slots=3, buckets=3)
+    ex = serve.GpuExecutor(m, max_rows=16384, max_events=16, slots=3, buckets=3, decode=True)
     srv = serve.Server(ex)
     rng = np.random.default_rng(9)
     evs = [synth.make_event(700 + i, int(rng.integers(50, 1500))) for i in range(30)]
     arrivals = synth.poisson_arrivals(800.0, len(evs), seed=1200)
-    serve.run_poisson(srv, [e.x for e in evs], arrivals - arrivals[0])
+    serve.run_poisson(srv, [e.x for e in evs], arrivals - arrivals[0], prims=[e.prim for e in evs])
     srv.close()
     assert srv.stats["events"] == len(evs)
     assert srv.stats["batches"] < len(evs)          # some events shared a batch
@@ -29,10 +29,11 @@ def test_serving_alone_vs_mix():
     bitwise = 0
     for e in evs:
         pk = synth.pack([e])
-        alone = m.reconstruct(torch.from_numpy(pk.x).cuda(), B.Batch.from_host(pk.row_start, pk.n_valid))
+        alone = m.reconstruct(torch.from_numpy(pk.x).cuda(), B.Batch.from_host(pk.row_start, pk.n_valid),
+                              prim=torch.from_numpy(pk.prim).cuda())
         torch.cuda.synchronize()
         got = next(r.future.result() for r in srv.completed if r.x.shape == e.x.shape and np.array_equal(r.x, e.x))
-        for k in ("logits", "reg"):
+        for k in ("logits", "reg", "decoded"):
             ref = alone[k].cpu().numpy()
             scale = max(np.abs(ref).max(), 1e-6)
             assert np.abs(got[k] - ref).max() <= 2e-2 * scale
