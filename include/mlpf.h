@@ -192,6 +192,21 @@ mlpf_status_t mlpf_reconstruct_events(mlpf_model_t model, const float* x,
                                       int32_t* cls, const float* prim, float* decoded, void* ws,
                                       size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, hosts that forbid allocation): mlpf_reconstruct_events without the workspace argument.
+ * Its scratch is a fixed array of 128 MiB in device memory that the library holds on each GPU it
+ * runs on from its load until the process ends; the call allocates nothing (no hipMalloc, no
+ * library routine that allocates). Batches whose workspace (mlpf_workspace_bytes) exceeds 128 MiB
+ * return MLPF_ERR_CAPACITY with nothing enqueued (a d_model 256 BF16 model fits about 20,000 rows,
+ * e.g. two events of 8192 elements). Every call on one GPU uses the same scratch: calls that
+ * overlap on a GPU (on different streams, or from different threads without ordering) race and
+ * give wrong results; calls ordered on one stream are safe. Nothing in the scratch needs to start
+ * at zero. Other arguments, errors and results as mlpf_reconstruct_events (bitwise the same). */
+mlpf_status_t mlpf_reconstruct_events_noalloc(mlpf_model_t model, const float* x,
+                                              const mlpf_batch_t* batch, float* logits, float* reg,
+                                              int32_t* cls, const float* prim, float* decoded,
+                                              void* stream);
+
 /* Particle candidates per event (Sec. 5.3: at inference an element yields a particle when its
  * predicted class is a particle, with that class and the four-momentum of its heads; Sec. 8: the
  * reconstruction module turns the outputs into a list of candidates per event). From cls[T] (as

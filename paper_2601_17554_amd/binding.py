@@ -72,6 +72,7 @@ def load() -> ctypes.CDLL:
         "mlpf_encoder_forward": (st, [vp, vp, bp, vp, sz, vp]),
         "mlpf_heads": (st, [vp, vp, bp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "mlpf_reconstruct_events": (st, [vp, vp, bp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "mlpf_reconstruct_events_noalloc": (st, [vp, vp, bp, vp, vp, vp, vp, vp, vp]),
         "mlpf_profiler_enable": (st, [vp, st]),
         "mlpf_profiler_read": (st, [vp, st, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64)]),
@@ -98,7 +99,7 @@ def load() -> ctypes.CDLL:
 def exported_symbols() -> Sequence[str]:
     return ("mlpf_weights_bytes", "mlpf_weights_count", "mlpf_model_create", "mlpf_model_destroy",
             "mlpf_workspace_bytes", "mlpf_embed", "mlpf_encoder_forward", "mlpf_heads",
-            "mlpf_reconstruct_events", "mlpf_profiler_enable", "mlpf_profiler_read",
+            "mlpf_reconstruct_events", "mlpf_reconstruct_events_noalloc", "mlpf_profiler_enable", "mlpf_profiler_read",
             "mlpf_attention_forward", "mlpf_calibrate_fp8", "mlpf_graph_create", "mlpf_graph_launch",
             "mlpf_graph_destroy", "mlpf_tune_count", "mlpf_tune_set", "mlpf_tune_get",
             "mlpf_tune_shape", "mlpf_candidates", "mlpf_status_string", "mlpf_last_error")
@@ -228,6 +229,13 @@ def mlpf_reconstruct_events(model: "Model", x, batch: Batch, logits, reg, cls, p
     _check(load().mlpf_reconstruct_events(model.handle, _ptr(x), batch.c, _ptr(logits), _ptr(reg),
                                           _ptr(cls), _ptr(prim), _ptr(decoded), _ptr(ws),
                                           ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mlpf_reconstruct_events_noalloc(model: "Model", x, batch: Batch, logits, reg, cls, prim,
+                                    decoded, stream=None) -> None:
+    _check(load().mlpf_reconstruct_events_noalloc(model.handle, _ptr(x), batch.c, _ptr(logits),
+                                                  _ptr(reg), _ptr(cls), _ptr(prim), _ptr(decoded),
+                                                  _stream(stream)))
 
 
 def mlpf_attention_forward(model: "Model", q, k, v, o, batch: Batch, ws, stream=None) -> None:

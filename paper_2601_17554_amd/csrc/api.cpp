@@ -722,6 +722,34 @@ mlpf_status_t do_heads(const Ctx& cx, const void* h, float* logits, float* reg, 
   return MLPF_OK;
 }
 
+// Scratch of mlpf_reconstruct_events_noalloc: a fixed-size array in device memory, one copy per
+// GPU, held from the library's load until the process ends (each GPU the library runs on holds its
+// own). In host code `scratch` names a host-side stand-in, never the device memory: host code uses
+// only the device address hipGetSymbolAddress returns, looked up once per device with that device
+// current (at mlpf_model_create, or at the entry point's first call on a device).
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+mlpf_status_t scratch_of_current_device(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(MLPF_ERR_UNSUPPORTED, "device %d is beyond the %d devices the scratch table holds",
+                dev, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+    if (!p) return fail(MLPF_ERR_INTERNAL, "no device address for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return MLPF_OK;
+}
+
 mlpf_status_t make_ctx(mlpf_model_t m, const mlpf_batch_t* b, void* ws, size_t ws_bytes,
                        void* stream, bool need_h, Ctx* cx) {
   if (!m) return fail(MLPF_ERR_INVALID_ARG, "model is NULL");
@@ -878,6 +906,10 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
   HIP_TRY(hipMemcpyAsync(dev_weights, img.data(), plan.total, hipMemcpyHostToDevice, s),
           "weight upload");
   HIP_TRY(hipStreamSynchronize(s), "weight upload sync");
+  // Set-up of the allocation-free entry point's scratch address on this device (a failure here is
+  // reported by that entry point, which looks the address up again).
+  void* scratch_dev = nullptr;
+  (void)scratch_of_current_device(&scratch_dev);
 
   mlpf_model_s* m = new (std::nothrow) mlpf_model_s();
   if (!m) return fail(MLPF_ERR_INTERNAL, "out of host memory");
@@ -987,6 +1019,23 @@ mlpf_status_t mlpf_candidates(const mlpf_batch_t* batch, const int32_t* cls, con
   a.cap = cap;
   HIP_TRY(launch_candidates(a, (hipStream_t)stream), "candidate launch");
   return MLPF_OK;
+}
+
+mlpf_status_t mlpf_reconstruct_events_noalloc(mlpf_model_t model, const float* x,
+                                              const mlpf_batch_t* batch, float* logits, float* reg,
+                                              int32_t* cls, const float* prim, float* decoded,
+                                              void* stream) {
+  if (!model) return fail(MLPF_ERR_INVALID_ARG, "model is NULL");
+  mlpf_status_t st = check_batch(model, batch);
+  if (st) return st;
+  const size_t need = plan_ws(model, batch->total_rows, batch->n_events).total;
+  if (need > kNoAllocScratchBytes)
+    return fail(MLPF_ERR_CAPACITY, "the batch needs %zu bytes of scratch, above the %zu bytes of the "
+                "allocation-free entry point", need, kNoAllocScratchBytes);
+  void* ws = nullptr;
+  if ((st = scratch_of_current_device(&ws))) return st;
+  return mlpf_reconstruct_events(model, x, batch, logits, reg, cls, prim, decoded, ws,
+                                 kNoAllocScratchBytes, stream);
 }
 
 struct mlpf_graph_s {
