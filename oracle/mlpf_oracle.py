@@ -19,6 +19,11 @@ What it follows (arxiv 2601.17554):
     list of particle candidates per event): ``candidates`` keeps, event by event and in element
     order, the elements whose predicted class is a particle, with their class and decoded
     four-momentum.
+  * Sec. 5.3 (closing remark: partitioning the event before the correlation-building layers) and
+    Sec. 9 (sparse or block attention): with ``parts`` (a partition label per element) every
+    attention layer takes as keys of an element only the elements of its own partition (a
+    block-diagonal attention mask); everything else in the network acts on each element alone and
+    is unchanged. This is an approximation of the full-event model, not the same function.
 
 Readings where the paper is silent (each is listed with its reason in the design notes):
   * serial topology by default (one stack of L blocks read by all heads); 'parallel2' is the
@@ -96,23 +101,33 @@ def attention_matrix(q: np.ndarray, k: np.ndarray) -> np.ndarray:
     return softmax_rows(q @ k.T / math.sqrt(q.shape[-1]))
 
 
-def mha(y: np.ndarray, w_qkv, b_qkv, w_o, b_o, n_heads: int) -> np.ndarray:
-    """Multi-head self-attention over the rows of y ([N, d]); returns [N, d] (before residual)."""
+def mha(y: np.ndarray, w_qkv, b_qkv, w_o, b_o, n_heads: int, parts=None) -> np.ndarray:
+    """Multi-head self-attention over the rows of y ([N, d]); returns [N, d] (before residual).
+    With ``parts`` ([N] labels) each row attends only to the rows of its own label."""
     d = y.shape[-1]
     dh = d // n_heads
     qkv = y @ w_qkv + b_qkv
     q, k, v = qkv[:, :d], qkv[:, d:2 * d], qkv[:, 2 * d:]
-    heads = [sdpa(q[:, j * dh:(j + 1) * dh], k[:, j * dh:(j + 1) * dh], v[:, j * dh:(j + 1) * dh])
-             for j in range(n_heads)]
-    o = np.concatenate(heads, axis=-1) if heads else np.zeros_like(y)
+    if parts is None:
+        groups = [np.arange(y.shape[0])]
+    else:
+        parts = np.asarray(parts)
+        groups = [np.flatnonzero(parts == lab) for lab in np.unique(parts)]
+    o = np.zeros((y.shape[0], d))
+    for idx in groups:
+        if idx.size == 0:
+            continue
+        for j in range(n_heads):
+            c = slice(j * dh, (j + 1) * dh)
+            o[idx, c] = sdpa(q[idx, c], k[idx, c], v[idx, c])
     return o @ w_o + b_o
 
 
 def encoder_block(h: np.ndarray, p: Mapping[str, np.ndarray], n_heads: int, eps: float,
-                  act=gelu) -> np.ndarray:
+                  act=gelu, parts=None) -> np.ndarray:
     """One pre-LN transformer block: LayerNorm before attention and before the FFN."""
     y = layer_norm(h, p["ln1.gamma"], p["ln1.beta"], eps)
-    h = h + mha(y, p["W_qkv"], p["b_qkv"], p["W_o"], p["b_o"], n_heads)
+    h = h + mha(y, p["W_qkv"], p["b_qkv"], p["W_o"], p["b_o"], n_heads, parts)
     y = layer_norm(h, p["ln2.gamma"], p["ln2.beta"], eps)
     return h + act(y @ p["W_1"] + p["b_1"]) @ p["W_2"] + p["b_2"]
 
@@ -161,8 +176,9 @@ def _layer_params(w: Mapping[str, np.ndarray], layer: int) -> Dict[str, np.ndarr
     return {k[len(pre):]: v for k, v in w.items() if k.startswith(pre)}
 
 
-def forward(x: np.ndarray, weights: Mapping[str, np.ndarray], cfg) -> Dict[str, np.ndarray]:
-    """The forward pass for ONE event's valid elements x ([N, F]).
+def forward(x: np.ndarray, weights: Mapping[str, np.ndarray], cfg, parts=None) -> Dict[str, np.ndarray]:
+    """The forward pass for ONE event's valid elements x ([N, F]); ``parts`` ([N] labels, or None)
+    restricts every attention layer to the elements of the same label.
 
     Returns float64 'logits' [N, 6], 'reg' [N, 5] = (p_T', eta, sin phi, cos phi, E'),
     int32 'cls' [N] and the encoder outputs 'h_cls', 'h_reg' (identical for 'serial')."""
@@ -174,16 +190,16 @@ def forward(x: np.ndarray, weights: Mapping[str, np.ndarray], cfg) -> Dict[str, 
     if cfg.topology == "serial":
         h = h0
         for layer in range(n_layers):
-            h = encoder_block(h, _layer_params(w, layer), n_heads, eps, act)
+            h = encoder_block(h, _layer_params(w, layer), n_heads, eps, act, parts)
         h_cls = h_reg = h
     elif cfg.topology == "parallel2":
         half = n_layers // 2
         h_cls = h0
         for layer in range(half):
-            h_cls = encoder_block(h_cls, _layer_params(w, layer), n_heads, eps, act)
+            h_cls = encoder_block(h_cls, _layer_params(w, layer), n_heads, eps, act, parts)
         h_reg = h0
         for layer in range(half, n_layers):
-            h_reg = encoder_block(h_reg, _layer_params(w, layer), n_heads, eps, act)
+            h_reg = encoder_block(h_reg, _layer_params(w, layer), n_heads, eps, act, parts)
     else:
         raise ValueError(f"unknown topology {cfg.topology!r}")
     if getattr(cfg, "binary_head", False):

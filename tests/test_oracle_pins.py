@@ -515,3 +515,59 @@ def test_std_weights_columns_ill_conditioned_in_bf16():
         worst[wset] = max(cols)
     print(worst)
     assert worst["std"] > 2e-2 > 2 * worst["wide"], worst
+
+
+# ---------------------------------------------------------------- partitioned attention (Sec. 5.3, 9)
+
+def test_partitions_one_label_is_the_dense_forward():
+    """One partition holding every element: exactly the full-event model."""
+    w = synth.make_weights(TINY, 40, sharpen=4.0)
+    ev = synth.make_event(41, 23, n_features=synth.N_FEATURES)
+    dense = O.forward(ev.x, w, TINY)
+    part = O.forward(ev.x, w, TINY, parts=np.zeros(23, np.int64))
+    for k in ("logits", "reg", "cls"):
+        np.testing.assert_array_equal(part[k], dense[k])
+
+
+@pytest.mark.parametrize("cfg", [TINY, dataclasses.replace(TINY, topology="parallel2")])
+def test_partitions_equal_separate_events(cfg):
+    """Only attention couples elements, so with partitions every partition's outputs are those of
+    the dense model run on the partition's elements alone as an event of their own; a mask applied
+    to the wrong rows, or a key leaking across partitions, breaks this."""
+    w = synth.make_weights(cfg, 42, sharpen=4.0)
+    ev = synth.make_event(43, 31)
+    labels = np.random.default_rng(44).integers(0, 4, size=31)
+    part = O.forward(ev.x, w, cfg, parts=labels)
+    for lab in np.unique(labels):
+        idx = np.flatnonzero(labels == lab)
+        alone = O.forward(ev.x[idx], w, cfg)
+        for k in ("logits", "reg"):
+            np.testing.assert_allclose(part[k][idx], alone[k], rtol=1e-12, atol=1e-14)
+    dense = O.forward(ev.x, w, cfg)
+    assert np.abs(part["logits"] - dense["logits"]).max() > 1e-6  # an approximation, not the same
+
+
+def test_partitions_singletons_closed_form():
+    """Every element its own partition: each softmax row is [1] (Eq. 4), so multi-head attention
+    returns the value projection: MHA(y) = (y W_v + b_v) W_o + b_o."""
+    rng = np.random.default_rng(45)
+    n, d, heads = 9, 8, 2
+    y = rng.standard_normal((n, d))
+    w_qkv = rng.standard_normal((d, 3 * d))
+    b_qkv = rng.standard_normal(3 * d)
+    w_o, b_o = rng.standard_normal((d, d)), rng.standard_normal(d)
+    got = O.mha(y, w_qkv, b_qkv, w_o, b_o, heads, parts=np.arange(n))
+    want = (y @ w_qkv[:, 2 * d:] + b_qkv[2 * d:]) @ w_o + b_o
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+
+
+def test_partitions_permutation_equivariance():
+    """Permuting elements together with their labels permutes the outputs."""
+    w = synth.make_weights(TINY, 46, sharpen=4.0)
+    ev = synth.make_event(47, 27)
+    labels = np.random.default_rng(48).integers(0, 3, size=27)
+    perm = np.random.default_rng(49).permutation(27)
+    a = O.forward(ev.x, w, TINY, parts=labels)
+    b = O.forward(ev.x[perm], w, TINY, parts=labels[perm])
+    np.testing.assert_allclose(b["logits"], a["logits"][perm], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(b["reg"], a["reg"][perm], rtol=1e-12, atol=1e-14)
