@@ -93,21 +93,32 @@ def _timed_steps(stream, steps, fn):
     return wall, np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
 
 
-def bench_varlen(args, cfg, w, model=None):
+def bench_varlen(args, cfg, w, model=None, partition_target=None):
     """Graph-replayed varlen batches (timed region), then the same steps eagerly with the
-    per-kernel HIP-event profiler (kernel durations for the roofline)."""
+    per-kernel HIP-event profiler (kernel durations for the roofline). ``partition_target``: the
+    attention runs within (eta, phi) cells of about that many elements of each event."""
     import torch
     from paper_2601_17554_amd import autotune
     from paper_2601_17554_amd import binding as B
+    from paper_2601_17554_amd import partition
 
     if model is None:
         model = B.Model(cfg, w, args.precision)
     batches = make_batches(args.batches)
     stream = torch.cuda.Stream()
     res = {}
+
+    def device_batch(pk):
+        if partition_target is None:
+            return torch.from_numpy(pk.x).cuda(), B.Batch.from_host(pk.row_start, pk.n_valid)
+        perm, prs, pnv = partition.partition_batch(pk.x, pk.row_start, pk.n_valid, partition_target)
+        b = B.Batch.from_host(pk.row_start, pk.n_valid).with_parts(B.Batch.from_host(prs, pnv))
+        res["partitions"] = res.get("partitions", 0) + len(pnv)
+        res.setdefault("part_n", []).append(pnv)
+        return torch.from_numpy(np.ascontiguousarray(pk.x[perm])).cuda(), b
     with torch.cuda.stream(stream):
-        dev = [(torch.from_numpy(pk.x).cuda(), B.Batch.from_host(pk.row_start, pk.n_valid)) for pk in batches]
-        wss = [model.workspace(pk.total_rows, EVENTS_PER_BATCH) for pk in batches]
+        dev = [device_batch(pk) for pk in batches]
+        wss = [model.workspace(pk.total_rows, b.work_events) for pk, (_, b) in zip(batches, dev)]
         outs = [model.outputs(pk.total_rows) for pk in batches]
         stream.synchronize()
         res["tiles"] = autotune.tune(model, dev[0][0], dev[0][1], ws=wss[0], use_cache=False)
@@ -135,7 +146,9 @@ def bench_varlen(args, cfg, w, model=None):
     res["events"] = len(n_timed)
     res["flops"] = forward_flops(n_timed, cfg)
     res["attn_ms"], res["attn_launches"] = res["prof"]["attention"]
-    res["attn_flops"] = sum(attention_flops(batches[i % len(batches)].n_valid, cfg) * cfg.n_layers
+    # Attention FLOPs of what runs: sum over events (or attention partitions) of 4 d n^2.
+    units = res["part_n"] if partition_target is not None else [pk.n_valid for pk in batches]
+    res["attn_flops"] = sum(attention_flops(units[i % len(batches)], cfg) * cfg.n_layers
                             for i in range(args.steps))
     res["mean_n"] = float(n_timed.mean())
     del graphs
@@ -389,6 +402,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-layout", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
+    ap.add_argument("--no-partitioned", action="store_true")
     ap.add_argument("--serve-rates", type=int, nargs="*", default=[200, 500, 1000, 2000])
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     args = ap.parse_args()
@@ -432,6 +446,22 @@ def main():
                                         / PEAK_EXP_T_PER_S, 4),
             "tiles": pr["tiles"]}
         print(f"bench: paper layout {pl_layout['value']} events/s", file=sys.stderr, flush=True)
+    part = None
+    if not args.no_partitioned:
+        # Partitioned attention (events cut into (eta, phi) cells of about 512 elements; attention
+        # within a cell only): an approximation of the model, timed on the same batches.
+        pargs = argparse.Namespace(**vars(args))
+        pargs.steps, pargs.warmup = min(args.steps, 10), 1
+        pr = bench_varlen(pargs, cfg, w, partition_target=512)
+        a_ms = pr["attn_ms"] / max(pr["attn_launches"], 1)
+        part = {"value": round(pr["events"] / pr["wall_s"], 2), "unit": "events/s",
+                "ms_per_step": round(pr["wall_s"] * 1e3 / pargs.steps, 3), "steps": pargs.steps,
+                "cell_target": 512, "partitions_per_batch": round(pr["partitions"] / args.batches, 1),
+                "attention_avg_launch_ms": round(a_ms, 4),
+                "attention_frac_bf16_peak": round(pr["attn_flops"] / max(pr["attn_launches"], 1)
+                                                  / (a_ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"], 4),
+                "tiles": pr["tiles"]}
+        print(f"bench: partitioned {part['value']} events/s", file=sys.stderr, flush=True)
     fp8 = None
     fp8_out0 = None
     if not args.no_fp8:
@@ -494,6 +524,7 @@ def main():
         "candidates": vr["candidates"],
         "paper_layout_bf16": pl_layout,
         "bf16_fp8ffn": fp8,
+        "partitioned_bf16": part,
     }
     if args.serve_rates:
         line["serving"] = bench_serving(args, cfg, w)

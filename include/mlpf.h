@@ -115,7 +115,7 @@ typedef struct mlpf_model_s* mlpf_model_t;
  * count above max_seqlen. Without mirrors the device values are not checked on the host: the
  * kernels clamp out-of-range values into [0, total_rows] and to max_seqlen, so bad offsets cannot
  * make a kernel touch memory outside the caller's buffers (they give wrong, not unsafe, results). */
-typedef struct {
+typedef struct mlpf_batch_s {
   const int32_t* row_start;      /* device, [n_events + 1], non-decreasing, last <= total_rows */
   const int32_t* n_valid;        /* device, [n_events], or NULL: every row of an event is valid */
   const int32_t* row_start_host; /* host mirror of row_start, or NULL */
@@ -123,6 +123,17 @@ typedef struct {
   int32_t n_events;              /* >= 0 */
   int32_t total_rows;            /* T: rows of x, h and the outputs (>= row_start[n_events]) */
   int32_t max_seqlen;            /* upper bound of every event's valid count; 0..8192 */
+  /* Partitioned attention (the paper's closing remark in Sec. 5.3 on partitioning the event before
+   * the correlation-building layers; block attention, Sec. 9), or NULL. When set, it describes
+   * the attention partitions in the same form over the same rows (total_rows equal, its own
+   * attn_parts NULL): partition p is rows row_start[p] .. row_start[p] + n_valid[p] - 1, and every
+   * attention layer gives an element as keys only the elements of its partition (everything else
+   * acts on each element alone and is unchanged). The partitions must tile each event's valid rows,
+   * in order and inside the event (valid rows in no partition get unspecified outputs); with host
+   * mirrors on the batch the partitions need theirs too, and the tiling is validated
+   * (MLPF_ERR_INVALID_ARG, nothing enqueued). Workspace sizes then take n_events as the larger of
+   * the events and the partitions. */
+  const struct mlpf_batch_s* attn_parts;
 } mlpf_batch_t;
 
 /* Bytes of the device weight buffer for (cfg, precision). */
@@ -154,8 +165,9 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
 mlpf_status_t mlpf_model_destroy(mlpf_model_t model); /* does not touch dev_weights */
 
 /* Bytes of the workspace needed by any call below for a batch of at most total_rows rows, at most
- * n_events events and valid counts of at most max_seqlen (0 for a NULL model, negative sizes or
- * max_seqlen above 8192). A workspace may be reused by consecutive calls on one stream. */
+ * n_events events (or attention partitions, whichever is larger) and valid counts of at most
+ * max_seqlen (0 for a NULL model, negative sizes or max_seqlen above 8192). A workspace may be
+ * reused by consecutive calls on one stream. */
 size_t mlpf_workspace_bytes(mlpf_model_t model, int32_t total_rows, int32_t max_seqlen,
                             int32_t n_events);
 
@@ -301,7 +313,8 @@ int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule *
  * columns, bytes per operand row and k-tile, persistent (1) or one workgroup per tile (0)};
  * MLPF_OP_ATTENTION {waves per workgroup, keys per LDS stage, 32-query blocks per wave, kernel
  * kind (0: online softmax with running maxima, 1: BF16 score-bound offset, 2: the same without the
- * look-ahead QK^T product; FP32 runs kind 0),
+ * look-ahead QK^T product, 3: the look-ahead without offset registers, the next block's MFMAs
+ * interleaved with this block's exponentials, 4: as 3 in the compiler's own order; FP32 runs kind 0),
  * 0, 0}; MLPF_OP_FFN {fused (1) or two products (0), rows per workgroup, waves, double buffered,
  * persistent, pipelined}; MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
 mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);

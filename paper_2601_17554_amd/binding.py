@@ -42,10 +42,13 @@ class _Config(ctypes.Structure):
 
 
 class _Batch(ctypes.Structure):
-    _fields_ = [("row_start", ctypes.c_void_p), ("n_valid", ctypes.c_void_p),
-                ("row_start_host", ctypes.c_void_p), ("n_valid_host", ctypes.c_void_p),
-                ("n_events", ctypes.c_int32), ("total_rows", ctypes.c_int32),
-                ("max_seqlen", ctypes.c_int32)]
+    pass
+
+
+_Batch._fields_ = [("row_start", ctypes.c_void_p), ("n_valid", ctypes.c_void_p),
+                   ("row_start_host", ctypes.c_void_p), ("n_valid_host", ctypes.c_void_p),
+                   ("n_events", ctypes.c_int32), ("total_rows", ctypes.c_int32),
+                   ("max_seqlen", ctypes.c_int32), ("attn_parts", ctypes.POINTER(_Batch))]
 
 
 _lib = None
@@ -169,9 +172,10 @@ class Batch:
 
     def __init__(self, row_start: torch.Tensor, n_valid: Optional[torch.Tensor], n_events: int,
                  total_rows: int, max_seqlen: int, row_start_host: Optional[np.ndarray] = None,
-                 n_valid_host: Optional[np.ndarray] = None):
+                 n_valid_host: Optional[np.ndarray] = None, parts: Optional["Batch"] = None):
         self.row_start, self.n_valid = row_start, n_valid
         self.n_events, self.total_rows, self.max_seqlen = n_events, total_rows, max_seqlen
+        self.parts = parts  # attention partitions (mlpf_batch_t.attn_parts), a Batch, or None
         self.set_host_mirrors(row_start_host, n_valid_host)
 
     def set_host_mirrors(self, row_start_host: Optional[np.ndarray],
@@ -180,8 +184,21 @@ class Batch:
             return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
         self.row_start_host, self.n_valid_host = host(row_start_host), host(n_valid_host)
         hp = lambda a: None if a is None else a.ctypes.data
+        parts = ctypes.pointer(self.parts._c) if self.parts is not None else None
         self._c = _Batch(_ptr(self.row_start), _ptr(self.n_valid), hp(self.row_start_host),
-                         hp(self.n_valid_host), self.n_events, self.total_rows, self.max_seqlen)
+                         hp(self.n_valid_host), self.n_events, self.total_rows, self.max_seqlen,
+                         parts)
+
+    def with_parts(self, parts: Optional["Batch"]) -> "Batch":
+        """Sets the attention partitions (a Batch over the same rows, or None); returns self."""
+        self.parts = parts
+        self.set_host_mirrors(self.row_start_host, self.n_valid_host)
+        return self
+
+    @property
+    def work_events(self) -> int:
+        """The event count that sizes workspaces: the larger of events and attention partitions."""
+        return max(self.n_events, self.parts.n_events if self.parts is not None else 0)
 
     @classmethod
     def from_host(cls, row_start: np.ndarray, n_valid: Optional[np.ndarray], device="cuda",
@@ -409,7 +426,7 @@ class Model:
                     ws: Optional[torch.Tensor] = None, out: Optional[Dict[str, torch.Tensor]] = None,
                     stream=None) -> Dict[str, torch.Tensor]:
         if ws is None:
-            ws = self.workspace(batch.total_rows, batch.n_events)
+            ws = self.workspace(batch.total_rows, batch.work_events)
         if out is None:
             out = self.outputs(batch.total_rows, decode=prim is not None)
         mlpf_reconstruct_events(self, x, batch, out["logits"], out["reg"], out["cls"], prim,
@@ -420,7 +437,7 @@ class Model:
         """q, k, v: [n_heads][total_rows][d_head] tensors of the operand dtype (float32 or
         bfloat16); returns o [total_rows][d_model] (rows beyond an event's count untouched: 0)."""
         if ws is None:
-            ws = self.workspace(batch.total_rows, batch.n_events)
+            ws = self.workspace(batch.total_rows, batch.work_events)
         o = torch.zeros(batch.total_rows, self.cfg.d_model, dtype=q.dtype, device=self.device)
         mlpf_attention_forward(self, q, k, v, o, batch, ws)
         return o
@@ -428,14 +445,14 @@ class Model:
     def calibrate_fp8(self, x, batch: Batch, amax: torch.Tensor, ws=None) -> torch.Tensor:
         """Raises amax ([2 n_layers] float32, device) to the FFN input maxima on this batch."""
         if ws is None:
-            ws = self.workspace(batch.total_rows, batch.n_events)
+            ws = self.workspace(batch.total_rows, batch.work_events)
         _check(load().mlpf_calibrate_fp8(self.handle, _ptr(x), batch.c, _ptr(amax), _ptr(ws),
                                          ws.numel() * ws.element_size(), _stream(None)))
         return amax
 
     def embed(self, x, batch: Batch, ws=None) -> torch.Tensor:
         if ws is None:
-            ws = self.workspace(batch.total_rows, batch.n_events)
+            ws = self.workspace(batch.total_rows, batch.work_events)
         h = torch.empty(self.stacks, batch.total_rows, self.cfg.d_model, dtype=self.residual_dtype,
                         device=self.device)
         mlpf_embed(self, x, batch, h, ws)
@@ -448,13 +465,13 @@ class Model:
 
     def encoder(self, h: torch.Tensor, batch: Batch, ws=None) -> torch.Tensor:
         if ws is None:
-            ws = self.workspace(batch.total_rows, batch.n_events)
+            ws = self.workspace(batch.total_rows, batch.work_events)
         mlpf_encoder_forward(self, h, batch, ws)
         return h
 
     def heads(self, h: torch.Tensor, batch: Batch, prim=None, ws=None) -> Dict[str, torch.Tensor]:
         if ws is None:
-            ws = self.workspace(batch.total_rows, batch.n_events)
+            ws = self.workspace(batch.total_rows, batch.work_events)
         out = self.outputs(batch.total_rows, decode=prim is not None)
         mlpf_heads(self, h, batch, out["logits"], out["reg"], out["cls"], prim, out.get("decoded"), ws)
         return out

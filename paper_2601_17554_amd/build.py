@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmlpf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["gemm.hip", "attention.hip", "ffn.hip", "misc.hip", "candidates.hip", "api.cpp"]
+SOURCES = ["gemm.hip", "attention.hip", "ffn.hip", "ffn_fp8.hip", "misc.hip", "candidates.hip", "api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
     # Packed FP32 VALU instructions are kept out of the generated code.

@@ -79,7 +79,7 @@ struct Layer {
 struct WeightPlan {
   size_t e_w1, e_b1, e_w2, e_b2;
   size_t c_w1 = 0, c_b1 = 0, c_w2 = 0, c_b2 = 0;  // second (non-track) embedding, embed_per_type
-  bool ffn_fused = false;  // the fused BF16 FFN kernel applies (its weight images are packed)
+  bool ffn_fused = false;  // a fused FFN kernel applies (BF16, or FP8; its weight images are packed)
   bool heads_fused = false;  // the head GEMM can take the second head layer into its epilogue
   std::vector<Layer> layers;
   size_t h_w1, h_b1, h_w2, h_b2;
@@ -135,7 +135,7 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
     w.c_b2 = take(d * 4);
   }
   w.layers.resize(c.n_layers);
-  w.ffn_fused = prec == MLPF_BF16 && ffn_fused_supported(c.d_model, c.d_ff);
+  w.ffn_fused = prec != MLPF_FP32 && ffn_fused_supported(c.d_model, c.d_ff);
   w.heads_fused = prec != MLPF_FP32 && c.d_model == 256;
   for (auto& L : w.layers) {
     L.ln1g = take(d * 4);
@@ -150,9 +150,12 @@ WeightPlan plan_weights(const mlpf_config_t& c, mlpf_precision_t prec) {
     L.b1 = take(ff * 4);
     L.w2 = take(d * ff * fb);
     L.b2 = take(d * 4);
-    if (w.ffn_fused) {
+    if (w.ffn_fused && prec == MLPF_BF16) {
       L.w1p = take(ffn_pack_bytes(c.d_model, c.d_ff, 1));
       L.w2p = take(ffn_pack_bytes(c.d_model, c.d_ff, 2));
+    } else if (w.ffn_fused) {
+      L.w1p = take(ffn_fp8_pack_bytes(c.d_model, c.d_ff, 1));
+      L.w2p = take(ffn_fp8_pack_bytes(c.d_model, c.d_ff, 2));
     }
   }
   const size_t nh = n_out_heads(c);
@@ -268,15 +271,63 @@ WsPlan plan_ws(const mlpf_model_s* m, int64_t T, int64_t E) {
 
 // Size-based default tile: enough workgroups to fill 256 CUs; BF16/FP8 take the 64-byte k-tile
 // shapes (more workgroups resident per CU).
-int pick_gemm_tile(int M, int N, Prec prec) {
+int pick_gemm_tile(int M, int N, int kp_bytes, Prec prec) {
   const double wg256 = 256.0;
   const bool narrow = prec != P_F32;
   if ((double)((M + 127) / 128) * ((N + 127) / 128) >= 2 * wg256) return narrow ? 6 : 2;
   if ((double)((M + 127) / 128) * ((N + 63) / 64) >= wg256) return narrow ? 7 : 1;
-  return 0;
+  return kp_bytes % 128 ? 8 : 0;  // rows of fewer or odd 64-byte k-tiles take the 64-byte shape
 }
 
+mlpf_status_t check_layout(const mlpf_batch_t* b);
+
+// The batch and, when given, its attention partitions: each checked on its own, and with host
+// mirrors the partitions must tile every event's valid rows, in order, inside the event.
 mlpf_status_t check_batch(const mlpf_model_s* m, const mlpf_batch_t* b) {
+  (void)m;
+  mlpf_status_t st = check_layout(b);
+  if (st || !b->attn_parts) return st;
+  const mlpf_batch_t* q = b->attn_parts;
+  if (q->attn_parts) return fail(MLPF_ERR_INVALID_ARG, "attention partitions cannot have partitions");
+  if (q->total_rows != b->total_rows)
+    return fail(MLPF_ERR_INVALID_ARG, "attention partitions span %d rows, the batch %d", q->total_rows,
+                b->total_rows);
+  if ((st = check_layout(q))) return st;
+  if (!b->row_start_host) return MLPF_OK;
+  if (!q->row_start_host)
+    return fail(MLPF_ERR_INVALID_ARG, "the batch has host mirrors, its attention partitions none");
+  const int32_t *rs = b->row_start_host, *ps = q->row_start_host;
+  int e = 0, pos = 0, end = 0;  // coverage of event e's valid rows reached `pos`
+  auto valid_end = [&](int ev) { return rs[ev] + (b->n_valid ? b->n_valid_host[ev] : rs[ev + 1] - rs[ev]); };
+  if (b->n_events > 0) {
+    pos = rs[0];
+    end = valid_end(0);
+  }
+  for (int p = 0; p < q->n_events; ++p) {
+    const int pn = q->n_valid ? q->n_valid_host[p] : ps[p + 1] - ps[p];
+    if (pn == 0) continue;
+    while (e < b->n_events && pos == end) {  // event e fully covered: on to the next one
+      if (++e < b->n_events) {
+        pos = rs[e];
+        end = valid_end(e);
+      }
+    }
+    if (e >= b->n_events || ps[p] != pos || ps[p] + pn > end)
+      return fail(MLPF_ERR_INVALID_ARG, "attention partition %d (rows %d..%d) does not continue the "
+                  "valid rows of an event in order", p, ps[p], ps[p] + pn - 1);
+    pos += pn;
+  }
+  while (e < b->n_events && pos == end)
+    if (++e < b->n_events) {
+      pos = rs[e];
+      end = valid_end(e);
+    }
+  if (e < b->n_events)
+    return fail(MLPF_ERR_INVALID_ARG, "valid rows of event %d are in no attention partition", e);
+  return MLPF_OK;
+}
+
+mlpf_status_t check_layout(const mlpf_batch_t* b) {
   if (!b) return fail(MLPF_ERR_INVALID_ARG, "batch is NULL");
   if (b->n_events < 0 || b->total_rows < 0)
     return fail(MLPF_ERR_INVALID_ARG, "negative n_events or total_rows");
@@ -284,7 +335,6 @@ mlpf_status_t check_batch(const mlpf_model_s* m, const mlpf_batch_t* b) {
   if (b->max_seqlen > MLPF_MAX_SEQLEN)
     return fail(MLPF_ERR_UNSUPPORTED, "max_seqlen=%d exceeds %d", b->max_seqlen, MLPF_MAX_SEQLEN);
   if (b->n_events > 0 && !b->row_start) return fail(MLPF_ERR_INVALID_ARG, "row_start is NULL");
-  (void)m;
   // Host mirrors: the documented layout is checked before anything is enqueued.
   const int32_t* rs = b->row_start_host;
   if (!rs) return MLPF_OK;
@@ -358,7 +408,8 @@ mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a, int 
   a.m_dev = cx.n_rows;
   a.relu = cx.m->cfg.activation == MLPF_ACT_RELU;
   const int pr = prec >= 0 ? prec : (int)cx.m->kprec;
-  const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N, (Prec)pr);
+  const int eb = pr == P_F32 ? 4 : pr == P_BF16 ? 2 : 1;
+  const int tile = cx.m->tune[op] >= 0 ? cx.m->tune[op] : pick_gemm_tile(a.M, a.N, a.Kp * eb, (Prec)pr);
   HIP_TRY(launch_gemm((Prec)pr, al, ep, tile, a, cx.s), "gemm launch");
   return MLPF_OK;
 }
@@ -432,6 +483,9 @@ mlpf_status_t do_embed(const Ctx& cx, const float* x, void* h) {
   return MLPF_OK;
 }
 
+// The sanitised event table, the live row count and the attention work list. With attention
+// partitions a second launch lists the work items of the partitions instead (the first one's items
+// are overwritten; its row count is the batch's).
 mlpf_status_t do_worklist(Ctx& cx) {
   const mlpf_model_s* m = cx.m;
   WorklistArgs a;
@@ -453,6 +507,14 @@ mlpf_status_t do_worklist(Ctx& cx) {
   {
     ProfScope prof(cx.m, MLPF_PROF_WORKLIST, cx.s);
     HIP_TRY(launch_worklist(a, cx.s), "worklist launch");
+    if (const mlpf_batch_t* q = cx.b->attn_parts) {
+      a.row_start = q->row_start;
+      a.n_valid = q->n_valid;
+      a.n_events = q->n_events;
+      a.max_seqlen = q->max_seqlen;
+      a.n_rows = ctr + 2;  // unused
+      HIP_TRY(launch_worklist(a, cx.s), "worklist launch");
+    }
   }
   cx.n_rows = ctr + 1;
   return MLPF_OK;
@@ -603,6 +665,14 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
       a.ln_b = m->atf(Ln.ln1b);
       a.ln_eps = c.ln_eps;
       if (y_next_out) *y_next_out = true;
+    }
+    if (fp8) {
+      a.fp8_in_scale = 1.f / L.s_a1;
+      a.acc_scale = L.s_a1 * L.s_w1;
+      a.out_scale = 1.f / L.s_a2;
+      a.acc_scale2 = L.s_a2 * L.s_w2;
+      HIP_TRY(launch_ffn_fp8(a, cx.s), "fused FP8 FFN launch");
+      return MLPF_OK;
     }
     const int ffn_default = (c.d_ff / 64) % 2 == 0 ? 4 : 3;  // pipelined when the chunk count is even
     HIP_TRY(launch_ffn_fused(a, m->tune[MLPF_OP_FFN] > 0 ? m->tune[MLPF_OP_FFN] : ffn_default, cx.s),
@@ -757,7 +827,7 @@ mlpf_status_t make_ctx(mlpf_model_t m, const mlpf_batch_t* b, void* ws, size_t w
   if (st) return st;
   cx->m = m;
   cx->b = b;
-  cx->w = plan_ws(m, b->total_rows, b->n_events);
+  cx->w = plan_ws(m, b->total_rows, std::max(b->n_events, b->attn_parts ? b->attn_parts->n_events : 0));
   const size_t need = need_h ? cx->w.total : cx->w.h;
   if (need > 0 && !ws) return fail(MLPF_ERR_INVALID_ARG, "workspace is NULL");
   if (ws_bytes < need)
@@ -870,6 +940,8 @@ mlpf_status_t mlpf_model_create(const mlpf_config_t* cfg, mlpf_precision_t preci
       put_f32(L.b2, d);
       Lm.s_a1 = fp8_scale(act_amax[2 * l]);
       Lm.s_a2 = fp8_scale(act_amax[2 * l + 1]);
+      if (plan.ffn_fused)
+        ffn_fp8_pack(img.data() + L.w1, img.data() + L.w2, d, ff, img.data() + L.w1p, img.data() + L.w2p);
     } else {
       put_wt(L.w1, d, ff, d);
       put_f32(L.b1, ff);
@@ -1028,7 +1100,9 @@ mlpf_status_t mlpf_reconstruct_events_noalloc(mlpf_model_t model, const float* x
   if (!model) return fail(MLPF_ERR_INVALID_ARG, "model is NULL");
   mlpf_status_t st = check_batch(model, batch);
   if (st) return st;
-  const size_t need = plan_ws(model, batch->total_rows, batch->n_events).total;
+  const size_t need =
+      plan_ws(model, batch->total_rows,
+              std::max(batch->n_events, batch->attn_parts ? batch->attn_parts->n_events : 0)).total;
   if (need > kNoAllocScratchBytes)
     return fail(MLPF_ERR_CAPACITY, "the batch needs %zu bytes of scratch, above the %zu bytes of the "
                 "allocation-free entry point", need, kNoAllocScratchBytes);
@@ -1113,7 +1187,7 @@ mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile) {
   if (tile < -1 || tile >= mlpf_tune_count(op))
     return fail(MLPF_ERR_INVALID_ARG, "tile=%d out of range for op %d", tile, op);
   if (op == MLPF_OP_FFN && tile >= 1 && !model->plan.ffn_fused)
-    return fail(MLPF_ERR_UNSUPPORTED, "the fused FFN needs an MLPF_BF16 model with d_model 64, 128 or 256");
+    return fail(MLPF_ERR_UNSUPPORTED, "the fused FFN needs a BF16 or FP8 model with d_model 64, 128 or 256");
   if (op == MLPF_OP_FFN && tile == 4 && (model->cfg.d_ff / 64) % 2 != 0)
     return fail(MLPF_ERR_UNSUPPORTED, "the pipelined fused FFN needs d_ff a multiple of 128");
   if (op == MLPF_OP_HEADS && tile == 1 && !model->plan.heads_fused)

@@ -120,6 +120,7 @@ __device__ __forceinline__ float add_bf16x4(float a, float b, float c, float d, 
 // inside a group is the same for A and B, so any fixed permutation gives the same sum.
 //   F32 : 4 x v_mfma_f32_32x32x2_f32  (group = 8 k-values: half h holds k = 4h .. 4h+3)
 //   BF16: 1 x v_mfma_f32_32x32x16_bf16 (group = 16 k-values: half h holds k = 8h .. 8h+7)
+// (FP8 operands take 64-value groups, mma_fp8_k64 below.)
 template <class T>
 __device__ __forceinline__ void mma_kg(const u32x4& a, const u32x4& b, f32x16& c);
 
@@ -136,14 +137,16 @@ __device__ __forceinline__ void mma_kg<BF16>(const u32x4& a, const u32x4& b, f32
                                               __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// FP8: 2 x v_mfma_f32_32x32x16_fp8_fp8 (group = 32 k-values: half h holds k = 16h .. 16h+15; the
-// first MFMA takes bytes 0..7 of both halves, the second bytes 8..15).
-template <>
-__device__ __forceinline__ void mma_kg<FP8>(const u32x4& a, const u32x4& b, f32x16& c) {
-  const long a0 = (long)a[0] | ((long)a[1] << 32), b0 = (long)b[0] | ((long)b[1] << 32);
-  const long a1 = (long)a[2] | ((long)a[3] << 32), b1 = (long)b[2] | ((long)b[3] << 32);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, c, 0, 0, 0);
+// FP8 E4M3 k-group of 64 values on gfx950's 32x32x64 F8F6F4 MFMA (twice the FP8 rate of the
+// 32x32x16 FP8 instruction): each lane holds 32 bytes of A (row l%32) and of B (column l%32), lane
+// half h the h-th 32 k-values of the group (a0 and b0 its first 16 bytes, a1 and b1 the next 16).
+// The unscaled form: format fields 0 (E4M3 for both operands), block scales 0.
+__device__ __forceinline__ void mma_fp8_k64(const u32x4& a0, const u32x4& a1, const u32x4& b0,
+                                            const u32x4& b1, f32x16& c) {
+  typedef int i32x8 __attribute__((ext_vector_type(8)));
+  const i32x8 a = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+  const i32x8 b = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+  c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
 }
 
 // Converts E = 16 / sizeof(T) floats to one 16-byte chunk of T.

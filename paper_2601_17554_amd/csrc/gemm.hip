@@ -37,7 +37,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   constexpr bool A_FROM_F32 = (ALD != A_PLAIN);
   constexpr int A_BYTES = BM * RS, B_BYTES = BN * RS;
   constexpr bool kSplit = (T::kBytes == 4);
-  static_assert(C % 2 == 0 && FM >= 1 && FN >= 1, "bad tile");
+  static_assert(C % (T::kBytes == 1 ? 4 : 2) == 0 && FM >= 1 && FN >= 1, "bad tile");
 
   // Epilogue staging: rows of the tile, FP32, or bf16 where the output is exactly the bf16 rounding
   // of the staged value (so the rounding happens once, on the way into LDS); one pass, or one pass
@@ -173,6 +173,27 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
 #pragma unroll
         for (int b = 0; b < FN; ++b) part[a][b] = f32x16{};
     }
+    if constexpr (T::kBytes == 1) {
+      // FP8: 64-value k-groups (32x32x64 MFMA); lane half h reads the group's chunks 2h and 2h+1.
+#pragma unroll
+      for (int g = 0; g < C / 4; ++g) {
+        u32x4 af[FM][2], bf[FN][2];
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+            af[a][e] = *(const u32x4*)(As + (wm * WTM + a * 32 + i) * RS + (4 * g + 2 * h + e) * 16);
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+            bf[b][e] = *(const u32x4*)(Bs + (wn * WTN + b * 32 + i) * RS + (4 * g + 2 * h + e) * 16);
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) mma_fp8_k64(af[a][0], af[a][1], bf[b][0], bf[b][1], acc[a][b]);
+      }
+    } else {
 #pragma unroll
     for (int g = 0; g < C / 2; ++g) {
       u32x4 af[FM], bf[FN];
@@ -191,6 +212,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
           else
             mma_kg<T>(af[a], bf[b], acc[a][b]);
         }
+    }
     }
     if constexpr (kSplit) {
 #pragma unroll

@@ -83,6 +83,10 @@ struct FfnArgs {
   const void* w2p = nullptr;
   const float* b2 = nullptr;
   int relu = 0;                 // ReLU instead of GELU
+  // FP8 form (launch_ffn_fp8): y = E4M3(LN2(h) * fp8_in_scale); U = E4M3(act(acc1 * acc_scale + b1)
+  // * out_scale); h += acc2 * acc_scale2 + b2 (the per-tensor scales 1/s_a1, s_a1 s_w1, 1/s_a2,
+  // s_a2 s_w2).
+  float fp8_in_scale = 1.f, acc_scale = 1.f, out_scale = 1.f, acc_scale2 = 1.f;
   void* h = nullptr;            // bf16 [M][d_model], updated in place (sum taken in FP32)
   // Optional: the next block's LN1 of the updated h, written as bf16 [M][d_model] (the operand of
   // the next QKV projection), bitwise equal to the LayerNorm kernel's output.
@@ -99,6 +103,13 @@ void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, u
               uint16_t* w2p);
 // variant 1: 128 rows x 8 waves, double-buffered weights; 2: 64 rows x 4 waves, single-buffered.
 hipError_t launch_ffn_fused(const FfnArgs& args, int variant, hipStream_t stream);
+// The FP8-E4M3 form (persistent, 128 rows x 8 waves, LN2 always computed from h: args.y = h and
+// ln_in_g set), weights packed by ffn_fp8_pack: W1^T [d_ff][d_model] and W2^T [d_model][d_ff] E4M3
+// bytes into chunk images of 64 hidden units.
+size_t ffn_fp8_pack_bytes(int d_model, int d_ff, int which);
+void ffn_fp8_pack(const uint8_t* w1t, const uint8_t* w2t, int d_model, int d_ff, uint8_t* w1p,
+                  uint8_t* w2p);
+hipError_t launch_ffn_fp8(const FfnArgs& args, hipStream_t stream);
 
 // Attention over a device work list (see worklist).
 struct AttnArgs {

@@ -162,3 +162,59 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         B.load()
+
+
+def _parts_batch(B, events, ev_valid, parts, part_valid, total, maxlen=100, parts_mirrors=True):
+    b = _mirror_batch(B, events, ev_valid, total, maxlen)
+    q = _mirror_batch(B, parts, part_valid, total, maxlen)
+    if not parts_mirrors:
+        q.row_start_host = None
+        q.n_valid_host = None
+    b.attn_parts = ctypes.pointer(q)
+    b._keep = (b._keep, q)
+    return b
+
+
+@pytest.mark.parametrize("events,ev_valid,parts,part_valid,total,what", [
+    ([0, 10, 20], [8, 10], [0, 4, 10, 15, 20], [3, 4, 5, 5], 20, b"does not continue"),  # gap
+    ([0, 10, 20], [8, 10], [0, 10, 20], [8, 0], 20, b"in no attention partition"),  # event uncovered
+    ([0, 10, 20], [10, 10], [0, 6, 14, 20], None, 20, b"does not continue"),        # crosses events
+    ([0, 10, 20], [10, 10], [0, 5, 10, 15, 20], [5, 5, 5, 4], 20, b"no attention partition"),  # short
+    ([0, 10, 20], [10, 10], [0, 5, 10, 15, 20], None, 24, b"span"),                  # row totals differ
+    ([0, 10, 20], [10, 10], [0, 10, 5, 20], None, 20, b"decreases"),                 # bad layout
+])
+def test_attention_partition_rejections_without_gpu(events, ev_valid, parts, part_valid, total, what):
+    """Attention partitions must tile every event's valid rows in order inside the event; with host
+    mirrors the library checks it before anything is enqueued."""
+    B, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    b = _parts_batch(B, events, ev_valid, parts, part_valid, 20)
+    b.attn_parts.contents.total_rows = total
+    st = lib.mlpf_candidates(ctypes.byref(b), fake, None, fake, fake, fake, None, 4, None)
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG", lib.mlpf_last_error()
+    assert what in lib.mlpf_last_error(), lib.mlpf_last_error()
+
+
+def test_attention_partitions_need_mirrors_without_gpu():
+    B, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    b = _parts_batch(B, [0, 10], [10], [0, 5, 10], None, 10, parts_mirrors=False)
+    st = lib.mlpf_candidates(ctypes.byref(b), fake, None, fake, fake, fake, None, 4, None)
+    assert lib.mlpf_status_string(st) == b"MLPF_ERR_INVALID_ARG"
+    assert b"mirrors" in lib.mlpf_last_error()
+
+
+def test_partition_helper_tiles_events():
+    """The host partitioner (cells of about `target` elements in (eta, phi)) returns a row
+    permutation inside each event's valid rows and partitions that tile them."""
+    import numpy as np
+    from paper_2601_17554_amd import partition as P
+    evs = [synth.make_event(60 + i, n) for i, n in enumerate([1300, 5, 0, 700, 1])]
+    pk = synth.pack(evs, pad_to=64)
+    perm, prs, pnv = P.partition_batch(pk.x, pk.row_start, pk.n_valid, target=256)
+    assert sorted(perm.tolist()) == list(range(pk.total_rows))
+    for e in range(pk.n_events):
+        r = pk.event_rows(e)
+        assert set(perm[r].tolist()) == set(range(r.start, r.stop))
+    assert prs[-1] == pk.total_rows and (np.diff(prs) >= pnv).all() and (pnv > 0).all()
+    assert pnv.sum() == pk.n_valid.sum() and pnv.max() <= 256

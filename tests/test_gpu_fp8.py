@@ -47,3 +47,27 @@ def test_fp8_ffn_against_oracle(wset):
         for k in keys:
             assert e8[k] <= FP8_SANITY, (k, e8[k])
         assert agree8 >= 0.99, agree8
+
+
+@pytest.mark.parametrize("cfg", [synth.FULL, synth.SMALL,
+                                 synth.Config(d_model=128, n_heads=4, d_ff=192, n_layers=2)],
+                         ids=["d256", "d64", "d128_3chunks"])
+def test_fp8_fused_ffn_bitwise(cfg):
+    """The fused FP8 FFN (LN2, both E4M3 products on the 32x32x64 MFMA and the activation in one
+    persistent kernel) gives the bits of the two-product FP8 path (LayerNorm kernel with E4M3
+    output, FFN1 GEMM, FFN2 GEMM), on ragged events with garbage padding, including a batch where
+    every workgroup loops over several row tiles."""
+    from paper_2601_17554_amd import binding as B
+    w = synth.make_weights(cfg, 17, sharpen=2.0, **synth.WIDE)
+    calib = synth.event_set(501, 4, lo=200)
+    m = B.build_fp8_model(cfg, w, [(e.x, np.array([0, e.n], np.int32), None) for e in calib])
+    sizes = [300, 1, 129, 64, 1000] if cfg is not synth.FULL else \
+        [8192] * 8 + [4000, 3000, 2500, 2100, 1500, 777, 1, 65]
+    evs = [synth.make_event(5900 + i, n) for i, n in enumerate(sizes)]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=16)
+    fused = run_gpu(m, pk)
+    m.tune_set("ffn", 0)
+    two = run_gpu(m, pk)
+    live = np.concatenate([np.arange(pk.event_rows(e).start, pk.event_rows(e).stop) for e in range(pk.n_events)])
+    for k in ("logits", "reg", "cls"):
+        np.testing.assert_array_equal(fused[k][live], two[k][live], err_msg=k)
