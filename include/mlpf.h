@@ -313,8 +313,7 @@ int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule *
  * columns, bytes per operand row and k-tile, persistent (1) or one workgroup per tile (0)};
  * MLPF_OP_ATTENTION {waves per workgroup, keys per LDS stage, 32-query blocks per wave, kernel
  * kind (0: online softmax with running maxima, 1: BF16 score-bound offset, 2: the same without the
- * look-ahead QK^T product, 3: the look-ahead without offset registers, the next block's MFMAs
- * interleaved with this block's exponentials, 4: as 3 in the compiler's own order; FP32 runs kind 0),
+ * look-ahead QK^T product; FP32 runs kind 0),
  * 0, 0}; MLPF_OP_FFN {fused (1) or two products (0), rows per workgroup, waves, double buffered,
  * persistent, pipelined}; MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
 mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);

@@ -327,23 +327,14 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(const AttnArgs p) {
 // whose interleaving then hides the MFMA latency (the faster form at d_head 32). K and V stages of
 // 32*G keys rotate through three LDS slots: while stage s is consumed, stage s+1 is resident (the
 // look-ahead product reads it) and stage s+2 travels from global memory in registers; one barrier
-// per stage. KIND 1: look-ahead with the offset -m_q in the C operand; KIND 2: no look-ahead, no
-// offset registers (exp2(s - m_q) only when some bound exceeds 64); KIND 3: the look-ahead with the
-// offsets of KIND 2, and each step (the next block's QK^T MFMAs, this block's exponentials and PV
-// MFMAs) kept in one basic block (the last block is masked before its step, not inside the
-// previous one) whose instructions the scheduler is asked to interleave, one MFMA between groups
-// of VALU instructions, so that a wave's own exponentials run under its MFMAs; KIND 4: KIND 3
-// without the interleaving request. Each wave owns QB blocks of 32 queries. V stays row-major in LDS (one 16-byte store
+// per stage. Each wave owns QB blocks of 32 queries. V stays row-major in LDS (one 16-byte store
 // per chunk); the V^T operand of O^T = V^T P^T is read with the transposing ds_read_b64_tr_b16: in
 // each 16-lane group, lane j receives element j%4 of the 8-byte chunks addressed by lanes j/4,
 // j/4+4, j/4+8 and j/4+12 of the group, so lane s addresses row (key) s/4 and dh columns
 // 4(s%4)..4(s%4)+3 and every lane gets one dh column of four consecutive keys.
-template <int DH, int NW, int G, int QB, int OCC, int KIND>
+template <int DH, int NW, int G, int QB, int OCC, bool PIPE>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(OCC)))
 void attn_bf16_kernel(const AttnArgs p) {
-  constexpr bool PIPE = KIND != 2;      // look-ahead QK^T product
-  constexpr bool OFFC = KIND == 1;      // offset -m_q in the C operand
-  constexpr bool LATEMASK = KIND >= 3;  // the last block is masked before the step that consumes it
   constexpr int NT = NW * 64;
   constexpr int KEYS = 32 * G;        // keys per stage
   constexpr int KRS = DH * 2 + 16;    // LDS row stride of K [KEYS][DH]
@@ -386,10 +377,10 @@ void attn_bf16_kernel(const AttnArgs p) {
 
   int qi[QB];
   u32x4 qr[QB][QKG];
-  // OFFC: the offset -m_q as the QK^T MFMA's C operand (16 registers per query block). Otherwise no
+  // PIPE: the offset -m_q as the QK^T MFMA's C operand (16 registers per query block). Otherwise no
   // offset while every bound m_q <= 64 (scores, P and the sums stay far inside the FP32 and bf16
   // ranges), else exp2(s - m_q) with the offset kept once per query.
-  f32x16 cneg[OFFC ? QB : 1];
+  f32x16 cneg[PIPE ? QB : 1];
   float mq_[QB];
 #pragma unroll
   for (int j = 0; j < QB; ++j) {
@@ -409,7 +400,7 @@ void attn_bf16_kernel(const AttnArgs p) {
     // Scores are sums of DH exact products in FP32: |s - q.k| <= DH * 2^-24 |q| |k|.
     const float mq = sqrtf(qn2 * kn2) * (1.f + 0x1p-12f);
     mq_[j] = mq;
-    if constexpr (OFFC) {
+    if constexpr (PIPE) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) cneg[j][r] = -mq;
     }
@@ -539,7 +530,7 @@ void attn_bf16_kernel(const AttnArgs p) {
     if (PIPE && nblk > 0) {
       kread(0, kn);
       scores(kn, sa, c0);
-      if (!LATEMASK && nblk == 1 && (n & 31)) mask(0, sa);
+      if (nblk == 1 && (n & 31)) mask(0, sa);
     }
     if (PIPE && nblk > 1) kread(1, kn);
     // Block b of stage st (position bb) is in `cur`; the look-ahead product fills `nxt` from the
@@ -548,32 +539,18 @@ void attn_bf16_kernel(const AttnArgs p) {
     // block (unused results; no branch, so the fragment registers rotate without copies).
     auto step = [&](int st, int slot, int bb, f32x16 (&cur)[QB], f32x16 (&nxt)[QB]) {
       const int b = st * G + bb;
-      if constexpr (LATEMASK) {
-        if (b + 1 == nblk && (n & 31)) mask(b, cur);
-      }
       {
         u32x4 ka[QKG];
 #pragma unroll
         for (int c = 0; c < QKG; ++c) ka[c] = kn[c];
         kread(min(b + 2, nblk - 1), kn);
         scores(ka, nxt, c0);
-        if constexpr (!LATEMASK) {
-          if (b + 2 == nblk && (n & 31)) mask(b + 1, nxt);
-        }
+        if (b + 2 == nblk && (n & 31)) mask(b + 1, nxt);
       }
-      if constexpr (MAXPASS) {
+      if constexpr (MAXPASS)
         take_max(cur);
-      } else {
+      else
         consume(slot, bb, cur, shift_tag);
-        if constexpr (KIND == 3) {
-          // One MFMA, then a group of VALU instructions, for every MFMA of the step.
-#pragma unroll
-          for (int k = 0; k < 4 * QB; ++k) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
-          }
-        }
-      }
     };
     // Without the look-ahead (PIPE false): block b is scored and consumed in the same step, with one
     // score set fewer in registers (more waves per SIMD hide the MFMA latency instead).
@@ -616,7 +593,7 @@ void attn_bf16_kernel(const AttnArgs p) {
   f32x16 zero[QB];
 #pragma unroll
   for (int j = 0; j < QB; ++j) zero[j] = f32x16{};
-  if constexpr (OFFC) {
+  if constexpr (PIPE) {
     sweep(std::false_type{}, cneg, std::false_type{});
   } else {
     bool big = false;
@@ -645,7 +622,7 @@ void attn_bf16_kernel(const AttnArgs p) {
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
       const float mx = fmaxf(m_ex[j], other_half(m_ex[j]));
-      if constexpr (OFFC) {
+      if constexpr (PIPE) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) cneg[j][r] = -mx;
       } else {
@@ -654,7 +631,7 @@ void attn_bf16_kernel(const AttnArgs p) {
       l_run[j] = 0.f;
       oacc[j] = f32x16{};
     }
-    if constexpr (OFFC)
+    if constexpr (PIPE)
       sweep(std::false_type{}, cneg, std::false_type{});
     else
       sweep(std::false_type{}, zero, std::true_type{});
@@ -719,12 +696,6 @@ constexpr AttnTile kTiles[] = {
     {4, 64, 2, 2},
     {4, 128, 2, 2},
     {4, 64, 1, 2},
-    // the look-ahead without offset registers, one basic block per step (kind 3: MFMAs interleaved
-    // with the exponentials on request; kind 4: as the compiler schedules it)
-    {4, 64, 2, 3},
-    {4, 64, 2, 4},
-    {4, 64, 1, 3},
-    {4, 128, 2, 3},
 };
 
 template <class T, int DH, int NW, int KT, int QB>
@@ -734,14 +705,14 @@ hipError_t launch_t(const AttnArgs& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <class T, int DH, int NW, int KT, int QB, int OCC = 1, int KIND = 1>
+template <class T, int DH, int NW, int KT, int QB, int OCC = 1, bool PIPE = true>
 hipError_t launch_b(const AttnArgs& p, hipStream_t s) {
   if constexpr (!std::is_same_v<T, BF16>) {
     return launch_t<T, DH, NW, KT, QB>(p, s);
   } else {
     if (p.cap_items <= 0) return hipSuccess;
     if (p.knorm == nullptr) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((attn_bf16_kernel<DH, NW, KT / 32, QB, OCC, KIND>), dim3(p.cap_items), dim3(NW * 64),
+    hipLaunchKernelGGL((attn_bf16_kernel<DH, NW, KT / 32, QB, OCC, PIPE>), dim3(p.cap_items), dim3(NW * 64),
                        0, s, p);
     return hipGetLastError();
   }
@@ -764,13 +735,9 @@ hipError_t launch_dh(int tile, const AttnArgs& p, hipStream_t s) {
     case 11: return launch_b<T, DH, 4, 64, 1, 4>(p, s);
     case 12: return launch_b<T, DH, 2, 64, 2>(p, s);
     case 13: return launch_b<T, DH, 4, 128, 2>(p, s);
-    case 14: return launch_b<T, DH, 4, 64, 2, 3, 2>(p, s);
-    case 15: return launch_b<T, DH, 4, 128, 2, 3, 2>(p, s);
-    case 16: return launch_b<T, DH, 4, 64, 1, 4, 2>(p, s);
-    case 17: return launch_b<T, DH, 4, 64, 2, 2, 3>(p, s);
-    case 18: return launch_b<T, DH, 4, 64, 2, 2, 4>(p, s);
-    case 19: return launch_b<T, DH, 4, 64, 1, 3, 3>(p, s);
-    case 20: return launch_b<T, DH, 4, 128, 2, 2, 3>(p, s);
+    case 14: return launch_b<T, DH, 4, 64, 2, 3, false>(p, s);
+    case 15: return launch_b<T, DH, 4, 128, 2, 3, false>(p, s);
+    case 16: return launch_b<T, DH, 4, 64, 1, 4, false>(p, s);
     default: return hipErrorInvalidValue;
   }
 }
