@@ -304,7 +304,17 @@ typedef enum {
    * biases, argmax and decode (the default; bf16 models with d_model 256 only, else
    * MLPF_ERR_UNSUPPORTED). The two differ by the order of the second-layer sums (rounding). */
   MLPF_OP_HEADS = 9,
-  MLPF_OP_COUNT = 10
+  /* Key splits of the BF16 score-bound attention (kinds 1 and 2): tile t = 2^t splits (1, 2, 4,
+   * 8). With s > 1 every work item runs as s workgroups, each over one contiguous range of the
+   * event's keys, writing unnormalised partial outputs with their row sums and exponent offsets
+   * to the workspace; a second kernel combines them exactly (O = sum_s 2^(m_s - M) O_s /
+   * sum_s 2^(m_s - M) l_s). Results differ from one split by rounding. The rule (-1) splits only
+   * launches too small to fill the chip (about three waves per SIMD when the rows form one
+   * event), and never beyond 8, 4 or 2 splits for up to 4096, 8192 or 16384 rows (the
+   * workspace's partial buffers; no split beyond 16384 rows); a pinned count is capped the same
+   * way. FP32 models and kind 0 never split. */
+  MLPF_OP_ATTN_SPLIT = 10,
+  MLPF_OP_COUNT = 11
 } mlpf_op_t;
 int32_t mlpf_tune_count(int32_t op);
 mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile);
@@ -315,7 +325,8 @@ int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule *
  * kind (0: online softmax with running maxima, 1: BF16 score-bound offset, 2: the same without the
  * look-ahead QK^T product; FP32 runs kind 0),
  * 0, 0}; MLPF_OP_FFN {fused (1) or two products (0), rows per workgroup, waves, double buffered,
- * persistent, pipelined}; MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
+ * persistent, pipelined}; MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0};
+ * MLPF_OP_ATTN_SPLIT {splits, 0, 0, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
 mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);
 
 /* FP8 activation calibration for MLPF_BF16_FP8FFN. Runs the embedding and encoder of `model` (an

@@ -25,7 +25,7 @@ from . import binding as B
 # Profiler class that times each op (ops sharing a class are compared with the others fixed).
 _CLASS = {"embed1": ("embed",), "embed2": ("embed",), "qkv": ("qkv",), "outproj": ("outproj",),
           "ffn1": ("ffn1",), "ffn2": ("ffn2",), "heads1": ("heads",), "attention": ("attention",),
-          "ffn": ("ffn1", "ffn2"), "heads": ("heads",)}
+          "ffn": ("ffn1", "ffn2"), "heads": ("heads",), "attn_split": ("attention",)}
 
 # Products that a fused kernel replaces by default: (product -> op whose tile 0 runs them unfused).
 # The ops are tuned in B.OPS order, so each fused op is decided after its products' tiles.
@@ -102,7 +102,7 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
             prof = _run(model, x, batch, ws, out, reps)
             t = sum(prof[c] for c in _CLASS[op])
             # (the reference ran the fused heads, whose sums the unfused heads1 tiles reorder)
-            exact = op == "ffn" or (op not in ("attention", "heads", "heads1") and (
+            exact = op == "ffn" or (op not in ("attention", "attn_split", "heads", "heads1") and (
                 model.precision != "fp32" or B.Model.tune_shape(op, tile)["bkb"] == ref_bkb))
             ok = _same(out, ref, exact, 1e-4 if model.precision == "fp32" else 2e-2)
             if verbose:
@@ -113,6 +113,11 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
         choice[op] = best if best is not None else -1
         if parent:
             model.tune_set(parent, -1)
+        # The guard of the next ops compares with the outputs of the choices made so far (a choice
+        # that changes the rounding, such as an attention tile, moves the bitwise reference).
+        model.reconstruct(x, batch, ws=ws, out=out)
+        torch.cuda.synchronize()
+        ref = {k: v.clone() for k, v in out.items()}
     if use_cache:
         try:
             data = json.load(open(path)) if os.path.exists(path) else {}

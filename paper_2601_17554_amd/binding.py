@@ -112,7 +112,7 @@ ACTIVATIONS = {"gelu": 0, "relu": 1}
 DECISIONS = {"argmax": 0, "binary": 1}
 PROF_CLASSES = ("embed", "qkv", "attention", "outproj", "ffn1", "ffn2", "heads", "worklist")
 OPS = ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1", "attention", "ffn",
-       "heads")
+       "heads", "attn_split")
 
 
 def _status_name(s: int) -> str:
@@ -397,12 +397,14 @@ class Model:
     @staticmethod
     def tune_shape(op: str, tile: int) -> Dict[str, int]:
         """Shape of one tile: GEMM ops {bm, bn, wm, wn, bkb, persist}; attention {waves, kt, qb,
-        kind}; ffn {fused, rows, waves, double_buffered}; heads {fused, bm, bn}."""
+        kind}; ffn {fused, rows, waves, double_buffered}; heads {fused, bm, bn}; attn_split
+        {splits}."""
         v = (ctypes.c_int32 * 6)()
         _check(load().mlpf_tune_shape(OPS.index(op), tile, v))
         keys = (("waves", "kt", "qb", "kind") if op == "attention" else
                 ("fused", "rows", "waves", "double_buffered", "persistent", "pipelined") if op == "ffn" else
-                ("fused", "bm", "bn") if op == "heads"
+                ("fused", "bm", "bn") if op == "heads" else
+                ("splits",) if op == "attn_split"
                 else ("bm", "bn", "wm", "wn", "bkb", "persist"))
         return {k: int(v[i]) for i, k in enumerate(keys)}
 

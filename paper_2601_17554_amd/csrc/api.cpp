@@ -234,9 +234,15 @@ namespace {
 
 // Workspace layout for a batch of T rows and E events.
 struct WsPlan {
-  size_t ev_start, ev_n, counters, items, knorm, q, k, v, o, y, u, h, total;
+  size_t ev_start, ev_n, counters, items, knorm, q, k, v, o, y, u, h, part_o, part_ml, total;
   int cap_items;
+  int split_cap;  // most key splits the attention may use (partial buffers for that many)
 };
+
+// Key splits of the BF16 attention are for batches too small to fill the chip: at most 8, 4 or 2
+// for up to 4096, 8192 or 16384 rows, none beyond (the partial buffers then hold at most 32768
+// rows' worth of FP32 outputs).
+int attn_split_cap(int64_t T) { return T <= 4096 ? 8 : T <= 8192 ? 4 : T <= 16384 ? 2 : 1; }
 
 WsPlan plan_ws(const mlpf_model_s* m, int64_t T, int64_t E) {
   const mlpf_config_t& c = m->cfg;
@@ -265,6 +271,11 @@ WsPlan plan_ws(const mlpf_model_s* m, int64_t T, int64_t E) {
   const size_t uw = std::max<size_t>((size_t)c.d_ff, (size_t)n_out_heads(c) * c.d_model);
   w.u = take((size_t)T * uw * eb);
   w.h = take((size_t)m->stacks * td * m->hbytes);
+  w.split_cap = m->kprec == P_BF16 ? attn_split_cap(T) : 1;
+  if (w.split_cap > 1) {
+    w.part_o = take((size_t)w.split_cap * td * 4);
+    w.part_ml = take((size_t)w.split_cap * T * c.n_heads * 8);
+  }
   w.total = off;
   return w;
 }
@@ -402,6 +413,23 @@ constexpr int kDefaultAttnTileBf16 = 14;
 int attn_tile_of(const mlpf_model_s* m) {
   if (m->tune[MLPF_OP_ATTENTION] >= 0) return m->tune[MLPF_OP_ATTENTION];
   return m->kprec == P_BF16 ? kDefaultAttnTileBf16 : 0;
+}
+
+// Key splits of one attention launch over T rows: the pinned count (MLPF_OP_ATTN_SPLIT), else the
+// fewest (a power of two) that give the launch about three waves per SIMD when the rows form one
+// event (4 SIMDs x 256 CUs); only the BF16 bound-offset kernels split, within the workspace's cap.
+int attn_split_of(const mlpf_model_s* m, const WsPlan& w, int64_t T) {
+  const AttnTile at = attn_tile(attn_tile_of(m));
+  if (m->kprec != P_BF16 || at.kind < 1 || w.split_cap < 2) return 1;
+  int s = 1;
+  if (m->tune[MLPF_OP_ATTN_SPLIT] >= 0) {
+    s = 1 << m->tune[MLPF_OP_ATTN_SPLIT];
+  } else {
+    const int64_t qt = 32 * at.waves * at.qb;
+    const int64_t waves = (int64_t)m->cfg.n_heads * ((T + qt - 1) / qt) * at.waves;
+    while (s < 8 && waves * s < 3 * 4 * 256) s *= 2;
+  }
+  return std::min(s, w.split_cap);
 }
 
 mlpf_status_t run_gemm(const Ctx& cx, int op, ALoad al, Epi ep, GemmArgs a, int prec = -1) {
@@ -550,8 +578,16 @@ mlpf_status_t run_attention(const Ctx& cx, const void* q, const void* k, const v
     }
     at.knorm = kn;
   }
+  at.rows = cx.b->total_rows;
+  at.q_tile = 32 * attn_tile(tile).waves * attn_tile(tile).qb;
+  at.ksplit = attn_split_of(m, cx.w, cx.b->total_rows);
+  if (at.ksplit > 1) {
+    at.part_o = (float*)cx.p(cx.w.part_o);
+    at.part_ml = (float*)cx.p(cx.w.part_ml);
+  }
   ProfScope prof(cx.m, MLPF_PROF_ATTENTION, cx.s);
   HIP_TRY(launch_attention(m->kprec, tile, at, cx.s), "attention launch");
+  if (at.ksplit > 1) HIP_TRY(launch_attn_combine(at, cx.s), "attention combine launch");
   return MLPF_OK;
 }
 
@@ -1178,6 +1214,7 @@ int32_t mlpf_tune_count(int32_t op) {
   if (op < 0 || op >= MLPF_OP_COUNT) return 0;
   if (op == MLPF_OP_FFN) return 5;
   if (op == MLPF_OP_HEADS) return 2;
+  if (op == MLPF_OP_ATTN_SPLIT) return 4;
   return op == MLPF_OP_ATTENTION ? attn_num_tiles() : gemm_num_tiles();
 }
 
@@ -1209,6 +1246,9 @@ mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape) {
   if (op == MLPF_OP_ATTENTION) {
     const AttnTile t = attn_tile(tile);
     const int32_t v[6] = {t.waves, t.kt, t.qb, t.kind, 0, 0};
+    for (int i = 0; i < 6; ++i) shape[i] = v[i];
+  } else if (op == MLPF_OP_ATTN_SPLIT) {
+    const int32_t v[6] = {1 << tile, 0, 0, 0, 0, 0};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else if (op == MLPF_OP_HEADS) {
     const GemmTile t = gemm_tile(kHeadsTile);

@@ -349,23 +349,29 @@ void attn_bf16_kernel(const AttnArgs p) {
 
   __shared__ __attribute__((aligned(16))) char smem[3 * SLOT];
 
-  if ((int)blockIdx.x >= min(*p.n_items, p.cap_items)) return;
-  const int ev = p.items[2 * blockIdx.x], code = p.items[2 * blockIdx.x + 1];
+  // Workgroup b runs work item b % n_it over key range b / n_it of the event (split-major).
+  const int n_it = min(*p.n_items, p.cap_items);
+  if ((int)blockIdx.x >= n_it * p.ksplit) return;
+  const int item = (int)blockIdx.x % n_it, split = (int)blockIdx.x / n_it;
+  const int ev = p.items[2 * item], code = p.items[2 * item + 1];
   const int head = code & 255, qtile = code >> 8;
-  const int start = p.ev_start[ev], n = p.ev_n[ev];
+  const int start = p.ev_start[ev], n = p.ev_n[ev];  // n queries; the keys are a range of them:
+  const int nbs = (((n + 31) >> 5) + p.ksplit - 1) / p.ksplit;  // 32-key blocks per split
+  const int k0 = 32 * nbs * split;                              // this split's first key
+  const int nk = min(max(n - k0, 0), 32 * nbs);                 // and its key count
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane & 31, h = lane >> 5;
 
   const __bf16* qb = (const __bf16*)p.q + (int64_t)head * p.hstride + (int64_t)start * DH;
-  const __bf16* kb = (const __bf16*)p.k + (int64_t)head * p.hstride + (int64_t)start * DH;
-  const __bf16* vb = (const __bf16*)p.v + (int64_t)head * p.hstride + (int64_t)start * DH;
+  const __bf16* kb = (const __bf16*)p.k + (int64_t)head * p.hstride + (int64_t)(start + k0) * DH;
+  const __bf16* vb = (const __bf16*)p.v + (int64_t)head * p.hstride + (int64_t)(start + k0) * DH;
 
-  // max_k |k|^2 over the event's keys (workgroup reduction through LDS).
+  // max_k |k|^2 over this workgroup's keys (workgroup reduction through LDS).
   float kn2 = 0.f;
   {
-    const float* kn = p.knorm + (int64_t)head * (p.hstride / DH) + start;
-    for (int r = tid; r < n; r += NT) kn2 = fmaxf(kn2, kn[r]);
+    const float* kn = p.knorm + (int64_t)head * (p.hstride / DH) + start + k0;
+    for (int r = tid; r < nk; r += NT) kn2 = fmaxf(kn2, kn[r]);
     kn2 = wave_max(kn2);
     float* red = (float*)smem;
     if (lane == 0) red[wave] = kn2;
@@ -406,8 +412,8 @@ void attn_bf16_kernel(const AttnArgs p) {
     }
   }
 
-  // Bounded buffer loads: zeros past the event's last key.
-  const int run_bytes = n * DH * 2;
+  // Bounded buffer loads: zeros past the last key.
+  const int run_bytes = nk * DH * 2;
   const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc((void*)kb, (short)0, run_bytes, kBufferWord3);
   const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc((void*)vb, (short)0, run_bytes, kBufferWord3);
   auto load = [&](int st, u32x4 (&rk)[PT], u32x4 (&rv)[PT]) {
@@ -450,9 +456,9 @@ void attn_bf16_kernel(const AttnArgs p) {
       for (int c = 0; c < QKG; ++c) mma_kg<BF16>(ka[c], qr[j][c], s[j]);
     }
   };
-  // Keys at or past n get -inf (only the event's last block can hold such keys).
+  // Keys at or past nk get -inf (only the last block can hold such keys).
   auto mask = [&](int b, f32x16 (&s)[QB]) {
-    const int lim = n - 32 * b - 4 * h;  // key 32b + 4h + c_r is valid iff c_r < lim
+    const int lim = nk - 32 * b - 4 * h;  // key 32b + 4h + c_r is valid iff c_r < lim
 #pragma unroll
     for (int j = 0; j < QB; ++j)
 #pragma unroll
@@ -509,7 +515,7 @@ void attn_bf16_kernel(const AttnArgs p) {
     }
   };
 
-  const int nblk = (n + 31) >> 5;
+  const int nblk = (nk + 31) >> 5;
   const int nst = (nblk + G - 1) / G;
   // One sweep over the keys through the LDS stages; MAXPASS: maxima only.
   auto sweep = [&](auto maxpass_tag, const f32x16 (&c0)[QB], auto shift_tag) {
@@ -530,7 +536,7 @@ void attn_bf16_kernel(const AttnArgs p) {
     if (PIPE && nblk > 0) {
       kread(0, kn);
       scores(kn, sa, c0);
-      if (nblk == 1 && (n & 31)) mask(0, sa);
+      if (nblk == 1 && (nk & 31)) mask(0, sa);
     }
     if (PIPE && nblk > 1) kread(1, kn);
     // Block b of stage st (position bb) is in `cur`; the look-ahead product fills `nxt` from the
@@ -545,7 +551,7 @@ void attn_bf16_kernel(const AttnArgs p) {
         for (int c = 0; c < QKG; ++c) ka[c] = kn[c];
         kread(min(b + 2, nblk - 1), kn);
         scores(ka, nxt, c0);
-        if (b + 2 == nblk && (n & 31)) mask(b + 1, nxt);
+        if (b + 2 == nblk && (nk & 31)) mask(b + 1, nxt);
       }
       if constexpr (MAXPASS)
         take_max(cur);
@@ -559,7 +565,7 @@ void attn_bf16_kernel(const AttnArgs p) {
       u32x4 ka[QKG];
       kread(b, ka);
       scores(ka, sa, c0);
-      if (b + 1 == nblk && (n & 31)) mask(b, sa);
+      if (b + 1 == nblk && (nk & 31)) mask(b, sa);
       if constexpr (MAXPASS)
         take_max(sa);
       else
@@ -590,6 +596,8 @@ void attn_bf16_kernel(const AttnArgs p) {
     l_run[j] = 0.f;
     oacc[j] = f32x16{};
   }
+  // The exponent offset of each query's P: -cneg (PIPE), else msh once shifted, 0 before.
+  bool shifted = false;
   f32x16 zero[QB];
 #pragma unroll
   for (int j = 0; j < QB; ++j) zero[j] = f32x16{};
@@ -600,6 +608,7 @@ void attn_bf16_kernel(const AttnArgs p) {
 #pragma unroll
     for (int j = 0; j < QB; ++j) big = big || (qi[j] < n && !(mq_[j] <= 64.f));
     if (__syncthreads_or(big)) {
+      shifted = true;
 #pragma unroll
       for (int j = 0; j < QB; ++j) msh[j] = mq_[j];
       sweep(std::false_type{}, zero, std::true_type{});
@@ -613,7 +622,7 @@ void attn_bf16_kernel(const AttnArgs p) {
 #pragma unroll
   for (int j = 0; j < QB; ++j) {
     const float l_tot = l_run[j] + other_half(l_run[j]);
-    loose = loose || (qi[j] < n && !(l_tot >= 0x1p-96f) && l_tot == l_tot);
+    loose = loose || (qi[j] < n && nk > 0 && !(l_tot >= 0x1p-96f) && l_tot == l_tot);
   }
   if (__syncthreads_or(loose)) {
 #pragma unroll
@@ -631,10 +640,31 @@ void attn_bf16_kernel(const AttnArgs p) {
       l_run[j] = 0.f;
       oacc[j] = f32x16{};
     }
+    shifted = true;
     if constexpr (PIPE)
       sweep(std::false_type{}, cneg, std::false_type{});
     else
       sweep(std::false_type{}, zero, std::true_type{});
+  }
+
+  // Key split: the unnormalised O^T, with l and the offset (l = 0 for a split without keys).
+  if (p.ksplit > 1) {
+    const int nh = p.d / DH;
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      const float l_tot = l_run[j] + other_half(l_run[j]);
+      if (qi[j] < n) {
+        const int64_t prow = (int64_t)split * p.rows + start + qi[j];
+        float* po = p.part_o + prow * p.d + head * DH + 4 * h;
+#pragma unroll
+        for (int c = 0; c < DH / 8; ++c)
+          *(f32x4*)(po + 8 * c) = f32x4{oacc[j][4 * c], oacc[j][4 * c + 1], oacc[j][4 * c + 2], oacc[j][4 * c + 3]};
+        const float moff = PIPE ? -cneg[j][0] : shifted ? msh[j] : 0.f;
+        // (the lane's half from its lane id, recomputed here rather than kept through the loop)
+        if (__lane_id() < 32) *(f32x2*)(p.part_ml + (prow * nh + head) * 2) = f32x2{moff, l_tot};
+      }
+    }
+    return;
   }
 
   // O = O^T / l. Lane l holds dh = 8c + 4*(l/32) + (0..3) of query l%32 in registers 4c..4c+3.
@@ -649,6 +679,50 @@ void attn_bf16_kernel(const AttnArgs p) {
         *(u32x2*)(orow + 8 * c + 4 * h) = pack_bf16x4(oacc[j][4 * c] * inv, oacc[j][4 * c + 1] * inv,
                                                      oacc[j][4 * c + 2] * inv, oacc[j][4 * c + 3] * inv);
     }
+  }
+}
+
+// Combination of the key-split partial results of one work item (event, head, query tile) per
+// workgroup: with M the largest offset among the splits that saw keys, O = sum_s 2^(m_s - M) O_s /
+// sum_s 2^(m_s - M) l_s (splits in order), rounded to bf16. One thread per 8 values of a query.
+template <int DH>
+__global__ __launch_bounds__(256) void attn_combine_kernel(const AttnArgs p) {
+  const int n_it = min(*p.n_items, p.cap_items);
+  if ((int)blockIdx.x >= n_it) return;
+  const int ev = p.items[2 * blockIdx.x], code = p.items[2 * blockIdx.x + 1];
+  const int head = code & 255, qtile = code >> 8;
+  const int start = p.ev_start[ev], n = p.ev_n[ev];
+  const int nh = p.d / DH;
+  constexpr int CH = DH / 8;
+  for (int t = threadIdx.x; t < p.q_tile * CH; t += 256) {
+    const int qi = qtile * p.q_tile + t / CH, c = t % CH;
+    if (qi >= n) continue;
+    const int64_t row = start + qi;
+    float mmax = -INFINITY;
+    for (int s = 0; s < p.ksplit; ++s) {
+      const f32x2 ml = *(const f32x2*)(p.part_ml + (((int64_t)s * p.rows + row) * nh + head) * 2);
+      if (ml[1] > 0.f) mmax = fmaxf(mmax, ml[0]);
+    }
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float den = 0.f;
+    for (int s = 0; s < p.ksplit; ++s) {
+      const int64_t prow = (int64_t)s * p.rows + row;
+      const f32x2 ml = *(const f32x2*)(p.part_ml + (prow * nh + head) * 2);
+      if (!(ml[1] > 0.f)) continue;
+      const float w = __builtin_amdgcn_exp2f(ml[0] - mmax);
+      den = fmaf(w, ml[1], den);
+      const float* po = p.part_o + prow * p.d + head * DH + 8 * c;
+      const f32x4 a = *(const f32x4*)po, b = *(const f32x4*)(po + 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[e] = fmaf(w, a[e], acc[e]);
+        acc[4 + e] = fmaf(w, b[e], acc[4 + e]);
+      }
+    }
+    const float inv = 1.0f / den;
+    const u32x2 lo = pack_bf16x4(acc[0] * inv, acc[1] * inv, acc[2] * inv, acc[3] * inv);
+    const u32x2 hi = pack_bf16x4(acc[4] * inv, acc[5] * inv, acc[6] * inv, acc[7] * inv);
+    *(u32x4*)((__bf16*)p.o + row * p.d + head * DH + 8 * c) = u32x4{lo[0], lo[1], hi[0], hi[1]};
   }
 }
 
@@ -711,9 +785,11 @@ hipError_t launch_b(const AttnArgs& p, hipStream_t s) {
     return launch_t<T, DH, NW, KT, QB>(p, s);
   } else {
     if (p.cap_items <= 0) return hipSuccess;
-    if (p.knorm == nullptr) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((attn_bf16_kernel<DH, NW, KT / 32, QB, OCC, PIPE>), dim3(p.cap_items), dim3(NW * 64),
-                       0, s, p);
+    if (p.knorm == nullptr || p.ksplit < 1 || p.ksplit > 8 ||
+        (p.ksplit > 1 && (p.part_o == nullptr || p.part_ml == nullptr)))
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL((attn_bf16_kernel<DH, NW, KT / 32, QB, OCC, PIPE>), dim3(p.cap_items * p.ksplit),
+                       dim3(NW * 64), 0, s, p);
     return hipGetLastError();
   }
 }
@@ -762,6 +838,18 @@ hipError_t launch_keynorm(const void* k, float* out, int64_t total, int dh, hipS
     hipLaunchKernelGGL(keynorm_kernel<32>, dim3((unsigned)blocks), dim3(256), 0, s, (const __bf16*)k, out, total);
   else if (dh == 16)
     hipLaunchKernelGGL(keynorm_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, s, (const __bf16*)k, out, total);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_attn_combine(const AttnArgs& p, hipStream_t s) {
+  if (p.cap_items <= 0) return hipSuccess;
+  if (p.ksplit < 2 || p.ksplit > 8 || !p.part_o || !p.part_ml || p.q_tile <= 0) return hipErrorInvalidValue;
+  if (p.dh == 32)
+    hipLaunchKernelGGL(attn_combine_kernel<32>, dim3(p.cap_items), dim3(256), 0, s, p);
+  else if (p.dh == 16)
+    hipLaunchKernelGGL(attn_combine_kernel<16>, dim3(p.cap_items), dim3(256), 0, s, p);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -125,6 +125,16 @@ struct AttnArgs {
   const int32_t* ev_n = nullptr;
   const float* knorm = nullptr;      // BF16 kernel: [H][rows_cap] squared key norms
   int cap_items = 0;
+  // Key split (BF16 bound-offset kernel): ksplit > 1 runs every work item as ksplit workgroups,
+  // each over one contiguous range of the event's keys, writing for each of its queries the
+  // unnormalised O (part_o [ksplit][rows][d], FP32), and the exponent offset and row sum
+  // (part_ml [ksplit][rows][H], (m, l)); launch_attn_combine then forms O. Grid: ksplit x
+  // cap_items workgroups, split-major.
+  int ksplit = 1;
+  int rows = 0;       // rows of the partial buffers (the batch's total rows)
+  int q_tile = 0;     // queries per work item
+  float* part_o = nullptr;
+  float* part_ml = nullptr;
 };
 struct AttnTile {
   int waves;  // waves per workgroup
@@ -136,6 +146,8 @@ struct AttnTile {
 int attn_num_tiles();
 AttnTile attn_tile(int id);
 hipError_t launch_attention(Prec prec, int tile, const AttnArgs& args, hipStream_t stream);
+// O of every work item's valid queries from the ksplit partial results (bf16 output).
+hipError_t launch_attn_combine(const AttnArgs& args, hipStream_t stream);
 // knorm[t] = |k_t|^2 for the total = H * rows_cap rows of a bf16 [H][rows_cap][dh] K.
 hipError_t launch_keynorm(const void* k, float* knorm, int64_t total, int dh, hipStream_t stream);
 

@@ -218,3 +218,12 @@ def test_partition_helper_tiles_events():
         assert set(perm[r].tolist()) == set(range(r.start, r.stop))
     assert prs[-1] == pk.total_rows and (np.diff(prs) >= pnv).all() and (pnv > 0).all()
     assert pnv.sum() == pk.n_valid.sum() and pnv.max() <= 256
+
+
+def test_attention_split_tiles_without_gpu():
+    """The key-split op: four settings (1, 2, 4 and 8 splits), nothing beyond."""
+    B, lib = _lib()
+    assert B.Model.tune_count("attn_split") == 4
+    assert [B.Model.tune_shape("attn_split", t)["splits"] for t in range(4)] == [1, 2, 4, 8]
+    with pytest.raises(B.MlpfError, match="INVALID_ARG"):
+        B.Model.tune_shape("attn_split", 4)

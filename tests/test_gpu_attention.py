@@ -60,12 +60,17 @@ def _operands(kind, H, T, dh, spread, rng):
 @pytest.mark.parametrize("kind,spread", [("random", 1.0), ("random", 3.0), ("shifted", 0.5),
                                          ("loose", 0.5)], ids=["flat", "sharp", "shifted", "loose"])
 def test_attention_alone(B, prec, cfg, kind, spread):
+    # The rule splits this small launch's keys (BF16); split tile 0 runs it unsplit.
     _attention_case(B, prec, cfg, kind, spread, tile=-1)
+    if prec == "bf16":
+        _attention_case(B, prec, cfg, kind, spread, tile=-1, split=0)
 
 
-def _attention_case(B, prec, cfg, kind, spread, tile):
+SIZES = [1, 2, 5, 31, 33, 64, 65, 100, 130, 300]
+
+
+def _attention_case(B, prec, cfg, kind, spread, tile, split=-1, sizes=SIZES):
     import torch
-    sizes = [1, 2, 5, 31, 33, 64, 65, 100, 130, 300]
     rs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
     T, H, dh = int(rs[-1]), cfg.n_heads, cfg.d_head
     rng = np.random.default_rng(7)
@@ -74,6 +79,7 @@ def _attention_case(B, prec, cfg, kind, spread, tile):
         q, k, v = _bf16(q), _bf16(k), _bf16(v)
     m = B.Model(cfg, synth.make_weights(cfg, 0), prec)
     m.tune_set("attention", tile)
+    m.tune_set("attn_split", split)
     tdt = torch.float32 if prec == "fp32" else torch.bfloat16
     dq, dk, dv = (torch.from_numpy(a).to(tdt).cuda() for a in (q, k, v))
     batch = B.Batch.from_host(rs, None)
@@ -100,8 +106,10 @@ def _attention_case(B, prec, cfg, kind, spread, tile):
                 # much smaller): negligible but for the "low" family's |s| ~ 200.
                 sv = np.abs(qs[j, r].astype(np.float64) @ k[j, r].astype(np.float64).T).max()
                 tol += 4 * 2.0 ** -24 * sv * math.log(2) * np.abs(v[j, r]).max() / max(np.abs(ref).max(), 1e-6)
-            assert err <= tol, f"tile {tile} event {e} (n={sizes[e]}) head {j}: {err:.3e} > {tol:.3e}"
-    print(f"{prec} dh={dh} {kind} spread={spread} tile {tile}: worst normwise error {worst:.2e}")
+            assert err <= tol, (f"tile {tile} split {split} event {e} (n={sizes[e]}) head {j}: "
+                                f"{err:.3e} > {tol:.3e}")
+    print(f"{prec} dh={dh} {kind} spread={spread} tile {tile} split {split}: worst normwise error "
+          f"{worst:.2e}")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -111,4 +119,19 @@ def test_attention_every_tile(B, prec, kind, spread):
     """Every attention kernel shape the tuner may pick, on the head size of the full model."""
     from paper_2601_17554_amd import binding
     for tile in range(binding.Model.tune_count("attention")):
-        _attention_case(B, prec, synth.FULL, kind, spread, tile)
+        _attention_case(B, prec, synth.FULL, kind, spread, tile, split=0)
+        if prec == "bf16" and binding.Model.tune_shape("attention", tile)["kind"] >= 1:
+            for split in (1, 3):  # 2 and 8 key splits
+                _attention_case(B, prec, synth.FULL, kind, spread, tile, split=split)
+
+
+@pytest.mark.parametrize("cfg", [synth.FULL, synth.SMALL], ids=["dh32", "dh16"])
+@pytest.mark.parametrize("kind,spread", [("random", 3.0), ("loose", 0.5), ("low", 0.3)],
+                         ids=["sharp", "loose", "low"])
+def test_attention_key_split_long_events(B, cfg, kind, spread):
+    """Key splits over events of several LDS stages per split (2, 4 and 8 splits of 2000, 1500
+    and 17 keys, the last event leaving most splits empty), on the default tile and the
+    look-ahead tile, against the oracle."""
+    for tile in (-1, 8):
+        for split in (1, 2, 3):
+            _attention_case(B, "bf16", cfg, kind, spread, tile, split=split, sizes=[2000, 1500, 17])
