@@ -294,8 +294,16 @@ typedef enum {
    * is not a multiple of 128; 4: as 3, software-pipelined: the GELU of one 64-unit chunk runs
    * beside the first product of the next, d_ff a multiple of 128 only, the default there), for
    * MLPF_BF16 models with d_model 64, 128 or 256, bitwise equal
-   * to tile 0 with any GEMM tiles. Setting 1 to 4 on another model returns MLPF_ERR_UNSUPPORTED.
-   * FP8 calibration always runs the two products. */
+   * to tile 0 with any GEMM tiles; tiles 5 to 8 = the shape of 2 with the hidden units split into
+   * 2, 4, 8 or 16 equal parts (a divisor of d_ff / 64, else MLPF_ERR_UNSUPPORTED), one workgroup
+   * per (64-row tile, part) writing its FP32 partial product to the workspace, then a kernel that
+   * adds the parts in order, the bias and the residual (and the next block's LN1): for launches
+   * too small to fill the chip; results differ from tile 0 by the rounding of the partial sums.
+   * The part count is capped like the attention's key splits (8, 4 or 2 for up to 4096, 8192 or
+   * 16384 rows; beyond, tiles 5 to 8 run as tile 2). The rule (-1) splits when the rows fit under
+   * that cap, into the fewest parts that give two workgroups per CU, else runs tile 4 (or 3).
+   * Setting 1 to 8 on another model returns MLPF_ERR_UNSUPPORTED. FP8 calibration always runs
+   * the two products. */
   MLPF_OP_FFN = 8,
   /* How the output heads run: tile 0 = the first-layer product (tiles of MLPF_OP_HEADS1 apply)
    * writing the five GELU hidden layers, then a kernel for the second layer, argmax and decode;
@@ -324,8 +332,9 @@ int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule *
  * MLPF_OP_ATTENTION {waves per workgroup, keys per LDS stage, 32-query blocks per wave, kernel
  * kind (0: online softmax with running maxima, 1: BF16 score-bound offset, 2: the same without the
  * look-ahead QK^T product; FP32 runs kind 0),
- * 0, 0}; MLPF_OP_FFN {fused (1) or two products (0), rows per workgroup, waves, double buffered,
- * persistent, pipelined}; MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0};
+ * 0, 0}; MLPF_OP_FFN {hidden-unit parts of one fused kernel (1: all at once, 2 to 16: split) or 0
+ * for two products, rows per workgroup, waves, double buffered, persistent, pipelined};
+ * MLPF_OP_HEADS {fused (1) or not (0), rows and columns of the fused tile, 0, 0, 0};
  * MLPF_OP_ATTN_SPLIT {splits, 0, 0, 0, 0, 0}. MLPF_ERR_INVALID_ARG for an op or tile out of range or a NULL shape. */
 mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape);
 

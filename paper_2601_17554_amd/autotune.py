@@ -3,11 +3,13 @@
 For one workload (model, device batch), every op's tile shapes (mlpf_tune_count) are timed with the
 library's HIP-event profiler while the other ops keep their current choice; the fastest shape that
 passes the correctness guard is pinned with mlpf_tune_set. The guard compares the final outputs of
-each candidate with the reference run: GEMM tiles must give bitwise identical outputs where the
-library guarantees it (BF16 and FP8 always; FP32 for equal k-tile lengths), and otherwise agree to
-the rounding level of the precision (relative to the output scale: 1e-4 in FP32, 2e-2 in BF16 and
-FP8), as attention tiles must (they change only the order and offsets of the softmax sums) and
-the fused heads (the order of the second-layer sums). Choices are cached in a JSON file
+each candidate with a reference run under the choices made so far (with the op's product unfused,
+and the two-product FFN for the FFN's shapes): GEMM tiles and the fused FFN shapes must give
+bitwise identical outputs where the library guarantees it (BF16 and FP8 always; FP32 for equal
+k-tile lengths), and otherwise agree to the rounding level of the precision (relative to the
+output scale: 1e-4 in FP32, 2e-2 in BF16 and FP8), as attention tiles and key splits must (they
+change only the order and offsets of the softmax sums), the split FFN shapes (the order of the
+partial sums) and the fused heads (the order of the second-layer sums). Choices are cached in a JSON file
 (``MLPF_AUTOTUNE_CACHE``, default ``~/.cache/mlpf_autotune.json``) keyed by GPU architecture,
 precision, model sizes and the batch's size bucket.
 """
@@ -25,7 +27,9 @@ from . import binding as B
 # Profiler class that times each op (ops sharing a class are compared with the others fixed).
 _CLASS = {"embed1": ("embed",), "embed2": ("embed",), "qkv": ("qkv",), "outproj": ("outproj",),
           "ffn1": ("ffn1",), "ffn2": ("ffn2",), "heads1": ("heads",), "attention": ("attention",),
-          "ffn": ("ffn1", "ffn2"), "heads": ("heads",), "attn_split": ("attention",)}
+          # the FFN's shapes also decide whether LN2 and the next LN1 run as kernels of their own
+          # (timed with the output projection and the Q/K/V projection) or inside the FFN
+          "ffn": ("ffn1", "ffn2", "outproj", "qkv"), "heads": ("heads",), "attn_split": ("attention",)}
 
 # Products that a fused kernel replaces by default: (product -> op whose tile 0 runs them unfused).
 # The ops are tuned in B.OPS order, so each fused op is decided after its products' tiles.
@@ -84,9 +88,6 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
     out = model.outputs(batch.total_rows)
     for op in B.OPS:
         model.tune_set(op, -1)
-    model.reconstruct(x, batch, ws=ws, out=out)
-    torch.cuda.synchronize()
-    ref = {k: v.clone() for k, v in out.items()}
     ref_bkb = B.Model.tune_shape("qkv", 0)["bkb"]  # FP32: the size-based rule picks among tiles 0..2
     choice: Dict[str, int] = {}
     for op in B.OPS:
@@ -94,6 +95,13 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
         parent = _UNFUSED.get(op)
         if parent:  # time the product's tiles with the fused kernel that replaces it switched off
             model.tune_set(parent, 0)
+        if op == "ffn":  # the fused FFN shapes are bitwise equal to the two-product FFN (tile 0)
+            model.tune_set(op, 0)
+        # The guard's reference: the outputs of the choices made so far, with this op's product
+        # unfused (a choice that changes the rounding, such as an attention tile, moves the bits).
+        model.reconstruct(x, batch, ws=ws, out=out)
+        torch.cuda.synchronize()
+        ref = {k: v.clone() for k, v in out.items()}
         for tile in range(B.Model.tune_count(op)):
             try:
                 model.tune_set(op, tile)
@@ -102,7 +110,9 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
             prof = _run(model, x, batch, ws, out, reps)
             t = sum(prof[c] for c in _CLASS[op])
             # (the reference ran the fused heads, whose sums the unfused heads1 tiles reorder)
-            exact = op == "ffn" or (op not in ("attention", "attn_split", "heads", "heads1") and (
+            # (the FFN's split tiles add partial products: rounding, not bits)
+            exact = (op == "ffn" and B.Model.tune_shape(op, tile)["fused"] <= 1) or (
+                op not in ("ffn", "attention", "attn_split", "heads", "heads1") and (
                 model.precision != "fp32" or B.Model.tune_shape(op, tile)["bkb"] == ref_bkb))
             ok = _same(out, ref, exact, 1e-4 if model.precision == "fp32" else 2e-2)
             if verbose:
@@ -113,11 +123,6 @@ def tune(model: B.Model, x: torch.Tensor, batch: B.Batch, ws: Optional[torch.Ten
         choice[op] = best if best is not None else -1
         if parent:
             model.tune_set(parent, -1)
-        # The guard of the next ops compares with the outputs of the choices made so far (a choice
-        # that changes the rounding, such as an attention tile, moves the bitwise reference).
-        model.reconstruct(x, batch, ws=ws, out=out)
-        torch.cuda.synchronize()
-        ref = {k: v.clone() for k, v in out.items()}
     if use_cache:
         try:
             data = json.load(open(path)) if os.path.exists(path) else {}

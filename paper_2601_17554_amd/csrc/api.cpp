@@ -596,6 +596,27 @@ bool ffn_fused_on(const mlpf_model_s* m) {
   return m->plan.ffn_fused && m->tune[MLPF_OP_FFN] != 0;
 }
 
+// FFN tiles 5 to 8 and 9 to 12: the 64-row and the 128-row fused shapes with the hidden units in
+// 2, 4, 8 or 16 parts.
+int ffn_tile_parts(int t) { return t >= 9 ? 1 << (t - 8) : t >= 5 ? 1 << (t - 4) : t > 0; }
+
+// Parts of the hidden units a fused FFN over T rows is split into (the tile's, or the rule's: the
+// fewest, a power of two, that give two 64-row workgroups per CU), within the workspace's partial
+// buffers and dividing the 64-unit chunk count; 1 = no split.
+int ffn_split_of(const mlpf_model_s* m, const WsPlan& w, int64_t T) {
+  const int t = m->tune[MLPF_OP_FFN];
+  int s = 1;
+  if (t >= 5) {
+    s = ffn_tile_parts(t);
+  } else if (t == -1) {
+    const int64_t row_tiles = (T + 63) / 64;
+    while (s < 16 && row_tiles * s < 2 * 256) s *= 2;
+  }
+  s = std::min(s, w.split_cap);
+  while (s > 1 && (m->cfg.d_ff / 64) % s) s /= 2;
+  return s;
+}
+
 // One encoder block. y_ready: y already holds LN1(h) (written by the previous block's fused FFN).
 // *y_next_out: set when this block's fused FFN also wrote the next block's LN1 into y.
 mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
@@ -711,8 +732,14 @@ mlpf_status_t do_layer(const Ctx& cx, int layer, void* h, bool y_ready = false,
       return MLPF_OK;
     }
     const int ffn_default = (c.d_ff / 64) % 2 == 0 ? 4 : 3;  // pipelined when the chunk count is even
-    HIP_TRY(launch_ffn_fused(a, m->tune[MLPF_OP_FFN] > 0 ? m->tune[MLPF_OP_FFN] : ffn_default, cx.s),
-            "fused FFN launch");
+    const int tune = m->tune[MLPF_OP_FFN];
+    int variant = tune >= 9 ? 1 : tune >= 5 ? 2 : tune > 0 ? tune : ffn_default;
+    a.split = ffn_split_of(m, cx.w, T);
+    if (a.split > 1) {
+      a.part = (float*)cx.p(cx.w.part_o);
+      variant = tune >= 9 ? 6 : 5;
+    }
+    HIP_TRY(launch_ffn_fused(a, variant, cx.s), "fused FFN launch");
     return MLPF_OK;
   }
   {
@@ -1212,7 +1239,7 @@ mlpf_status_t mlpf_graph_destroy(mlpf_graph_t graph) {
 
 int32_t mlpf_tune_count(int32_t op) {
   if (op < 0 || op >= MLPF_OP_COUNT) return 0;
-  if (op == MLPF_OP_FFN) return 5;
+  if (op == MLPF_OP_FFN) return 13;
   if (op == MLPF_OP_HEADS) return 2;
   if (op == MLPF_OP_ATTN_SPLIT) return 4;
   return op == MLPF_OP_ATTENTION ? attn_num_tiles() : gemm_num_tiles();
@@ -1225,6 +1252,9 @@ mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile) {
     return fail(MLPF_ERR_INVALID_ARG, "tile=%d out of range for op %d", tile, op);
   if (op == MLPF_OP_FFN && tile >= 1 && !model->plan.ffn_fused)
     return fail(MLPF_ERR_UNSUPPORTED, "the fused FFN needs a BF16 or FP8 model with d_model 64, 128 or 256");
+  if (op == MLPF_OP_FFN && tile >= 5 && (model->cfg.d_ff / 64) % ffn_tile_parts(tile) != 0)
+    return fail(MLPF_ERR_UNSUPPORTED, "the split FFN needs d_ff / 64 divisible by its part count %d",
+                ffn_tile_parts(tile));
   if (op == MLPF_OP_FFN && tile == 4 && (model->cfg.d_ff / 64) % 2 != 0)
     return fail(MLPF_ERR_UNSUPPORTED, "the pipelined fused FFN needs d_ff a multiple of 128");
   if (op == MLPF_OP_HEADS && tile == 1 && !model->plan.heads_fused)
@@ -1255,8 +1285,10 @@ mlpf_status_t mlpf_tune_shape(int32_t op, int32_t tile, int32_t* shape) {
     const int32_t v[6] = {tile, tile ? t.bm : 0, tile ? t.bn : 0, 0, 0, 0};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else if (op == MLPF_OP_FFN) {
-    const int rows = tile == 2 ? 64 : tile > 0 ? 128 : 0, waves = tile == 2 ? 4 : tile > 0 ? 8 : 0;
-    const int32_t v[6] = {tile > 0, rows, waves, tile != 0 && tile != 2, tile >= 3, tile == 4};
+    const bool narrow = tile == 2 || (tile >= 5 && tile <= 8);  // 64 rows, 4 waves, single-buffered
+    const int rows = narrow ? 64 : tile > 0 ? 128 : 0, waves = narrow ? 4 : tile > 0 ? 8 : 0;
+    const int parts = ffn_tile_parts(tile);
+    const int32_t v[6] = {parts, rows, waves, tile != 0 && !narrow, tile == 3 || tile == 4, tile == 4};
     for (int i = 0; i < 6; ++i) shape[i] = v[i];
   } else {
     const GemmTile t = gemm_tile(tile);

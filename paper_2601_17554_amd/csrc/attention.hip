@@ -371,7 +371,14 @@ void attn_bf16_kernel(const AttnArgs p) {
   float kn2 = 0.f;
   {
     const float* kn = p.knorm + (int64_t)head * (p.hstride / DH) + start + k0;
-    for (int r = tid; r < nk; r += NT) kn2 = fmaxf(kn2, kn[r]);
+    // Eight independent loads in flight per thread and round (one memory latency per round).
+    for (int r0 = tid; r0 < nk; r0 += 8 * NT) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = r0 + u * NT < nk ? kn[r0 + u * NT] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) kn2 = fmaxf(kn2, v[u]);
+    }
     kn2 = wave_max(kn2);
     float* red = (float*)smem;
     if (lane == 0) red[wave] = kn2;
@@ -684,8 +691,9 @@ void attn_bf16_kernel(const AttnArgs p) {
 
 // Combination of the key-split partial results of one work item (event, head, query tile) per
 // workgroup: with M the largest offset among the splits that saw keys, O = sum_s 2^(m_s - M) O_s /
-// sum_s 2^(m_s - M) l_s (splits in order), rounded to bf16. One thread per 8 values of a query.
-template <int DH>
+// sum_s 2^(m_s - M) l_s (splits in order), rounded to bf16. One thread per 8 values of a query;
+// all of a thread's loads are issued before any result is used.
+template <int DH, int S>
 __global__ __launch_bounds__(256) void attn_combine_kernel(const AttnArgs p) {
   const int n_it = min(*p.n_items, p.cap_items);
   if ((int)blockIdx.x >= n_it) return;
@@ -698,25 +706,32 @@ __global__ __launch_bounds__(256) void attn_combine_kernel(const AttnArgs p) {
     const int qi = qtile * p.q_tile + t / CH, c = t % CH;
     if (qi >= n) continue;
     const int64_t row = start + qi;
-    float mmax = -INFINITY;
-    for (int s = 0; s < p.ksplit; ++s) {
-      const f32x2 ml = *(const f32x2*)(p.part_ml + (((int64_t)s * p.rows + row) * nh + head) * 2);
-      if (ml[1] > 0.f) mmax = fmaxf(mmax, ml[0]);
+    f32x2 ml[S];
+    f32x4 oa[S], ob[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int64_t prow = (int64_t)s * p.rows + row;
+      ml[s] = *(const f32x2*)(p.part_ml + (prow * nh + head) * 2);
+      const float* po = p.part_o + prow * p.d + head * DH + 8 * c;
+      oa[s] = *(const f32x4*)po;
+      ob[s] = *(const f32x4*)(po + 4);
     }
+    float mmax = -INFINITY;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      if (ml[s][1] > 0.f) mmax = fmaxf(mmax, ml[s][0]);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float den = 0.f;
-    for (int s = 0; s < p.ksplit; ++s) {
-      const int64_t prow = (int64_t)s * p.rows + row;
-      const f32x2 ml = *(const f32x2*)(p.part_ml + (prow * nh + head) * 2);
-      if (!(ml[1] > 0.f)) continue;
-      const float w = __builtin_amdgcn_exp2f(ml[0] - mmax);
-      den = fmaf(w, ml[1], den);
-      const float* po = p.part_o + prow * p.d + head * DH + 8 * c;
-      const f32x4 a = *(const f32x4*)po, b = *(const f32x4*)(po + 4);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      // Splits without keys (l = 0) weigh nothing; their O values are not read into the sums.
+      const bool live = ml[s][1] > 0.f;
+      const float w = live ? __builtin_amdgcn_exp2f(ml[s][0] - mmax) : 0.f;
+      den = fmaf(w, ml[s][1], den);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        acc[e] = fmaf(w, a[e], acc[e]);
-        acc[4 + e] = fmaf(w, b[e], acc[4 + e]);
+        acc[e] = live ? fmaf(w, oa[s][e], acc[e]) : acc[e];
+        acc[4 + e] = live ? fmaf(w, ob[s][e], acc[4 + e]) : acc[4 + e];
       }
     }
     const float inv = 1.0f / den;
@@ -785,7 +800,7 @@ hipError_t launch_b(const AttnArgs& p, hipStream_t s) {
     return launch_t<T, DH, NW, KT, QB>(p, s);
   } else {
     if (p.cap_items <= 0) return hipSuccess;
-    if (p.knorm == nullptr || p.ksplit < 1 || p.ksplit > 8 ||
+    if (p.knorm == nullptr || (p.ksplit != 1 && p.ksplit != 2 && p.ksplit != 4 && p.ksplit != 8) ||
         (p.ksplit > 1 && (p.part_o == nullptr || p.part_ml == nullptr)))
       return hipErrorInvalidValue;
     hipLaunchKernelGGL((attn_bf16_kernel<DH, NW, KT / 32, QB, OCC, PIPE>), dim3(p.cap_items * p.ksplit),
@@ -845,13 +860,21 @@ hipError_t launch_keynorm(const void* k, float* out, int64_t total, int dh, hipS
 
 hipError_t launch_attn_combine(const AttnArgs& p, hipStream_t s) {
   if (p.cap_items <= 0) return hipSuccess;
-  if (p.ksplit < 2 || p.ksplit > 8 || !p.part_o || !p.part_ml || p.q_tile <= 0) return hipErrorInvalidValue;
-  if (p.dh == 32)
-    hipLaunchKernelGGL(attn_combine_kernel<32>, dim3(p.cap_items), dim3(256), 0, s, p);
-  else if (p.dh == 16)
-    hipLaunchKernelGGL(attn_combine_kernel<16>, dim3(p.cap_items), dim3(256), 0, s, p);
-  else
+  if ((p.ksplit != 2 && p.ksplit != 4 && p.ksplit != 8) || !p.part_o || !p.part_ml || p.q_tile <= 0)
     return hipErrorInvalidValue;
+  if (p.dh != 32 && p.dh != 16) return hipErrorInvalidValue;
+  auto go = [&](auto dh_tag) {
+    constexpr int DH = decltype(dh_tag)::value;
+    switch (p.ksplit) {
+      case 2: hipLaunchKernelGGL((attn_combine_kernel<DH, 2>), dim3(p.cap_items), dim3(256), 0, s, p); break;
+      case 4: hipLaunchKernelGGL((attn_combine_kernel<DH, 4>), dim3(p.cap_items), dim3(256), 0, s, p); break;
+      default: hipLaunchKernelGGL((attn_combine_kernel<DH, 8>), dim3(p.cap_items), dim3(256), 0, s, p); break;
+    }
+  };
+  if (p.dh == 32)
+    go(std::integral_constant<int, 32>{});
+  else
+    go(std::integral_constant<int, 16>{});
   return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@
 // of the unfused products, so the results match the two-GEMM path bit for bit. Two shapes: 128 rows
 // per workgroup of 8 waves with double-buffered weights, or 64 rows per workgroup of 4 waves with
 // single-buffered weights (two workgroups per CU).
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -156,12 +158,14 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane & 31, h = lane >> 5;
-  const int nch = p.d_ff / kFfnHC;
+  // Hidden chunks c0 .. c1-1: all of them, or part blockIdx.y of p.split equal parts.
+  const int per = p.d_ff / kFfnHC / p.split;
+  const int c0 = per * (int)blockIdx.y, c1 = c0 + per;
   const char* w1p = (const char*)p.w1p;
   const char* w2p = (const char*)p.w2p;
 
-  copy_to_lds<NT>(w1p, w1buf, L::W1CH, wave, lane);
-  copy_to_lds<NT>(w2p, w2buf, L::W2CH, wave, lane);
+  copy_to_lds<NT>(w1p + (size_t)c0 * L::W1CH, w1buf, L::W1CH, wave, lane);
+  copy_to_lds<NT>(w2p + (size_t)c0 * L::W2CH, w2buf, L::W2CH, wave, lane);
 
   // Phase-1 role: hidden block hb (32 units of the chunk) x token block tb (32 rows).
   const int hb = wave / (BM / 32), tb = wave % (BM / 32);
@@ -200,17 +204,17 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) bq_next[q] = *(const f32x4*)(b1 + 8 * q);
   };
-  load_b1(0);
+  load_b1(c0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  for (int c = 0; c < nch; ++c) {
-    const int buf = DBUF ? (c & 1) : 0;
+  for (int c = c0; c < c1; ++c) {
+    const int buf = DBUF ? ((c - c0) & 1) : 0;
     f32x4 bq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) bq[q] = bq_next[q];
-    if (c + 1 < nch) load_b1(c + 1);
-    if (DBUF && c + 1 < nch) {
+    if (c + 1 < c1) load_b1(c + 1);
+    if (DBUF && c + 1 < c1) {
       copy_to_lds<NT>(w1p + (size_t)(c + 1) * L::W1CH, w1buf + (buf ^ 1) * L::W1CH, L::W1CH, wave, lane);
       copy_to_lds<NT>(w2p + (size_t)(c + 1) * L::W2CH, w2buf + (buf ^ 1) * L::W2CH, L::W2CH, wave, lane);
     }
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
       }
     }
     __syncthreads();
-    if (!DBUF && c + 1 < nch)  // W1 is free once every wave is past phase 1
+    if (!DBUF && c + 1 < c1)  // W1 is free once every wave is past phase 1
       copy_to_lds<NT>(w1p + (size_t)(c + 1) * L::W1CH, w1buf, L::W1CH, wave, lane);
     // Phase 2: O += U W2_c over the chunk's k-groups in order.
     {
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
           for (int b = 0; b < FN2; ++b) mma_kg<BF16>(af[a], bf[b], acc[a][b]);
       }
     }
-    if (!DBUF && c + 1 < nch) {
+    if (!DBUF && c + 1 < c1) {
       __syncthreads();  // W2 is free once every wave is past phase 2
       copy_to_lds<NT>(w2p + (size_t)(c + 1) * L::W2CH, w2buf, L::W2CH, wave, lane);
     }
@@ -274,6 +278,34 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
   constexpr int CPR = D / 8;
   constexpr int ROUNDS = BM * CPR / NT;
   static_assert(BM * CPR % NT == 0 && NT % CPR == 0, "epilogue rounds");
+  if (p.part) {
+    // One part of a split: the FP32 product U W2 over this part's chunks, rows staged through LDS
+    // and written as 32-byte runs to part [split][M][D] (no bias, no residual: the reduction
+    // kernel adds the parts in order, then b2, then h).
+#pragma unroll
+    for (int a = 0; a < FM2; ++a)
+#pragma unroll
+      for (int b = 0; b < FN2; ++b) {
+        const int col = 32 * (wn2 * FN2 + b) + i;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 32 * (wm2 * FM2 + a) + 8 * (r >> 2) + 4 * h + (r & 3);
+          *(float*)(smem + row * L::SRS + col * 4) = acc[a][b][r];
+        }
+      }
+    __syncthreads();
+    float* part = p.part + (int64_t)blockIdx.y * p.M * D;
+#pragma unroll
+    for (int q = 0; q < ROUNDS; ++q) {
+      const int t = tid + q * NT, row = t / CPR, col = (t % CPR) * 8;
+      if (m0 + row < M) {
+        float* dst = part + (int64_t)(m0 + row) * D + col;
+        *(f32x4*)dst = *(const f32x4*)(smem + row * L::SRS + col * 4);
+        *(f32x4*)(dst + 4) = *(const f32x4*)(smem + row * L::SRS + col * 4 + 16);
+      }
+    }
+    return;
+  }
   // Every round of this thread covers the same 8 columns: their LN gamma and beta load once.
   f32x4 lng[2], lnb[2];
   if (p.y_next) {
@@ -327,6 +359,60 @@ __global__ __launch_bounds__(NW * 64) void ffn_fused_kernel(const FfnArgs p) {
       const u32x4 yn = ln_row_chunk8<CPR>(x, lng[0], lng[1], lnb[0], lnb[1], p.ln_eps);
       if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)(m0 + row) * D + col) = yn;
     }
+  }
+}
+
+// Reduction of a split FFN: h = bf16(h + ((part_0 + part_1 + ...) + b2)) per row, parts added in
+// order in FP32, and the next block's LN1 of the new h when y_next is set (the LayerNorm kernel's
+// reduction tree, as in the fused epilogue). CPR = D / 8 consecutive threads own one row, 8 values
+// each; all of a thread's loads are issued before the sums.
+template <int D, int S>
+__global__ __launch_bounds__(256) void ffn_reduce_kernel(const FfnArgs p) {
+  constexpr int CPR = D / 8;
+  int M = p.M;
+  if (p.m_dev) M = min(M, max(*p.m_dev, 0));
+  const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  const int row = t / CPR, col = (t % CPR) * 8;
+  if ((row - row % (256 / CPR)) >= M) return;  // uniform over the workgroup's rows
+  const bool live = row < M;
+  float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  u32x4 o = u32x4{0, 0, 0, 0};
+  if (live) {
+    o = *(const u32x4*)((const __bf16*)p.h + (int64_t)row * D + col);
+    f32x4 pa[S], pb[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float* src = p.part + ((int64_t)s * p.M + row) * D + col;
+      pa[s] = *(const f32x4*)src;
+      pb[s] = *(const f32x4*)(src + 4);
+    }
+    const f32x4 b0 = *(const f32x4*)(p.b2 + col), b1 = *(const f32x4*)(p.b2 + col + 4);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[e] += pa[s][e];
+        v[4 + e] += pb[s][e];
+      }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] += b0[e];
+      v[4 + e] += b1[e];
+    }
+  }
+  const u32x2 lo = pack_bf16x4(v[0] + __uint_as_float(o[0] << 16), v[1] + __uint_as_float(o[0] & 0xffff0000u),
+                               v[2] + __uint_as_float(o[1] << 16), v[3] + __uint_as_float(o[1] & 0xffff0000u));
+  const u32x2 hi = pack_bf16x4(v[4] + __uint_as_float(o[2] << 16), v[5] + __uint_as_float(o[2] & 0xffff0000u),
+                               v[6] + __uint_as_float(o[3] << 16), v[7] + __uint_as_float(o[3] & 0xffff0000u));
+  const u32x4 hn = u32x4{lo[0], lo[1], hi[0], hi[1]};
+  if (live) *(u32x4*)((__bf16*)p.h + (int64_t)row * D + col) = hn;
+  if (p.y_next) {
+    float x[8];
+    unpack_bf16x8(hn, x);
+    const f32x4 g0 = *(const f32x4*)(p.ln_g + col), g1 = *(const f32x4*)(p.ln_g + col + 4);
+    const f32x4 e0 = *(const f32x4*)(p.ln_b + col), e1 = *(const f32x4*)(p.ln_b + col + 4);
+    const u32x4 yn = ln_row_chunk8<CPR>(x, g0, g1, e0, e1, p.ln_eps);
+    if (live) *(u32x4*)((__bf16*)p.y_next + (int64_t)row * D + col) = yn;
   }
 }
 
@@ -830,10 +916,31 @@ hipError_t launch_v(const FfnArgs& p, hipStream_t s) {
   const int64_t grid = ((int64_t)p.M + BM - 1) / BM;
   if (grid == 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  const int nch = p.d_ff / kFfnHC;
+  if (p.split < 1 || nch % p.split != 0 || (p.split > 1) != (p.part != nullptr)) return hipErrorInvalidValue;
+  const dim3 g((unsigned)grid, (unsigned)p.split);
   switch (p.d_model) {
-    case 64: hipLaunchKernelGGL((ffn_fused_kernel<64, BM, NW, DBUF, RELU>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
-    case 128: hipLaunchKernelGGL((ffn_fused_kernel<128, BM, NW, DBUF, RELU>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
-    default: hipLaunchKernelGGL((ffn_fused_kernel<256, BM, NW, DBUF, RELU>), dim3((unsigned)grid), dim3(NW * 64), 0, s, p); break;
+    case 64: hipLaunchKernelGGL((ffn_fused_kernel<64, BM, NW, DBUF, RELU>), g, dim3(NW * 64), 0, s, p); break;
+    case 128: hipLaunchKernelGGL((ffn_fused_kernel<128, BM, NW, DBUF, RELU>), g, dim3(NW * 64), 0, s, p); break;
+    default: hipLaunchKernelGGL((ffn_fused_kernel<256, BM, NW, DBUF, RELU>), g, dim3(NW * 64), 0, s, p); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.split == 1) return e;
+  const int64_t rgrid = ((int64_t)p.M * (p.d_model / 8) + 255) / 256;
+  auto reduce = [&](auto d_tag) {
+    constexpr int DM = decltype(d_tag)::value;
+    switch (p.split) {
+      case 2: hipLaunchKernelGGL((ffn_reduce_kernel<DM, 2>), dim3((unsigned)rgrid), dim3(256), 0, s, p); break;
+      case 4: hipLaunchKernelGGL((ffn_reduce_kernel<DM, 4>), dim3((unsigned)rgrid), dim3(256), 0, s, p); break;
+      case 8: hipLaunchKernelGGL((ffn_reduce_kernel<DM, 8>), dim3((unsigned)rgrid), dim3(256), 0, s, p); break;
+      default: hipLaunchKernelGGL((ffn_reduce_kernel<DM, 16>), dim3((unsigned)rgrid), dim3(256), 0, s, p); break;
+    }
+  };
+  if (p.split != 2 && p.split != 4 && p.split != 8 && p.split != 16) return hipErrorInvalidValue;
+  switch (p.d_model) {
+    case 64: reduce(std::integral_constant<int, 64>{}); break;
+    case 128: reduce(std::integral_constant<int, 128>{}); break;
+    default: reduce(std::integral_constant<int, 256>{}); break;
   }
   return hipGetLastError();
 }
@@ -865,12 +972,14 @@ void ffn_pack(const uint16_t* w1t, const uint16_t* w2t, int d_model, int d_ff, u
 }
 
 // Variants 1 and 2 as declared; 3 = variant 1 as a persistent kernel (ffn_persistent_kernel);
-// 4 = the software-pipelined persistent kernel (even chunk counts).
+// 4 = the software-pipelined persistent kernel (even chunk counts); 5 and 6 = variants 2 and 1
+// over p.split parts of the hidden units (p.part set) plus the reduction kernel.
 namespace {
 template <bool RELU>
 hipError_t launch_variant(const FfnArgs& p, int variant, hipStream_t s) {
-  if (variant == 1) return launch_v<128, 8, true, RELU>(p, s);
-  if (variant == 2) return launch_v<64, 4, false, RELU>(p, s);
+  if (variant != 5 && variant != 6 && (p.split != 1 || p.part)) return hipErrorInvalidValue;
+  if (variant == 1 || variant == 6) return launch_v<128, 8, true, RELU>(p, s);
+  if (variant == 2 || variant == 5) return launch_v<64, 4, false, RELU>(p, s);
   if (variant == 3) {
     switch (p.d_model) {
       case 64: return launch_persistent<64, RELU>(p, s);

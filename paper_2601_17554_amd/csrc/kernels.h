@@ -94,6 +94,11 @@ struct FfnArgs {
   const float* ln_g = nullptr;
   const float* ln_b = nullptr;
   float ln_eps = 1e-5f;
+  // Variant 5: the hidden units in `split` equal parts (a divisor of d_ff / 64), one workgroup per
+  // (row tile, part) writing its FP32 partial product to part [split][M][d_model]; a reduction
+  // kernel then updates h (and writes y_next).
+  int split = 1;
+  float* part = nullptr;
 };
 int ffn_fused_supported(int d_model, int d_ff);
 // Bytes of the packed W1 (which = 1) or W2 (which = 2) image.

@@ -20,6 +20,8 @@ def test_graph_replay_matches_eager(prec):
     # between the graph (its capacity) and the eager reference (the batch): pinned here (BF16: 4
     # key splits, so the captured combine step is replayed too).
     m.tune_set("attn_split", 2)
+    if prec == "bf16":
+        m.tune_set("ffn", 7)  # likewise the FFN's split into 8 parts of the hidden units
     batches = [synth.pack([synth.make_event(50 + i, n) for i, n in enumerate(sizes)])
                for sizes in ([700, 31, 1200], [5], [64, 900, 2, 300, 1000, 77])]
     e_cap = 8

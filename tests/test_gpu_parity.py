@@ -326,6 +326,7 @@ def test_fused_ffn_bitwise(B, cfg):
     w, m = _model(B, cfg, 15, "bf16", sharpen=2.0)
     evs = [synth.make_event(5000 + i, n) for i, n in enumerate([300, 1, 129, 64, 1000])]
     pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=9)
+    m.tune_set("ffn", 1)
     fused = run_gpu(m, pk)
     for variant in (2, 3, 4):
         if variant == 4 and (cfg.d_ff // 64) % 2:
@@ -347,6 +348,38 @@ def test_fused_ffn_bitwise(B, cfg):
                 np.testing.assert_array_equal(fused[k][r], two[k][r], err_msg=f"tile {tile} {k}")
     with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
         B.Model(cfg, w, "fp32").tune_set("ffn", 1)
+
+
+@pytest.mark.parametrize("wset", WEIGHT_SETS)
+@pytest.mark.parametrize("cfg", [synth.FULL, synth.SMALL,
+                                 synth.Config(d_model=128, n_heads=4, d_ff=192, n_layers=2)],
+                         ids=["d256", "d64", "d128"])
+def test_split_ffn(B, cfg, wset):
+    """The FFN with its hidden units split into 2 to 16 parts (partial products reduced by a
+    second kernel, for launches too small to fill the chip; 64- and 128-row shapes) against the
+    oracle on ragged events
+    with garbage padding, and within rounding of the fused FFN; the rule's choice too. A part
+    count that does not divide d_ff / 64 is refused."""
+    w, m = _model(B, cfg, 15, "bf16", sharpen=2.0, wset=wset)
+    evs = [synth.make_event(5000 + i, n) for i, n in enumerate([300, 1, 129, 64, 1000])]
+    pk = synth.pack(evs, pad_to=64, pad_fill=1e4, seed=9)
+    m.tune_set("ffn", 1)
+    fused = run_gpu(m, pk)
+    nch = cfg.d_ff // 64
+    for tile in (-1, 5, 6, 7, 8, 9, 10, 11, 12):
+        parts = B.Model.tune_shape("ffn", tile)["fused"] if tile >= 5 else None
+        if parts and nch % parts:
+            with pytest.raises(B.MlpfError, match="UNSUPPORTED"):
+                m.tune_set("ffn", tile)
+            continue
+        m.tune_set("ffn", tile)
+        got = run_gpu(m, pk)
+        _check_all(got, pk, w, cfg, TOL["bf16"], f"split FFN tile {tile} {wset}", wset=wset)
+        for e in range(pk.n_events):
+            r = pk.event_rows(e)
+            for k in ("logits", "reg"):
+                d = np.abs(got[k][r] - fused[k][r]).max() / max(np.abs(fused[k][r]).max(), 1e-6)
+                assert d <= 2e-2, f"tile {tile} event {e} {k}: {d:.3e} from the fused FFN"
 
 
 def test_persistent_ffn_many_tiles(B):
@@ -391,13 +424,15 @@ def test_relu_activation(B, prec, cfg):
     got = run_gpu(m, pk)
     _check_all(got, pk, w, cfg, TOL[prec], f"relu {prec}", wset="wide")
     if prec == "bf16":
-        for variant in (0, 1, 2, 3, 4):
+        m.tune_set("ffn", 0)
+        two = run_gpu(m, pk)
+        for variant in (1, 2, 3, 4):
             m.tune_set("ffn", variant)
             other = run_gpu(m, pk)
             for e in range(pk.n_events):
                 r = pk.event_rows(e)
                 for k in ("logits", "reg", "cls"):
-                    np.testing.assert_array_equal(got[k][r], other[k][r], err_msg=f"ffn {variant} {k}")
+                    np.testing.assert_array_equal(two[k][r], other[k][r], err_msg=f"ffn {variant} {k}")
 
 
 @pytest.mark.parametrize("prec,cfg", [("fp32", synth.SMALL), ("bf16", synth.FULL), ("bf16", synth.PAPER)],
