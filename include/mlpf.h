@@ -294,16 +294,16 @@ typedef enum {
    * is not a multiple of 128; 4: as 3, software-pipelined: the GELU of one 64-unit chunk runs
    * beside the first product of the next, d_ff a multiple of 128 only, the default there), for
    * MLPF_BF16 models with d_model 64, 128 or 256, bitwise equal
-   * to tile 0 with any GEMM tiles; tiles 5 to 8 = the shape of 2 with the hidden units split into
-   * 2, 4, 8 or 16 equal parts (a divisor of d_ff / 64, else MLPF_ERR_UNSUPPORTED), one workgroup
-   * per (64-row tile, part) writing its FP32 partial product to the workspace, then a kernel that
-   * adds the parts in order, the bias and the residual (and the next block's LN1): for launches
-   * too small to fill the chip; results differ from tile 0 by the rounding of the partial sums.
-   * The part count is capped like the attention's key splits (8, 4 or 2 for up to 4096, 8192 or
-   * 16384 rows; beyond, tiles 5 to 8 run as tile 2). The rule (-1) splits when the rows fit under
-   * that cap, into the fewest parts that give two workgroups per CU, else runs tile 4 (or 3).
-   * Setting 1 to 8 on another model returns MLPF_ERR_UNSUPPORTED. FP8 calibration always runs
-   * the two products. */
+   * to tile 0 with any GEMM tiles; tiles 5 to 8 (9 to 12) = the shape of 2 (of 1) with the hidden
+   * units split into 2, 4, 8 or 16 equal parts (a divisor of d_ff / 64, else
+   * MLPF_ERR_UNSUPPORTED), one workgroup per (row tile, part) writing its FP32 partial product to
+   * the workspace, then a kernel that adds the parts in order, the bias and the residual (and the
+   * next block's LN1): for launches too small to fill the chip; results differ from tile 0 by the
+   * rounding of the partial sums. The part count is capped like the attention's key splits (8, 4
+   * or 2 for up to 4096, 8192 or 16384 rows; beyond, tiles 5 to 12 run unsplit in their shape).
+   * The rule (-1) splits when the rows fit under that cap, into the fewest parts that give two
+   * 64-row workgroups per CU, else runs tile 4 (or 3). Setting 1 to 12 on another model returns
+   * MLPF_ERR_UNSUPPORTED. FP8 calibration always runs the two products. */
   MLPF_OP_FFN = 8,
   /* How the output heads run: tile 0 = the first-layer product (tiles of MLPF_OP_HEADS1 apply)
    * writing the five GELU hidden layers, then a kernel for the second layer, argmax and decode;
