@@ -85,39 +85,54 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   float raf[A_FROM_F32 ? A_PT * E : 1];
   u32x4 rb[B_PT];
 
+  // Plain A and W^T are read with bounded buffer loads whose descriptors cover the tile's own rows
+  // (columns of W): rows at or past M (columns past N) read as zeros without a compare per chunk,
+  // and the byte offsets stay within the tile.
   auto load = [&](int m0, int n0, int k0) {
+    if constexpr (ALD == A_PLAIN) {
+      const int rows = max(0, min(BM, M - m0));
+      const __amdgpu_buffer_rsrc_t ars = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)((const S*)p.a + (int64_t)m0 * p.lda), (short)0, rows * p.lda * (int)sizeof(S), kBufferWord3);
 #pragma unroll
-    for (int t = 0; t < A_PT; ++t) {
-      const int c = t * NT + tid;
-      const int row = c / C, ch = c % C;
-      const int grow = m0 + row, kb = k0 + ch * E;
-      const bool ok = (A_CH % NT == 0 || c < A_CH) && grow < M;
-      if constexpr (ALD == A_PLAIN) {
-        ra[t] = ok ? *(const u32x4*)((const S*)p.a + (int64_t)grow * p.lda + kb) : u32x4{0, 0, 0, 0};
-      } else if constexpr (ALD == A_SCALAR) {
-        const float* ar = (const float*)p.a + (int64_t)(ok ? grow : 0) * p.lda;
+      for (int t = 0; t < A_PT; ++t) {
+        const int c = t * NT + tid;
+        if (A_CH % NT == 0 || c < A_CH)
+          ra[t] = __builtin_amdgcn_raw_buffer_load_b128(
+              ars, ((c / C) * p.lda + k0 + (c % C) * E) * (int)sizeof(S), 0, 0);
+      }
+    } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e) raf[t * E + e] = (ok && kb + e < p.K) ? ar[kb + e] : 0.f;
-      } else {
-        const f32x4* ar = (const f32x4*)((const float*)p.a + (int64_t)(ok ? grow : 0) * p.lda + kb);
+      for (int t = 0; t < A_PT; ++t) {
+        const int c = t * NT + tid;
+        const int row = c / C, ch = c % C;
+        const int grow = m0 + row, kb = k0 + ch * E;
+        const bool ok = (A_CH % NT == 0 || c < A_CH) && grow < M;
+        if constexpr (ALD == A_SCALAR) {
+          const float* ar = (const float*)p.a + (int64_t)(ok ? grow : 0) * p.lda;
 #pragma unroll
-        for (int e = 0; e < E / 4; ++e) {
-          const f32x4 v = ok ? ar[e] : f32x4{0.f, 0.f, 0.f, 0.f};
-          raf[t * E + 4 * e + 0] = v[0];
-          raf[t * E + 4 * e + 1] = v[1];
-          raf[t * E + 4 * e + 2] = v[2];
-          raf[t * E + 4 * e + 3] = v[3];
+          for (int e = 0; e < E; ++e) raf[t * E + e] = (ok && kb + e < p.K) ? ar[kb + e] : 0.f;
+        } else {
+          const f32x4* ar = (const f32x4*)((const float*)p.a + (int64_t)(ok ? grow : 0) * p.lda + kb);
+#pragma unroll
+          for (int e = 0; e < E / 4; ++e) {
+            const f32x4 v = ok ? ar[e] : f32x4{0.f, 0.f, 0.f, 0.f};
+            raf[t * E + 4 * e + 0] = v[0];
+            raf[t * E + 4 * e + 1] = v[1];
+            raf[t * E + 4 * e + 2] = v[2];
+            raf[t * E + 4 * e + 3] = v[3];
+          }
         }
       }
     }
+    const int cols = max(0, min(BN, p.N - n0));
+    const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const S*)p.wt + (int64_t)n0 * p.Kp), (short)0, cols * p.Kp * (int)sizeof(S), kBufferWord3);
 #pragma unroll
     for (int t = 0; t < B_PT; ++t) {
       const int c = t * NT + tid;
-      const int n = c / C, ch = c % C;
-      const int col = n0 + n;
-      const bool ok = (B_CH % NT == 0 || c < B_CH) && col < p.N;
-      rb[t] = ok ? *(const u32x4*)((const S*)p.wt + (int64_t)col * p.Kp + k0 + ch * E)
-                 : u32x4{0, 0, 0, 0};
+      if (B_CH % NT == 0 || c < B_CH)
+        rb[t] = __builtin_amdgcn_raw_buffer_load_b128(
+            brs, ((c / C) * p.Kp + k0 + (c % C) * E) * (int)sizeof(S), 0, 0);
     }
   };
 
@@ -382,12 +397,21 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
         } else {
           dst = (S*)p.out + (int64_t)row * p.ldo + col;
         }
+        // Q, K and V are written with non-temporal stores: they are read back by the next kernel
+        // from memory, and streaming them through L2 would evict the tiles of W every workgroup
+        // re-reads.
         if constexpr (sizeof(S) == 4) {
           const f32x4 v = *(const f32x4*)src;
-          *(f32x4*)dst = v * qs;
+          if constexpr (EPI == E_QKV)
+            __builtin_nontemporal_store(v * qs, (f32x4*)dst);
+          else
+            *(f32x4*)dst = v * qs;
         } else if constexpr (sizeof(S) == 2) {  // staged as bf16 (Q already scaled)
           const u32x4 w = *(const u32x4*)src;
-          *(u32x4*)dst = w;
+          if constexpr (EPI == E_QKV)
+            __builtin_nontemporal_store(w, (u32x4*)dst);
+          else
+            *(u32x4*)dst = w;
           if constexpr (EPI == E_QKV) {
             if (p.knorm && col >= p.d && col < 2 * p.d) {
 #pragma unroll
