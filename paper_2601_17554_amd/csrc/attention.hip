@@ -445,8 +445,27 @@ void attn_bf16_kernel(const AttnArgs p) {
     }
   };
 
-  float l_run[QB], m_ex[QB];
+  float m_ex[QB];
   f32x16 oacc[QB];
+  // Row sums of the packed P, of exactly the bf16 values the PV product uses. d_head 32: per lane
+  // with v_dot2 (the two lane halves added at the end). d_head 16: V^T rows 16-31 are idle, and
+  // row 16 holds ones, so the PV MFMA itself produces the row sum as O^T row 16 (register 8 of the
+  // lanes of half 0, zero in half 1) at no VALU cost.
+  [[maybe_unused]] float l_run[QB];
+  auto reset_sums = [&]() {
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      oacc[j] = f32x16{};
+      if constexpr (DH == 32) l_run[j] = 0.f;
+    }
+  };
+  // The full row sum of this lane's query (block j); every lane must call it (lane exchange).
+  auto row_sum = [&](int j) {
+    if constexpr (DH == 32)
+      return l_run[j] + other_half(l_run[j]);
+    else
+      return oacc[j][8] + other_half(oacc[j][8]);
+  };
 
   // K fragments of key block b (its stage b / G sits in LDS slot (b / G) % 3).
   auto kread = [&](int b, u32x4 (&ka)[QKG]) {
@@ -489,7 +508,8 @@ void attn_bf16_kernel(const AttnArgs p) {
       const tr4 v1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_tr4*)(vp + 8 * VRS));
       const u32x2 w0 = __builtin_bit_cast(u32x2, v0), w1 = __builtin_bit_cast(u32x2, v1);
       u32x4 va = u32x4{w0[0], w0[1], w1[0], w1[1]};
-      if (DH < 32 && i >= DH) va = u32x4{0, 0, 0, 0};
+      if (DH < 32 && i >= DH)
+        va = i == DH ? u32x4{0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u} : u32x4{0, 0, 0, 0};
 #pragma unroll
       for (int j = 0; j < QB; ++j) {
         u32x4 pb;
@@ -500,7 +520,7 @@ void attn_bf16_kernel(const AttnArgs p) {
           const float e2 = __builtin_amdgcn_exp2f(SHIFT ? s[j][8 * c + 4 * q + 2] - msh[j] : s[j][8 * c + 4 * q + 2]);
           const float e3 = __builtin_amdgcn_exp2f(SHIFT ? s[j][8 * c + 4 * q + 3] - msh[j] : s[j][8 * c + 4 * q + 3]);
           const u32x2 pk = pack_bf16x4(e0, e1, e2, e3);
-          l_run[j] = add_bf16x4(e0, e1, e2, e3, l_run[j]);
+          if constexpr (DH == 32) l_run[j] = add_bf16x4(e0, e1, e2, e3, l_run[j]);
           pb[2 * q] = pk[0];
           pb[2 * q + 1] = pk[1];
         }
@@ -598,11 +618,7 @@ void attn_bf16_kernel(const AttnArgs p) {
     }
   };
 
-#pragma unroll
-  for (int j = 0; j < QB; ++j) {
-    l_run[j] = 0.f;
-    oacc[j] = f32x16{};
-  }
+  reset_sums();
   // The exponent offset of each query's P: -cneg (PIPE), else msh once shifted, 0 before.
   bool shifted = false;
   f32x16 zero[QB];
@@ -628,7 +644,7 @@ void attn_bf16_kernel(const AttnArgs p) {
   bool loose = false;
 #pragma unroll
   for (int j = 0; j < QB; ++j) {
-    const float l_tot = l_run[j] + other_half(l_run[j]);
+    const float l_tot = row_sum(j);
     loose = loose || (qi[j] < n && nk > 0 && !(l_tot >= 0x1p-96f) && l_tot == l_tot);
   }
   if (__syncthreads_or(loose)) {
@@ -644,9 +660,8 @@ void attn_bf16_kernel(const AttnArgs p) {
       } else {
         msh[j] = mx;
       }
-      l_run[j] = 0.f;
-      oacc[j] = f32x16{};
     }
+    reset_sums();
     shifted = true;
     if constexpr (PIPE)
       sweep(std::false_type{}, cneg, std::false_type{});
@@ -659,7 +674,7 @@ void attn_bf16_kernel(const AttnArgs p) {
     const int nh = p.d / DH;
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
-      const float l_tot = l_run[j] + other_half(l_run[j]);
+      const float l_tot = row_sum(j);
       if (qi[j] < n) {
         const int64_t prow = (int64_t)split * p.rows + start + qi[j];
         float* po = p.part_o + prow * p.d + head * DH + 4 * h;
@@ -677,7 +692,7 @@ void attn_bf16_kernel(const AttnArgs p) {
   // O = O^T / l. Lane l holds dh = 8c + 4*(l/32) + (0..3) of query l%32 in registers 4c..4c+3.
 #pragma unroll
   for (int j = 0; j < QB; ++j) {
-    const float l_tot = l_run[j] + other_half(l_run[j]);
+    const float l_tot = row_sum(j);
     if (qi[j] < n) {
       const float inv = 1.0f / l_tot;
       __bf16* orow = (__bf16*)p.o + (int64_t)(start + qi[j]) * p.d + head * DH;
