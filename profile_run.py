@@ -5,6 +5,9 @@ known size whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters.
 
     python profile_run.py [--precision bf16] [--batches 4] [--copy-mib 256]
         [--tiles '{"attention": 7, ...}']
+
+With --one-event it instead runs the one-event-per-launch workload of bench.py's plain legs: the
+event of median element count among its 40 events, tiles autotuned for it, 20 graph replays.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ def main() -> None:
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--batches", type=int, default=4)
     ap.add_argument("--tiles", default="", help="JSON {op: tile} to pin (default: autotune)")
+    ap.add_argument("--one-event", action="store_true", help="one median full-size event per launch")
     args = ap.parse_args()
     root = os.path.dirname(os.path.abspath(__file__))
     sys.path.insert(0, root)
@@ -32,6 +36,9 @@ def main() -> None:
 
     cfg = synth.FULL
     model = B.Model(cfg, synth.make_weights(cfg, 1), args.precision)
+    if args.one_event:
+        one_event(model, args, B, autotune, synth, torch)
+        return
     batches = bench.make_batches(args.batches)
     dev = []
     for pk in batches:
@@ -62,6 +69,38 @@ def main() -> None:
         n2 = float((pk.n_valid.astype("float64") ** 2).sum())
         print(f"profile_run: batch {i} rows {pk.total_rows} sum n^2 {n2:.6e}", flush=True)
     print(f"profile_run: copy {args.copy_mib} MiB", flush=True)
+
+
+def one_event(model, args, B, autotune, synth, torch) -> None:
+    """The median event of bench.py's one-event legs (40 events, seed 200, at least 500 elements),
+    padded to a multiple of 64, graph-replayed 20 times after the autotuner's choice."""
+    import numpy as np
+    evs = synth.event_set(200, 40, lo=500)
+    ev = evs[int(np.argsort([e.n for e in evs])[len(evs) // 2])]
+    pk = synth.pack([ev], pad_to=64)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        x = torch.from_numpy(pk.x).cuda()
+        batch = B.Batch.from_host(pk.row_start, pk.n_valid)
+        ws = model.workspace(pk.total_rows, 1)
+        out = model.outputs(pk.total_rows)
+        stream.synchronize()
+        if args.tiles:
+            for op, t in json.loads(args.tiles).items():
+                model.tune_set(op, int(t))
+            tiles = json.loads(args.tiles)
+        else:
+            tiles = autotune.tune(model, x, batch, ws=ws, use_cache=False)
+        print(f"profile_run: one event of {ev.n} elements, tiles " + json.dumps(tiles), flush=True)
+        graph = B.Graph(model, x, batch, out, ws, stream)
+        for _ in range(5):
+            graph.launch()
+        stream.synchronize()
+        print("profile_run: measured replays begin", flush=True)
+        for _ in range(20):
+            graph.launch()
+        stream.synchronize()
+    print("profile_run: done", flush=True)
 
 
 if __name__ == "__main__":
