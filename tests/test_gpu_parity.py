@@ -143,6 +143,28 @@ def test_max_seqlen_8192(B, prec):
                 scale=output_scale([ref, ref1]))
 
 
+@pytest.mark.parametrize("n", [4096, 4097, 8192])
+def test_split_caps(B, n):
+    """Single events at the workspace caps of the key split and the split FFN (at most 8 parts
+    up to 4096 rows, 4 up to 8192): the rule's splits and the unsplit kernels (key split pinned to
+    one, the pipelined FFN) each against the oracle, and within BF16 rounding of each other."""
+    cfg = synth.Config(d_model=256, n_heads=8, d_ff=1024, n_layers=1)
+    w, m = _model(B, cfg, 5, "bf16", sharpen=4.0, wset="wide")
+    ev = synth.make_event(90 + n, n)
+    pk = synth.pack([ev])
+    ref = oracle(ev.x, w, cfg, ("caps", n))
+    split = run_gpu(m, pk)
+    m.tune_set("attn_split", 0)
+    m.tune_set("ffn", 4)
+    whole = run_gpu(m, pk)
+    for got, tag in ((split, "split"), (whole, "unsplit")):
+        check_event(got, ref, pk.event_rows(0), TOL["bf16"], f"{tag} n={n}",
+                    columns=strict_columns(TOL["bf16"], "wide"))
+    for k in ("logits", "reg"):
+        d = np.abs(split[k] - whole[k]).max() / max(np.abs(whole[k]).max(), 1e-6)
+        assert d <= TOL["bf16"], f"n={n} {k}: split vs unsplit {d:.3e}"
+
+
 @pytest.mark.parametrize("cfg", [
     synth.Config(d_model=64, n_heads=4, d_ff=256, n_layers=2, topology="parallel2"),
     synth.Config(d_model=128, n_heads=8, d_ff=256, n_layers=2, topology="parallel2"),
