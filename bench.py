@@ -291,8 +291,10 @@ def bench_serving(args, cfg, w):
 
     model = B.Model(cfg, w, args.precision)
     budget = 64 << 30
+    # Row-capacity buckets 262144 / 2^k down to 4096: a lone event replays a graph captured for
+    # at most 4096 rows, where the key split and the split FFN apply.
     ex = serve.GpuExecutor(model, max_rows=262144, max_events=EVENTS_PER_BATCH, slots=3,
-                           hbm_budget=budget, buckets=4, decode=True)
+                           hbm_budget=budget, buckets=7, decode=True)
 
     def pct(a, q):
         return round(float(np.percentile(a, q)), 3) if len(a) else None
