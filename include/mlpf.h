@@ -13,8 +13,11 @@
  *   class   = from the six classification outputs by the config's decision rule (mlpf_decision_t)
  *   decode  : pT = pT_prim exp(pT'), E = E_prim exp(E') (inverse of Eq. 2), phi = atan2(sin, cos)
  * act is GELU (default) or ReLU (the paper's network) after every hidden linear layer, none after
- * output layers. GELU(z) = z (1 + erf(z / sqrt 2)) / 2 with erf evaluated by the Abramowitz-Stegun
- * rational approximation 7.1.26 (absolute error of erf at most 1.5e-7) in FP32.
+ * output layers. GELU(z) = z (1 + erf(z / sqrt 2)) / 2: in MLPF_FP32 with erf evaluated by the
+ * Abramowitz-Stegun rational approximation 7.1.26 (absolute error of erf at most 1.5e-7); in the
+ * BF16 and FP8 modes, whose hidden activations are rounded to bf16 or E4M3, as z sigma(g(z)) with
+ * g an odd quintic fitted to the normal CDF (absolute error of the CDF at most 1.9e-5, of GELU
+ * 5.5e-5).
  * Readings where the paper is silent: LayerNorm eps from the config, biased variance; no final
  * LayerNorm; Q/K/V/O biases; contiguous head split.
  *
@@ -73,7 +76,8 @@ typedef enum {
                              regression heads */
 } mlpf_topology_t;
 
-/* The hidden-layer activation: the exact (erf) GELU, or ReLU as in the paper's network (Sec. 5.3). */
+/* The hidden-layer activation: the erf GELU (evaluated as stated above), or ReLU as in the paper's
+ * network (Sec. 5.3). */
 typedef enum { MLPF_ACT_GELU = 0, MLPF_ACT_RELU = 1 } mlpf_activation_t;
 /* The class rule (Sec. 5.3). ARGMAX: cls = argmax of the six logits, class 0 = no particle.
  * BINARY: output 0 is a binary "is a particle" logit and outputs 1..5 the particle-type logits;

@@ -26,11 +26,12 @@ namespace {
 
 constexpr int kFfnHC = 64;  // hidden units per chunk
 
-// The hidden activation: exact (erf) GELU, or ReLU (the paper's network).
+// The hidden activation: GELU (the logistic form of the bf16 paths, gelu_fast), or ReLU (the
+// paper's network).
 template <bool RELU>
 __device__ __forceinline__ float hidden_act(float z) {
   if constexpr (RELU) return fmaxf(z, 0.f);
-  else return gelu_erf(z);
+  else return gelu_fast(z);
 }
 
 // LDS image of one workgroup: W1 and W2^T chunk buffers (two of each when double buffered), the U

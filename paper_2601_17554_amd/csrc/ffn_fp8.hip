@@ -27,7 +27,7 @@ constexpr int kHC = 64;  // hidden units per chunk (one 64-value k-group of the 
 template <bool RELU>
 __device__ __forceinline__ float act8(float z) {
   if constexpr (RELU) return fmaxf(z, 0.f);
-  else return gelu_erf(z);
+  else return gelu_fast(z);
 }
 
 typedef __attribute__((address_space(3))) void lds_void8;

@@ -282,11 +282,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
             const int lrow = (PASSES == 1 ? wm * WTM : 0) + a * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
             float v = (T::kBytes == 1 ? acc[a][b][r] * p.acc_scale : acc[a][b][r]) + bias;
             if constexpr (EPI == E_GELU) {
-              v = p.relu ? fmaxf(v, 0.f) : gelu_erf(v);
+              // (FP32: the erf form; bf16 and FP8 outputs: the logistic form, see gelu_fast)
+              v = p.relu ? fmaxf(v, 0.f) : T::kBytes == 4 ? gelu_erf(v) : gelu_fast(v);
               if (m0 + pass * PROWS + lrow < M && col < p.N) amax = fmaxf(amax, fabsf(v));
             }
             if constexpr (EPI == E_HEADS) {  // the hidden layer, bf16 rows of kHeadsRS bytes
-              *(__bf16*)(smem + lrow * kHeadsRS + lcol * 2) = (__bf16)(p.relu ? fmaxf(v, 0.f) : gelu_erf(v));
+              *(__bf16*)(smem + lrow * kHeadsRS + lcol * 2) = (__bf16)(p.relu ? fmaxf(v, 0.f) : gelu_fast(v));
             } else if constexpr (kStageB16) {
               if constexpr (EPI == E_QKV) v *= col < p.d ? p.q_scale : 1.f;  // Q pre-scaled
               *(__bf16*)(smem + lrow * SRS + lcol * 2) = (__bf16)v;
