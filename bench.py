@@ -37,8 +37,8 @@ EVENTS_PER_BATCH = 64
 # (profiles/attention_bf16_varlen64_hbm_traffic.md). Valid only for the kernel source it was
 # measured on: reported as null once that source changes (attention.hip, common.h, and the
 # attention declarations of kernels.h: AttnArgs, AttnTile and the launchers).
-ATTN_TRAFFIC = {"sha256": "b85c8da4f2626a6ea0fe68c5c8f8addd2cc4f37f8f6bd74c74bb3c6b8cc1d348",
-                "bytes_per_launch": 458221656.1}
+ATTN_TRAFFIC = {"sha256": "ce919856719c313bf501cd4171f28d8612aa806aaa38196baea70f32ce0549c5",
+                "bytes_per_launch": 458213662.2}
 
 
 def attention_source_hash() -> str:
