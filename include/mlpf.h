@@ -332,7 +332,9 @@ int32_t mlpf_tune_count(int32_t op);
 mlpf_status_t mlpf_tune_set(mlpf_model_t model, int32_t op, int32_t tile);
 int32_t mlpf_tune_get(mlpf_model_t model, int32_t op); /* -1 = size-based rule */
 /* Shape of tile `tile` of op, written to shape[6]: GEMM ops {rows, columns, wave rows, wave
- * columns, bytes per operand row and k-tile, persistent (1) or one workgroup per tile (0)};
+ * columns, bytes per operand row and k-tile, schedule: one workgroup per tile (0), persistent (1), or
+ * one workgroup per tile whose k-tiles travel by direct-to-LDS loads through three LDS stages (2;
+ * products with an FP32 A operand that the kernel converts run such tiles' shape as 0)};
  * MLPF_OP_ATTENTION {waves per workgroup, keys per LDS stage, 32-query blocks per wave, kernel
  * kind (0: online softmax with running maxima, 1: BF16 score-bound offset, 2: the same without the
  * look-ahead QK^T product; FP32 runs kind 0),

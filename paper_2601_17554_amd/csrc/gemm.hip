@@ -23,7 +23,10 @@ namespace mlpf {
 constexpr int kHeadsRS = 528;
 constexpr int kHeadsHid = 64 * kHeadsRS;
 
-template <class T, int ALD, int EPI, int BM, int BN, int BK, int WM, int WN, bool PERSIST>
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void gbl_cvoid;
+
+template <class T, int ALD, int EPI, int BM, int BN, int BK, int WM, int WN, bool PERSIST, bool DMA>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   using S = typename T::storage;
   constexpr int NT = 64 * WM * WN;
@@ -38,6 +41,14 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   constexpr int A_BYTES = BM * RS, B_BYTES = BN * RS;
   constexpr bool kSplit = (T::kBytes == 4);
   static_assert(C % (T::kBytes == 1 ? 4 : 2) == 0 && FM >= 1 && FN >= 1, "bad tile");
+  // DMA (plain A only): k-tiles of A and W^T travel by direct-to-LDS loads through kStages LDS
+  // stages, unpadded rows with the 16-byte chunks of row r permuted by an XOR with swz(r) (the 8
+  // rows one ds_read_b128 phase serves then hit distinct banks); the loads of k-tile kt + 2 are in
+  // flight while k-tile kt is multiplied, with no registers holding them.
+  constexpr bool kDma = DMA && ALD == A_PLAIN;
+  constexpr int kStages = 3;
+  static_assert(!(kDma && PERSIST), "DMA tiles are not persistent");
+  static_assert(!kDma || ((BM * C) % NT == 0 && (BN * C) % NT == 0), "DMA tile: whole loads per wave");
 
   // Epilogue staging: rows of the tile, FP32, or bf16 where the output is exactly the bf16 rounding
   // of the staged value (so the rounding happens once, on the way into LDS); one pass, or one pass
@@ -45,7 +56,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   // the head's slice of W2 instead.
   constexpr bool kStageB16 = (EPI == E_QKV || EPI == E_GELU) ? sizeof(S) == 2 : EPI == E_BIAS_B;
   constexpr int SRS = BN * (kStageB16 ? 2 : 4) + 16;    // staging row stride (bytes)
-  constexpr int MAIN = 2 * (A_BYTES + B_BYTES);
+  constexpr int MAIN = kDma ? kStages * (BM + BN) * C * 16 : 2 * (A_BYTES + B_BYTES);
   constexpr int PASSES = (BM * SRS <= MAIN || WM == 1) ? 1 : WM;
   constexpr int PROWS = BM / PASSES;                     // rows staged per pass
   constexpr int STAGE = EPI == E_HEADS ? kHeadsHid + 32 * kHeadsRS : PROWS * SRS;
@@ -164,7 +175,38 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
   const int nk = p.Kp / BK;
   const int i = lane & 31, h = lane >> 5;
   [[maybe_unused]] float amax = 0.f;  // E_GELU: largest |output| of this workgroup's tiles
-  load(m0, n0, 0);
+  if constexpr (!kDma) load(m0, n0, 0);
+  // The 16-byte chunk ch of LDS operand row r (DMA stages: permuted, unpadded rows).
+  auto swz = [](int r) { return C == 4 ? (r >> 1) & 3 : (r & 7) & (C - 1); };
+  auto frag = [&](const char* base, int r, int ch) -> u32x4 {
+    if constexpr (kDma)
+      return *(const u32x4*)(base + (r * C + (ch ^ swz(r))) * 16);
+    else
+      return *(const u32x4*)(base + r * RS + ch * 16);
+  };
+  // Direct-to-LDS loads of k-tile k0 into DMA stage st: load t of a thread fills slot t NT + tid
+  // (row slot / C, position slot % C) with the chunk (position XOR swz(row)) of that row; rows past
+  // M (columns past N) read the last valid one, whose products only reach discarded outputs.
+  [[maybe_unused]] auto dma = [&](int st, int k0) {
+    char* As = smem + st * (BM + BN) * C * 16;
+    char* Bs = As + BM * C * 16;
+    const S* a = (const S*)p.a;
+    const S* w = (const S*)p.wt;
+#pragma unroll
+    for (int t = 0; t < BM * C / NT; ++t) {
+      const int slot = t * NT + tid, r = slot / C, q = slot % C;
+      const int row = min(m0 + r, M - 1);
+      __builtin_amdgcn_global_load_lds((gbl_cvoid*)(a + (int64_t)row * p.lda + k0 + (q ^ swz(r)) * E),
+                                       (lds_void*)(As + (t * NT + wave * 64) * 16), 16, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < BN * C / NT; ++t) {
+      const int slot = t * NT + tid, r = slot / C, q = slot % C;
+      const int col = min(n0 + r, p.N - 1);
+      __builtin_amdgcn_global_load_lds((gbl_cvoid*)(w + (int64_t)col * p.Kp + k0 + (q ^ swz(r)) * E),
+                                       (lds_void*)(Bs + (t * NT + wave * 64) * 16), 16, 0, 0);
+    }
+  };
   while (true) {
   f32x16 acc[FM][FN];
 #pragma unroll
@@ -172,13 +214,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = f32x16{};
 
-  store(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load(m0, n0, (kt + 1) * BK);
-    const char* As = smem + buf * (A_BYTES + B_BYTES);
-    const char* Bs = As + A_BYTES;
+  // One k-tile's products from the operand images at As and Bs.
+  auto ktile = [&](const char* As, const char* Bs) {
     // FP32 operands: each k-tile sums into a fresh partial that is then added to the total, so
     // the longest chain of sequential FP32 additions is BK/2 + K/BK instead of K/2.
     f32x16 part[kSplit ? FM : 1][kSplit ? FN : 1];
@@ -197,12 +234,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
         for (int a = 0; a < FM; ++a)
 #pragma unroll
           for (int e = 0; e < 2; ++e)
-            af[a][e] = *(const u32x4*)(As + (wm * WTM + a * 32 + i) * RS + (4 * g + 2 * h + e) * 16);
+            af[a][e] = frag(As, wm * WTM + a * 32 + i, 4 * g + 2 * h + e);
 #pragma unroll
         for (int b = 0; b < FN; ++b)
 #pragma unroll
           for (int e = 0; e < 2; ++e)
-            bf[b][e] = *(const u32x4*)(Bs + (wn * WTN + b * 32 + i) * RS + (4 * g + 2 * h + e) * 16);
+            bf[b][e] = frag(Bs, wn * WTN + b * 32 + i, 4 * g + 2 * h + e);
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -214,10 +251,10 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
       u32x4 af[FM], bf[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a)
-        af[a] = *(const u32x4*)(As + (wm * WTM + a * 32 + i) * RS + (2 * g + h) * 16);
+        af[a] = frag(As, wm * WTM + a * 32 + i, 2 * g + h);
 #pragma unroll
       for (int b = 0; b < FN; ++b)
-        bf[b] = *(const u32x4*)(Bs + (wn * WTN + b * 32 + i) * RS + (2 * g + h) * 16);
+        bf[b] = frag(Bs, wn * WTN + b * 32 + i, 2 * g + h);
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -235,11 +272,47 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] += part[a][b];
     }
-    if (kt + 1 < nk) store(buf ^ 1);
+  };
+
+  if constexpr (kDma) {
+    // Stage kt % 3 holds k-tile kt. Each step waits for its own loads of k-tile kt (those of kt + 1
+    // may stay in flight: the wave's vector-memory counter counts only these loads here), meets
+    // the other waves at a barrier (after which every wave has loaded k-tile kt and finished
+    // reading stage (kt + 2) % 3 = (kt - 1) % 3), starts k-tile kt + 2 into that stage, and
+    // multiplies k-tile kt. No fence: the barrier alone orders the stages.
+    constexpr int DPS = (BM + BN) * C / NT;  // direct-to-LDS loads per thread and k-tile
+    constexpr int kWaitOne = (DPS & 15) | ((DPS >> 4) << 14) | (7 << 4) | (15 << 8);  // vmcnt(DPS)
+    constexpr int kWaitAll = (7 << 4) | (15 << 8);                                    // vmcnt(0)
+    static_assert(DPS <= 63, "vmcnt range");
+    dma(0, 0);
+    if (nk > 1) dma(1, BK);
+    for (int kt = 0; kt < nk; ++kt) {
+      if (kt + 1 < nk)
+        __builtin_amdgcn_s_waitcnt(kWaitOne);
+      else
+        __builtin_amdgcn_s_waitcnt(kWaitAll);
+      __builtin_amdgcn_s_barrier();
+      if (kt + 2 < nk) dma((kt + 2) % kStages, (kt + 2) * BK);
+      const char* As = smem + (kt % kStages) * (BM + BN) * C * 16;
+      ktile(As, As + BM * C * 16);
+    }
+    __syncthreads();  // every wave is done with the stages before the epilogue reuses the LDS
+  } else {
+    store(0);
     __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load(m0, n0, (kt + 1) * BK);
+      const char* As = smem + buf * (A_BYTES + B_BYTES);
+      ktile(As, As + A_BYTES);
+      if (kt + 1 < nk) store(buf ^ 1);
+      __syncthreads();
+    }
   }
   const int next = tile + tile_step;
-  if (PERSIST && next < tile_end) load((next / ntn) * BM, (next % ntn) * BN, 0);
+  if constexpr (PERSIST) {
+    if (next < tile_end) load((next / ntn) * BM, (next % ntn) * BN, 0);
+  }
 
   // Epilogue, staged through LDS so that global memory sees whole 16-byte row chunks: the waves
   // write bias + activation (FP32) into an LDS tile, then every thread moves 16-byte chunks of
@@ -482,6 +555,12 @@ constexpr GemmTile kTiles[] = {
     {128, 128, 2, 2, 128, 1},
     // 64 rows x 256 columns, 1 x 4 waves: whole 256-wide rows per workgroup (fused output heads)
     {64, 256, 1, 4, 64, 0},
+    // 8 waves with 64 x 64 wave tiles, k-tiles by direct-to-LDS loads through three LDS stages
+    // (plain A operands; a converted FP32 A runs the shape double buffered through registers): the
+    // larger tiles cut the L2 reads of A and W^T (each row of one is read once per tile of the
+    // other), and the loads need no staging registers
+    {128, 256, 2, 4, 64, 2},
+    {256, 128, 4, 2, 64, 2},
 };
 
 // Workgroups of one kernel that fit on the device at once (the grid of a persistent launch). The
@@ -500,7 +579,8 @@ int resident_workgroups(K kernel, int threads) {
   return cached;
 }
 
-template <class T, int ALD, int EPI, int BM, int BN, int WM, int WN, int BKB = 128, bool PERSIST = false>
+template <class T, int ALD, int EPI, int BM, int BN, int WM, int WN, int BKB = 128, bool PERSIST = false,
+          bool DMA = false>
 hipError_t launch_t(const GemmArgs& p, hipStream_t s) {
   constexpr int BK = BKB / T::kBytes;  // BKB bytes of each row per k-tile
   if (p.Kp % BK != 0 || p.N % 16 != 0) return hipErrorInvalidValue;
@@ -508,7 +588,7 @@ hipError_t launch_t(const GemmArgs& p, hipStream_t s) {
   int64_t grid = (int64_t)gm * gn;
   if (grid == 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  auto kernel = gemm_kernel<T, ALD, EPI, BM, BN, BK, WM, WN, PERSIST>;
+  auto kernel = gemm_kernel<T, ALD, EPI, BM, BN, BK, WM, WN, PERSIST, DMA>;
   if constexpr (PERSIST) {
     const int res = std::max(8, resident_workgroups(kernel, 64 * WM * WN));
     grid = std::min<int64_t>((grid + 7) / 8 * 8, res / 8 * 8);
@@ -534,6 +614,8 @@ hipError_t launch_tile(int tile, const GemmArgs& p, hipStream_t s) {
     case 11: return launch_t<T, ALD, EPI, 64, 128, 2, 2, 64, true>(p, s);
     case 12: return launch_t<T, ALD, EPI, 128, 128, 2, 2, 128, true>(p, s);
     case 13: return launch_t<T, ALD, EPI, 64, 256, 1, 4, 64>(p, s);
+    case 14: return launch_t<T, ALD, EPI, 128, 256, 2, 4, 64, false, true>(p, s);
+    case 15: return launch_t<T, ALD, EPI, 256, 128, 4, 2, 64, false, true>(p, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -61,7 +61,8 @@ struct GemmArgs {
 struct GemmTile {
   int bm, bn, wm, wn;
   int bkb;      // bytes of each operand row per k-tile
-  int persist;  // 1: persistent workgroups looping over tiles
+  int persist;  // 1: persistent workgroups looping over tiles; 2: k-tiles by direct-to-LDS loads
+                // through three LDS stages (plain A operands)
 };
 int gemm_num_tiles();
 GemmTile gemm_tile(int id);
