@@ -287,11 +287,14 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(const GemmArgs p) {
     dma(0, 0);
     if (nk > 1) dma(1, BK);
     for (int kt = 0; kt < nk; ++kt) {
+      // (the signal fences keep the compiler from moving LDS reads or copies across the barrier)
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (kt + 1 < nk)
         __builtin_amdgcn_s_waitcnt(kWaitOne);
       else
         __builtin_amdgcn_s_waitcnt(kWaitAll);
       __builtin_amdgcn_s_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (kt + 2 < nk) dma((kt + 2) % kStages, (kt + 2) * BK);
       const char* As = smem + (kt % kStages) * (BM + BN) * C * 16;
       ktile(As, As + BM * C * 16);
