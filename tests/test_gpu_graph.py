@@ -9,8 +9,9 @@ import synth
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("gemm", ["rule", "direct_lds"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_graph_replay_matches_eager(prec):
+def test_graph_replay_matches_eager(prec, gemm):
     import torch
     from paper_2601_17554_amd import binding as B
 
@@ -22,6 +23,12 @@ def test_graph_replay_matches_eager(prec):
     m.tune_set("attn_split", 2)
     if prec == "bf16":
         m.tune_set("ffn", 7)  # likewise the FFN's split into 8 parts of the hidden units
+    if gemm == "direct_lds":  # every product on the 128 x 256 tile with direct-to-LDS k-tiles
+        assert B.Model.tune_shape("qkv", 14)["persist"] == 2
+        for op in ("embed1", "embed2", "qkv", "outproj", "ffn1", "ffn2", "heads1"):
+            m.tune_set(op, 14)
+        m.tune_set("heads", 0)
+        m.tune_set("ffn", 0)
     batches = [synth.pack([synth.make_event(50 + i, n) for i, n in enumerate(sizes)])
                for sizes in ([700, 31, 1200], [5], [64, 900, 2, 300, 1000, 77])]
     e_cap = 8
